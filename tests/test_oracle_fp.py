@@ -1,0 +1,275 @@
+"""Pins for the floating-point oracle: rounding semantics, exact special
+cases, library cross-checks and the paper's printed error magnitudes."""
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from conftest import GOLDEN, read_table
+from oracle import fp
+from oracle import toomcook as tc
+
+# Point sets whose normalisers N_i are all powers of two, so that every entry
+# of A^T, G and B^T is a short dyadic rational (exact in float32).
+DYADIC_SETS = [[Fr(0), Fr(1), Fr(-1)], [Fr(0), Fr(2), Fr(-2)], [Fr(-1, 2), Fr(0), Fr(1, 2)]]
+
+
+# ----------------------------------------------------------------------------
+# Rounding semantics
+# ----------------------------------------------------------------------------
+def test_matrices_are_rounded_exact_values():
+    pts = [Fr(-1, 3), Fr(-3), Fr(0), Fr(3), Fr(1, 3)]
+    ATx, Gx, BTx = tc.transforms(pts, 4, 3)
+    AT, G, BT = fp.mats_f32(pts, 4, 3)
+    for ex, f in ((ATx, AT), (Gx, G), (BTx, BT)):
+        for i, row in enumerate(ex):
+            for j, v in enumerate(row):
+                # the nearest float32 of the nearest float64 of the exact value
+                assert f[i, j] == np.float32(float(v))
+                # and within half an ulp (plus the double rounding) of it
+                assert abs(Fr(float(f[i, j])) - v) <= abs(v) * Fr(1, 2 ** 23)
+
+
+def test_ascending_order_and_no_fma():
+    """apply_left sums in ascending index order with every operation rounded."""
+    X = np.array([[1e8], [1.0], [-1e8]], dtype=np.float32)
+    ones = np.ones((1, 3), dtype=np.float32)
+    # (1e8 + 1) rounds to 1e8 in float32, so the ascending sum is exactly 0
+    assert fp.apply_left(ones, X, 0)[0, 0] == 0.0
+    assert fp.apply_left(ones[:, ::-1].copy(), X[::-1].copy(), 0)[0, 0] == 0.0
+    # product rounded before the add: a*b + c with a*b inexact in float32
+    a, b, c = np.float32(1 + 2 ** -12), np.float32(1 + 2 ** -12), np.float32(-1.0)
+    got = fp.apply_left(np.array([[a, 1]], dtype=np.float32), np.array([[b], [c]], dtype=np.float32), 0)[0, 0]
+    assert got == np.float32(np.float32(a * b) + c)
+    assert got != np.float32(float(a) * float(b) + float(c))       # what a fused multiply-add gives
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000).astype(np.float32) * 10.0 ** rng.integers(-30, 30, 10000),
+                        np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 3.3895314e38, -0.0, np.inf, -np.inf], dtype=np.float32)])
+    x = x.astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    got = fp.round_bf16(x)
+    assert np.array_equal(got, ref)
+    assert np.isnan(fp.round_bf16(np.array([np.nan], dtype=np.float32))[0])
+
+
+def test_f16_rounding_ties_to_even():
+    x = np.array([1 + 2 ** -11, 1 + 3 * 2 ** -11, 65504.0, 65520.0, 2 ** -25], dtype=np.float32)
+    got = fp.round_f16(x)
+    assert got[0] == 1.0 and got[1] == np.float32(1 + 2 ** -9)
+    assert got[2] == 65504.0 and np.isinf(got[3]) and got[4] == 0.0
+
+
+# ----------------------------------------------------------------------------
+# Exact special cases of the float path
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("pts", DYADIC_SETS)
+def test_float_tiles_exact_on_dyadic_points(dims, pts):
+    """With dyadic transforms and small integer data every intermediate value is
+    representable, so the float32 tile must equal the exact correlation."""
+    mats = fp.mats_f32(pts, 2, 3)
+    shape_d = (300, 4) if dims == 1 else (300, 4, 4)
+    shape_g = (300, 3) if dims == 1 else (300, 3, 3)
+    d = synth.exact_small_ints(shape_d, 1)
+    g = synth.exact_small_ints(shape_g, 2)
+    f = fp.tile_1d_f32 if dims == 1 else fp.tile_2d_f32
+    assert np.array_equal(f(mats, d, g).astype(np.float64), fp.direct_tile_f64(d, g))
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("alpha,c", [(6, 1.622), (8, 2.0), (10, 1.3)])
+def test_float_tiles_within_forward_error_bound(dims, alpha, c):
+    """Larger tiles: |y32 - y| <= 4 alpha u (|A^T| (|G||g| (.) |B^T||d|)), the
+    absolute-value propagation of rounding through the nested products
+    (u = 2^-24); a wrong index or operand gives errors of order |y|."""
+    m = alpha - 2
+    pts = tc.family_points(alpha, c, 2.7)
+    mats = fp.mats_f32(pts, m, 3)
+    AT, G, BT = (np.abs(M.astype(np.float64)) for M in mats)
+    d, g = synth.tile_pool(300, alpha, 3, dims, seed=4)
+    ad, ag = np.abs(d.astype(np.float64)), np.abs(g.astype(np.float64))
+    if dims == 1:
+        y = fp.tile_1d_f32(mats, d, g)
+        bound = np.einsum("ji,ni->nj", AT, np.einsum("ik,nk->ni", G, ag) * np.einsum("il,nl->ni", BT, ad))
+    else:
+        y = fp.tile_2d_f32(mats, d, g)
+        Ub = np.einsum("ik,nkl,jl->nij", G, ag, G)
+        Vb = np.einsum("ik,nkl,jl->nij", BT, ad, BT)
+        bound = np.einsum("ik,nkl,jl->nij", AT, Ub * Vb, AT)
+    err = np.abs(y.astype(np.float64) - fp.direct_tile_f64(d, g))
+    assert np.all(err <= 4 * alpha * 2.0 ** -24 * bound)
+    assert err.max() > 0                                    # the test is not vacuous
+
+
+@pytest.mark.parametrize("padding,H,W", [("same", 11, 9), ("valid", 10, 13), ("same", 7, 7), ("valid", 5, 4)])
+def test_float_layer_exact_on_dyadic_points(padding, H, W):
+    """The float32 layer (tiling, padding, ragged edge, channel sum) equals the
+    float64 direct layer exactly when all values are representable."""
+    mats = fp.mats_f32(DYADIC_SETS[0], 2, 3)
+    x = synth.exact_small_ints((2, 3, H, W), 3, -2, 2)
+    w = synth.exact_small_ints((4, 3, 3, 3), 4, -2, 2)
+    y = fp.winograd_layer(x, w, mats, 2, padding)
+    assert np.array_equal(y.astype(np.float64), fp.direct_layer_f64(x, w, padding))
+
+
+@pytest.mark.parametrize("m,padding,H,W", [(4, "same", 11, 9), (6, "valid", 13, 10), (6, "same", 28, 28)])
+def test_float_layer_close_to_direct(m, padding, H, W):
+    """Larger tiles: relative L1 error of the float32 layer against the float64
+    direct layer is small (well below 1e-5 for these well-conditioned points)."""
+    pts = tc.family_points(m + 2, 2.0, 1.0)
+    mats = fp.mats_f32(pts, m, 3)
+    x, w = synth.layer_inputs(2, 8, 4, H, W, 3, "normal")
+    e = fp.l1_errors(fp.winograd_layer(x, w, mats, m, padding), fp.direct_layer_f64(x, w, padding))
+    assert 0 < e["rel_l1"] < 1e-5
+
+
+def test_layer_tiles_subset_matches_full_layer():
+    x, w = synth.layer_inputs(2, 5, 3, 13, 10, 3, "normal")
+    mats = fp.mats_f32(tc.family_points(6, 1.7), 4, 3)
+    full = fp.winograd_layer_tiles(x, w, mats, 4, "same")
+    sel = np.array([0, 5, 11, 17])
+    assert np.array_equal(fp.winograd_layer_tiles(x, w, mats, 4, "same", tiles=sel), full[:, sel])
+
+
+# ----------------------------------------------------------------------------
+# Library cross-checks
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("padding", ["same", "valid"])
+def test_direct_f64_matches_torch_conv2d(padding):
+    x, w = synth.layer_inputs(2, 4, 5, 9, 7, 3, "normal")
+    ref = torch.nn.functional.conv2d(torch.from_numpy(x).double(), torch.from_numpy(w).double(),
+                                     padding=1 if padding == "same" else 0).numpy()
+    got = fp.direct_layer_f64(x, w, padding)
+    assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+    coords = [(0, 0, 0, 0), (1, 4, 8, 6), (1, 2, 3, 0), (0, 3, 5, 6)]
+    coords = [c for c in coords if c[2] < got.shape[2] and c[3] < got.shape[3]]
+    pts = fp.direct_points_f64(x, w, padding, coords)
+    assert np.allclose(pts, [got[c] for c in coords], rtol=1e-13, atol=1e-13)
+
+
+def test_direct_f64_matches_exact_on_rationals():
+    rng = np.random.default_rng(9)
+    x = rng.integers(-5, 6, size=(1, 2, 5, 4)).astype(np.float32) / 4
+    w = rng.integers(-5, 6, size=(2, 2, 3, 3)).astype(np.float32) / 8
+    xe = [[[[Fr(float(v)) for v in row] for row in ch] for ch in im] for im in x]
+    we = [[[[Fr(float(v)) for v in row] for row in ch] for ch in k] for k in w]
+    ex = tc.direct_layer(xe, we, "same")
+    got = fp.direct_layer_f64(x, w, "same")
+    assert np.array_equal(got, np.array(ex, dtype=np.float64))
+
+
+def test_hadamard_channel_sum_within_higham_bound():
+    """M = sum_c U V in float32 (ascending c) is within gamma_C |U||V| of the
+    float64 product (Higham, Accuracy and Stability, eq. 3.5)."""
+    rng = np.random.default_rng(3)
+    C = 256
+    U = rng.standard_normal((8, C, 4, 4)).astype(np.float32)
+    V = rng.standard_normal((16, C, 4, 4)).astype(np.float32)
+    M = fp.hadamard_channel_sum(U, V).astype(np.float64)
+    U64, V64 = U.astype(np.float64), V.astype(np.float64)
+    exact = np.einsum("kce,pce->kpe", U64.reshape(8, C, 16), V64.reshape(16, C, 16)).reshape(M.shape)
+    absprod = np.einsum("kce,pce->kpe", np.abs(U64).reshape(8, C, 16), np.abs(V64).reshape(16, C, 16)).reshape(M.shape)
+    u = 2.0 ** -24
+    gamma = C * u / (1 - C * u)
+    assert np.all(np.abs(M - exact) <= gamma * absprod)
+
+
+# ----------------------------------------------------------------------------
+# Reduced precision Hadamard stage
+# ----------------------------------------------------------------------------
+def test_power_of_two_scaling_is_exact():
+    """Scaling V by 2^-s and U by 2^+s leaves every float32 product and hence the
+    float32 layer bit-identical (no rounding to 16 bits here)."""
+    x, w = synth.layer_inputs(1, 6, 4, 12, 12, 3, "normal")
+    mats = fp.mats_f32(tc.family_points(8, 2.0, 1.0), 6, 3)
+    U, V = fp.transformed_operands(x, w, mats, 6, "same")
+    s = np.moveaxis(fp.scale_exponents(mats, w), 2, 0)
+    assert s.min() != 0 or s.max() != 0                           # scaling is not trivial here
+    Us, Vs = np.ldexp(U, s[None]).astype(np.float32), np.ldexp(V, -s[None]).astype(np.float32)
+    assert np.array_equal(fp.hadamard_channel_sum(Us, Vs), fp.hadamard_channel_sum(U, V))
+
+
+@pytest.mark.parametrize("c", [0.05, 0.3, 2.0, 7.0, 20.0])
+def test_f16_operands_do_not_overflow(c):
+    """For the F(6x6,3x3) family {0, inf, +-1, +-c, +-1/c} over c in [0.05, 20]
+    with N(0,1) data the scaled float16 operands stay finite."""
+    x, w = synth.layer_inputs(1, 8, 4, 28, 28, 3, "normal")
+    mats = fp.mats_f32(tc.family_points(8, c, 1.0), 6, 3)
+    ax = np.abs(x).max(axis=(0, 2, 3))
+    U, V = fp.transformed_operands(x, w, mats, 6, "same", "f16", x_absmax=ax)
+    assert np.isfinite(U).all() and np.isfinite(V).all()
+
+
+def test_scale_exponents_closed_form():
+    """Row-norm exponents for points {0, 1, -1}: |B^T rows|_1 = 2, 2, 2, 2 and
+    |G rows|_1 = 1, 3/2, 3/2, 1; weights of max 1 and unit inputs give
+    s = floor((2+2+1 - (E_G1+E_G2+1)) / 2)."""
+    mats = fp.mats_f32([Fr(0), Fr(1), Fr(-1)], 2, 3)
+    w = np.zeros((1, 1, 3, 3), dtype=np.float32)
+    w[0, 0, 0, 0] = 1.0
+    s = fp.scale_exponents(mats, w)[:, :, 0]
+    eg = [1, 1, 1, 1]                           # frexp exponents of 1, 1.5, 1.5, 1
+    eb = [2, 2, 2, 2]                           # frexp exponent of 2
+    for e1 in range(4):
+        for e2 in range(4):
+            assert s[e1, e2] == ((eb[e1] + eb[e2] + 1) - (eg[e1] + eg[e2] + 1)) // 2
+
+
+# ----------------------------------------------------------------------------
+# The paper's printed error magnitudes (Tables tab:sota_1d and tab:sota_2d)
+# ----------------------------------------------------------------------------
+def _rows():
+    return read_table(f"{GOLDEN}/sota_tables.txt")
+
+
+def _err(dims, pts, n_total, nsamp=5000):
+    m = n_total - 2
+    d, g = synth.tile_pool(nsamp, n_total, 3, dims, seed=2)
+    mats = fp.mats_f32(pts, m, 3)
+    f = fp.tile_1d_f32 if dims == 1 else fp.tile_2d_f32
+    return fp.l1_errors(f(mats, d, g), fp.direct_tile_f64(d, g))["mean_abs"]
+
+
+def test_direct_rows_pin_the_error_metric():
+    """Mean absolute error per output with uniform[-1,1] data reproduces the
+    float32 direct-convolution rows (n = 0) within 4%."""
+    for row in _rows():
+        if row[2] != "direct":
+            continue
+        dims, printed = int(row[0]), float(row[6])
+        d, g = synth.tile_pool(40000, 3, 3, dims, seed=3)
+        got = fp.l1_errors(fp.direct_tile_f32(d, g), fp.direct_tile_f64(d, g))["mean_abs"]
+        assert abs(got / printed - 1) < 0.04, (dims, got, printed)
+
+
+def test_winograd_rows_magnitude():
+    """Winograd errors agree with the printed values within a factor 1.5 (the
+    paper used an undefined summation order; this oracle sums ascending)."""
+    for row in _rows():
+        if row[2] in ("direct", "improvement%"):
+            continue
+        dims, n = int(row[0]), int(row[1])
+        syms = {"c": Fr(row[4]) if row[4] != "-" else None}
+        pts = [eval(p, {"Fr": Fr}, {"c": syms["c"]}) if "c" in p else Fr(p.strip())
+               for p in row[3].split(",")]
+        pts = [p if isinstance(p, Fr) else Fr(p) for p in pts]
+        got = _err(dims, pts, n)
+        printed = float(row[6])
+        assert 1 / 1.5 < got / printed < 1.5, (row, got)
+
+
+def test_f43_improvement_over_barabasz_points():
+    """F(4,3): the proposed c reduces the error by roughly the printed percentage
+    (18.35% in 1D at c=1.829, 27.96% in 2D at c=1.622), within 5 points."""
+    printed = {int(r[0]): float(r[6]) for r in _rows() if r[2] == "improvement%"}
+    for dims, base, c in ((1, [0, -1, 1, Fr(1, 2), -3], 1.829), (2, [0, -1, 1, Fr(1, 2), -2], 1.622)):
+        e_base = _err(dims, [Fr(b) for b in base], 6)
+        e_prop = _err(dims, tc.family_points(6, Fr(str(c))), 6)
+        imp = 100 * (e_base - e_prop) / e_base
+        assert abs(imp - printed[dims]) < 5.0, (dims, imp)
