@@ -1,0 +1,228 @@
+/*
+ * wg.h - C ABI of the MI355X (gfx950) Winograd / Toom-Cook convolution
+ * library with arbitrary interpolation points.
+ *
+ * Method: Alam, Anderson, Barabasz, Gregg, "Winograd Convolution for Deep
+ * Neural Networks: Efficient Point Selection" (arXiv:2201.10369).
+ *   - 1D algorithm Y = A^T[(G g) (.) (B^T d)]              (Section 4, eq. conv_1d)
+ *   - 2D algorithm Y = A^T[(G g G^T) (.) (B^T d B)] A      (Section 4, eq. conv_2d)
+ *   - matrices from points: A^T Vandermonde, G Vandermonde with the Lagrange
+ *     normalisation N_i folded in, B^T Lagrange numerators (Section 4.1),
+ *     modified with the point at infinity appended last (Section 4.2)
+ *   - point families {0, inf, +-c, +-1/c, +-d, +-1/d} and subsets (Section 5)
+ *   - float32 error against a float64 direct convolution, L1 norm (Section 6)
+ *
+ * Conventions for every entry point
+ *   - Return value: WG_OK (0) or a negative wg_status.  Nothing throws across
+ *     the ABI and nothing aborts.  wg_last_error() describes the last failure
+ *     of the calling thread.
+ *   - All arguments are validated on the host before anything is launched; a
+ *     failed validation launches nothing and writes nothing.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.  The library
+ *     keeps no pointer after a call returns (plans keep only their own small
+ *     host-side tables).
+ *   - Device work is enqueued asynchronously on `stream` (a hipStream_t; NULL
+ *     means the default stream); the call returns once it is enqueued.  HIP
+ *     launch failures return WG_EHIP with the HIP error string.
+ *   - Layouts: x is N x C x H x W, w is K x C x r x r, y is N x K x Hout x Wout,
+ *     all float32, dense, row-major (NCHW / KCRS / NKHW).  Stride 1, no bias,
+ *     no dilation, no groups.  padding WG_SAME needs odd r (pad (r-1)/2);
+ *     WG_VALID pads nothing.
+ *   - NaN and Inf in the data propagate unchecked.
+ */
+#ifndef WG_H
+#define WG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t, declared opaquely so this header needs no HIP headers. */
+typedef struct ihipStream_t* wg_stream_t;
+
+typedef enum {
+    WG_OK = 0,
+    WG_EINVAL = -1,        /* bad argument: null pointer, bad size, bad enum */
+    WG_ESINGULAR = -2,     /* two points coincide: some N_i = 0 (Section 4.1) */
+    WG_EUNSUPPORTED = -3,  /* valid request outside what this build implements */
+    WG_EWORKSPACE = -4,    /* caller workspace smaller than required */
+    WG_ENOMEM = -5,        /* host or device allocation failed */
+    WG_EHIP = -6           /* a HIP runtime call failed */
+} wg_status;
+
+/* construction flags */
+enum { WG_MODIFIED = 0,    /* alpha-1 finite points + infinity (Section 4.2) */
+       WG_UNMODIFIED = 1 };/* alpha finite points (plain Toom-Cook, Section 4.1) */
+/* padding */
+enum { WG_SAME = 0, WG_VALID = 1 };
+/* element type of the Hadamard (channel-sum) stage */
+enum { WG_F32 = 0, WG_F16 = 1, WG_BF16 = 2 };
+
+/* Description of the last error on the calling thread; valid until the next
+ * call on that thread.  Never NULL. */
+const char* wg_last_error(void);
+
+/* ABI version (major*10000 + minor*100 + patch). */
+int wg_version(void);
+
+/* Limits of this build: 1 <= m <= 8, r in {3, 5}, alpha = m + r - 1 <= 12. */
+int wg_supported(int m, int r);   /* 1 if (m, r) is implemented, else 0 */
+
+/* ------------------------------------------------------------------------
+ * Points -> transforms (host, synchronous).  Section 4.1 and 4.2.
+ *
+ * pts: host, the ordered finite points (n_pts of them).  With
+ *   flags = WG_MODIFIED, n_pts must be alpha-1 = m+r-2 and the point at
+ *   infinity is appended as the last point; with WG_UNMODIFIED, n_pts must be
+ *   alpha.  The order of the points is kept (it permutes rows/columns).
+ * Outputs (host, caller allocated, row-major):
+ *   AT: m x alpha, G: alpha x r, BT: alpha x alpha.
+ *   A^T[j][i] = a_i^j;  G[i][k] = a_i^k / N_i;  B^T[i][l] = coefficient of x^l
+ *   in prod_{j != i}(x - a_j), with N_i = prod_{j != i}(a_i - a_j); for the
+ *   infinity point A^T gets column e_{m-1}, G row e_{r-1} and B^T the row of
+ *   coefficients of prod_j (x - a_j).
+ * Computed exactly (every float64 point is a dyadic rational; the entries are
+ * evaluated in integer arithmetic) and each entry rounded once to the nearest
+ * float64, ties to even, so cancellations give exact zeros.
+ * Errors: WG_EINVAL (null pointer, m < 1, r < 2,
+ * alpha > 16, wrong n_pts, non-finite point), WG_ESINGULAR (two points equal,
+ * or some |N_i| < 1e-300).  Nothing is written on error.
+ * ---------------------------------------------------------------------- */
+int wg_transforms(int m, int r, const double* pts, int n_pts, int flags,
+                  double* AT, double* G, double* BT);
+
+/* Same, rounded on to the nearest float32 (ties to even): the matrices the
+ * layer kernels use. */
+int wg_transforms_f32(int m, int r, const double* pts, int n_pts, int flags,
+                      float* AT, float* G, float* BT);
+
+/* Point families of Section 5 (eqs. ps0, ps1, ps2 and the subsets of
+ * eq. ps3), one canonical subset per size, c2 playing the role of d:
+ *   alpha 4: -c, 0, c          5: 0, -c, c, 1/c       6: -1/c, -c, 0, c, 1/c
+ *   alpha 7: (6), d            8: (6), -d, d          9: (6), -1/d, -d, d
+ *   alpha 10: (6), -1/d, -d, d, 1/d
+ * pts_out (host) receives alpha-1 finite points (infinity is implicit).
+ * c2 is ignored for alpha <= 6.  Returns alpha-1, or WG_EINVAL (alpha outside
+ * 4..10, c1 or c2 not finite and nonzero where used). */
+int wg_family_points(int alpha, double c1, double c2, double* pts_out);
+
+/* ------------------------------------------------------------------------
+ * Convolution layer plans (host).
+ * A plan fixes the point set, tile size F(m x m, r x r), layer shape, padding
+ * and the element type of the Hadamard stage.  It owns only host-side tables
+ * (the float32 matrices and their row-norm exponents), is immutable after
+ * creation and may be used concurrently from several streams.
+ * ---------------------------------------------------------------------- */
+typedef struct wg_plan wg_plan;
+
+/* Creates a plan.  Errors: WG_EINVAL (null out/pts, non-positive sizes,
+ * padding or dtype out of range, output smaller than 1x1), WG_EUNSUPPORTED
+ * ((m, r) not implemented; WG_SAME with even r; WG_UNMODIFIED), WG_ESINGULAR,
+ * WG_ENOMEM.  *out is set only on success. */
+int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, int flags,
+                   int N, int C, int K, int H, int W, int padding, int dtype);
+int wg_plan_destroy(wg_plan* plan);      /* NULL is accepted */
+
+/* Sizes in bytes of the transformed-filter buffer U and of the forward
+ * workspace, and the output size.  Any output pointer may be NULL. */
+int wg_plan_sizes(const wg_plan* plan, size_t* filter_bytes, size_t* workspace_bytes,
+                  int* Hout, int* Wout);
+
+/* Buffer layout (all offsets in bytes from the start of the buffer named).
+ *   U buffer:  U'[e][k][c], e < alpha^2, k < K_pad, c < C_pad, elem_bytes each;
+ *              then (WG_F16 / WG_BF16 only) at scale_offset the int32 exponents
+ *              s[e][c], c < C_pad.
+ *   workspace: V'[e][p][c] at v_offset (e < alpha^2, p < P_pad, c < C_pad,
+ *              elem_bytes each) and M[e][k][p] float32 at m_offset
+ *              (k < K_pad, p < P_pad).
+ * Tile index p = (n*Th + th)*Tw + tw; tile (th, tw) covers outputs
+ * [th*m, th*m+m) x [tw*m, tw*m+m) and reads the input window whose top-left
+ * corner is (th*m - pad, tw*m - pad). */
+typedef struct {
+    int alpha, m, r, pad;
+    int N, C, K, H, W, Hout, Wout, Th, Tw;
+    int P, P_pad, K_pad, C_pad;
+    int dtype, elem_bytes;
+    size_t scale_offset, filter_bytes;
+    size_t v_offset, m_offset, workspace_bytes;
+} wg_layout;
+int wg_plan_layout(const wg_plan* plan, wg_layout* out);
+
+/* The float32 matrices of the plan (host outputs, sizes as wg_transforms). */
+int wg_plan_matrices(const wg_plan* plan, float* AT, float* G, float* BT);
+
+/* ------------------------------------------------------------------------
+ * Layer (device, asynchronous).  Section 4 eq. conv_2d applied tile by tile
+ * to the layer of eq. conv; Section 4.1 notes that the filter and input
+ * transforms are amortised and that the channel sum of the Hadamard products
+ * is a matrix product.
+ * ---------------------------------------------------------------------- */
+
+/* Filter transform U = G g G^T for every (k, c) (offline, once per weights).
+ * w: device, K x C x r x r float32.  U: device, filter_bytes.
+ * x_absmax: device, C float32 per-input-channel bounds of |x| used for the
+ *   power-of-two scaling of the 16-bit Hadamard stage, or NULL (bound 1).
+ *   Ignored for WG_F32.
+ * For WG_F16 / WG_BF16 the per (tile element e=(e1,e2), channel c) exponent
+ *   s = floor((E_V - E_U) / 2),
+ *   E_V = E(|B^T_e1|_1) + E(|B^T_e2|_1) + E(x_absmax[c]),
+ *   E_U = E(|G_e1|_1) + E(|G_e2|_1) + E(max_k,u,v |w[k][c][u][v]|),
+ * with E(v) the binary exponent of v (v = f 2^E, 0.5 <= f < 1; E(0) = 0) and
+ * row norms summed in float64, is stored with U, and U' = RN16(U 2^s).
+ * Padding rows/columns of U (k >= K, c >= C) are written as zeros. */
+int wg_transform_filters(const wg_plan* plan, const float* w, const float* x_absmax,
+                         void* U, wg_stream_t stream);
+
+/* Full forward pass: input transform -> Hadamard/channel-sum GEMM ->
+ * output transform.  x: device N x C x H x W.  U: device, from
+ * wg_transform_filters with the same plan.  y: device N x K x Hout x Wout.
+ * ws: device workspace of at least workspace_bytes (WG_EWORKSPACE otherwise);
+ * its contents on return are the V' and M buffers of this pass. */
+int wg_conv2d_forward(const wg_plan* plan, const float* x, const void* U, float* y,
+                      void* ws, size_t ws_bytes, wg_stream_t stream);
+
+/* The three stages of wg_conv2d_forward, separately (same buffers):
+ *   input:  V'[e][p][c] = scaled/rounded (B^T d B)[e] of tile p, channel c
+ *   gemm:   M[e][k][p] = sum_c U'[e][k][c] V'[e][p][c]  (float32 accumulation)
+ *   output: y tile p, channel k = (A^T M[.][k][p] A), outputs past the edge
+ *           discarded. */
+int wg_input_transform(const wg_plan* plan, const float* x, const void* U,
+                       void* ws, size_t ws_bytes, wg_stream_t stream);
+int wg_hadamard_gemm(const wg_plan* plan, const void* U, void* ws, size_t ws_bytes,
+                     wg_stream_t stream);
+int wg_output_transform(const wg_plan* plan, const void* ws, size_t ws_bytes, float* y,
+                        wg_stream_t stream);
+
+/* Per-channel max |x| over n, h, w.  x: device N x C x H x W; out: device C. */
+int wg_channel_absmax(const float* x, int N, int C, int H, int W, float* out,
+                      wg_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Error scoring (device).  Section 6: the error of a float32 result is its
+ * L1 distance to a float64 direct convolution.
+ * ---------------------------------------------------------------------- */
+
+/* float64 direct convolution of the float32 inputs (eq. conv as a zero-padded
+ * cross-correlation): y_ref[n][k][i][j] = sum_{c,u,v} x[n][c][i+u-p][j+v-p]
+ * w[k][c][u][v].  x, w: device float32; y_ref: device float64 N x K x Hout x
+ * Wout.  1 <= r <= 7.  Errors: WG_EINVAL. */
+int wg_direct_conv_f64(const float* x, const float* w, double* y_ref,
+                       int N, int C, int K, int H, int W, int r, int padding,
+                       wg_stream_t stream);
+
+/* out2 (device, 2 doubles) = { sum |y - y_ref|, sum |y_ref| } in float64, with
+ * a fixed reduction tree (bitwise reproducible for a given count).
+ * ws: device, at least wg_score_workspace_bytes(count) bytes.
+ * Relative L1 = out2[0]/out2[1]; mean absolute error = out2[0]/count. */
+size_t wg_score_workspace_bytes(size_t count);
+int wg_score_error(const float* y, const double* y_ref, size_t count, double* out2,
+                   void* ws, size_t ws_bytes, wg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WG_H */

@@ -284,15 +284,22 @@ def winograd_layer_tiles(x, w, mats, m, padding, dtype="f32", x_absmax=None, til
     return xform2d(AT, Mh)
 
 
+def assemble_tiles(Y, N, Th, Tw, Ho, Wo):
+    """Output tiles (K, P, m, m) -> image layout (N, K, Ho, Wo); the parts of
+    edge tiles past the output are discarded."""
+    K, P, m, _ = Y.shape
+    Y = Y.reshape(K, N, Th, Tw, m, m).transpose(1, 0, 2, 4, 3, 5)
+    Y = Y.reshape(N, K, Th * m, Tw * m)
+    return np.ascontiguousarray(Y[:, :, :Ho, :Wo])
+
+
 def winograd_layer(x, w, mats, m, padding, dtype="f32", x_absmax=None):
     """Full float Winograd layer: x (N,C,H,W), w (K,C,r,r) -> y (N,K,Ho,Wo)."""
     N, C, H, W = x.shape
     K, r = w.shape[0], w.shape[2]
     p, Ho, Wo, Th, Tw = layer_geometry(H, W, r, m, padding)
     Y = winograd_layer_tiles(x, w, mats, m, padding, dtype, x_absmax)
-    Y = Y.reshape(K, N, Th, Tw, m, m).transpose(1, 0, 2, 4, 3, 5)
-    Y = Y.reshape(N, K, Th * m, Tw * m)
-    return np.ascontiguousarray(Y[:, :, :Ho, :Wo])
+    return assemble_tiles(Y, N, Th, Tw, Ho, Wo)
 
 
 def direct_layer_f64(x, w, padding):

@@ -1,0 +1,245 @@
+// Hadamard product + channel sum of the Winograd layer as alpha^2 independent
+// matrix products on the gfx950 matrix cores (MFMA):
+//
+//     M[e] (K x P) = U'[e] (K x C) . V'[e]^T        for every tile element e
+//
+// The paper points out that this stage dominates the run time of a Winograd
+// layer and is a matrix multiplication independent of the points
+// (arXiv:2201.10369, Sections 4.1 and 5.2).  Both operands are stored with
+// the contraction index c contiguous (U'[e][k][c], V'[e][p][c]), which is the
+// register layout the MFMA instructions want for both A and B; M[e][k][p]
+// keeps p contiguous for the output transform.
+//
+// Tiling: a 256-thread block computes a BM x BN tile of M[e] with four waves
+// in a 2 x 2 arrangement, each wave a (BM/2) x (BN/2) sub-tile made of 32 x 32
+// MFMA blocks.  The contraction runs in steps of BK elements (128 bytes of
+// each operand row) through double-buffered LDS, with the next step's global
+// loads in flight while the current one is multiplied.  Block ids are mapped
+// so that consecutive work items (same e, neighbouring tiles) run on the same
+// XCD and share its L2.
+//
+// Element types: float32 (v_mfma_f32_32x32x2_f32), float16 and bfloat16 with
+// float32 accumulation (v_mfma_f32_32x32x16_{f16,bf16}).
+#include <hip/hip_runtime.h>
+
+#include "wg_device.h"
+#include "wg_internal.h"
+
+namespace wg {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kXcds = 8;
+
+// Bytes per operand row per contraction step, and LDS row pitch (16 bytes of
+// padding keep the 16-byte LDS reads of 8 consecutive rows on distinct banks).
+constexpr int kStepBytes = 128;
+constexpr int kPitchBytes = kStepBytes + 16;
+
+template <int DT>
+struct MfmaOp;
+
+template <>
+struct MfmaOp<kF32> {
+    static constexpr int kElem = 4;
+    // per 128-byte step (32 floats): each half-wave holds 16 consecutive k of
+    // one row; instruction q multiplies element q of both operands.
+    __device__ static __forceinline__ void step(const char* a_row, const char* b_row, int half,
+                                                f32x16& acc) {
+        const f32x4* pa = reinterpret_cast<const f32x4*>(a_row + half * 64);
+        const f32x4* pb = reinterpret_cast<const f32x4*>(b_row + half * 64);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const f32x4 a = pa[v];
+            const f32x4 b = pb[v];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], acc, 0, 0, 0);
+        }
+    }
+};
+
+template <>
+struct MfmaOp<kF16> {
+    static constexpr int kElem = 2;
+    // per 128-byte step (64 halves): 4 instructions of k = 16, each half-wave
+    // holding 8 consecutive k of its row.
+    __device__ static __forceinline__ void step(const char* a_row, const char* b_row, int half,
+                                                f32x16& acc) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const u32x4 a = *reinterpret_cast<const u32x4*>(a_row + s * 32 + half * 16);
+            const u32x4 b = *reinterpret_cast<const u32x4*>(b_row + s * 32 + half * 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                         __builtin_bit_cast(f16x8, b), acc, 0, 0, 0);
+        }
+    }
+};
+
+template <>
+struct MfmaOp<kBF16> {
+    static constexpr int kElem = 2;
+    __device__ static __forceinline__ void step(const char* a_row, const char* b_row, int half,
+                                                f32x16& acc) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const u32x4 a = *reinterpret_cast<const u32x4*>(a_row + s * 32 + half * 16);
+            const u32x4 b = *reinterpret_cast<const u32x4*>(b_row + s * 32 + half * 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                          __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+        }
+    }
+};
+
+template <int BM, int BN, int DT>
+__global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restrict__ U,
+                                                            const char* __restrict__ V,
+                                                            float* __restrict__ Mout, int K_pad,
+                                                            int P_pad, int C_pad, int nKb, int nPb,
+                                                            int total, int per_xcd) {
+    constexpr int WM = BM / 2, WN = BN / 2;          // wave sub-tile
+    constexpr int FM = WM / 32, FN = WN / 32;         // 32 x 32 blocks per wave
+    constexpr int ELEM = MfmaOp<DT>::kElem;
+    constexpr int A_CHUNKS = BM * kStepBytes / 16;    // 16-byte chunks per A tile
+    constexpr int B_CHUNKS = BN * kStepBytes / 16;
+    constexpr int A_PER_T = A_CHUNKS / 256, B_PER_T = B_CHUNKS / 256;
+    static_assert(A_CHUNKS % 256 == 0 && B_CHUNKS % 256 == 0, "tile too small");
+
+    __shared__ __attribute__((aligned(16))) char smem[2 * (BM + BN) * kPitchBytes];
+
+    // XCD-aware work mapping
+    const int b = blockIdx.x;
+    const int w = (b % kXcds) * per_xcd + b / kXcds;
+    if (w >= total) return;
+    const int kb = w % nKb;
+    const int t2 = w / nKb;
+    const int pb = t2 % nPb;
+    const int e = t2 / nPb;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int half = lane >> 5, l32 = lane & 31;
+
+    const size_t row_bytes = (size_t)C_pad * ELEM;
+    const char* Ag = U + ((size_t)e * K_pad + (size_t)kb * BM) * row_bytes;
+    const char* Bg = V + ((size_t)e * P_pad + (size_t)pb * BN) * row_bytes;
+
+    u32x4 ra[A_PER_T], rb[B_PER_T];
+    auto gload = [&](int step) {
+        const size_t koff = (size_t)step * kStepBytes;
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) {
+            const int q = tid + i * 256;
+            const int row = q >> 3, ch = q & 7;
+            ra[i] = *reinterpret_cast<const u32x4*>(Ag + row * row_bytes + koff + ch * 16);
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i) {
+            const int q = tid + i * 256;
+            const int row = q >> 3, ch = q & 7;
+            rb[i] = *reinterpret_cast<const u32x4*>(Bg + row * row_bytes + koff + ch * 16);
+        }
+    };
+    auto sstore = [&](int buf) {
+        char* As = smem + buf * (BM + BN) * kPitchBytes;
+        char* Bs = As + BM * kPitchBytes;
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) {
+            const int q = tid + i * 256;
+            const int row = q >> 3, ch = q & 7;
+            *reinterpret_cast<u32x4*>(As + row * kPitchBytes + ch * 16) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i) {
+            const int q = tid + i * 256;
+            const int row = q >> 3, ch = q & 7;
+            *reinterpret_cast<u32x4*>(Bs + row * kPitchBytes + ch * 16) = rb[i];
+        }
+    };
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const int nsteps = (int)(row_bytes / kStepBytes);
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) gload(st + 1);
+        const char* As = smem + buf * (BM + BN) * kPitchBytes;
+        const char* Bs = As + BM * kPitchBytes;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const char* arow = As + (wm * WM + i * 32 + l32) * kPitchBytes;
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const char* brow = Bs + (wn * WN + j * 32 + l32) * kPitchBytes;
+                MfmaOp<DT>::step(arow, brow, half, acc[i][j]);
+            }
+        }
+        if (st + 1 < nsteps) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // 32 x 32 accumulator layout: lane holds column (lane % 32) and, in
+    // register r, row 8*(r/4) + 4*(lane/32) + r%4.
+    float* Mg = Mout + ((size_t)e * K_pad + (size_t)kb * BM) * P_pad + (size_t)pb * BN;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = wn * WN + j * 32 + l32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                Mg[(size_t)row * P_pad + col] = acc[i][j][r];
+            }
+        }
+}
+
+template <int BM, int BN, int DT>
+static int gemm_launch(const Plan& p, const void* U, void* ws, hipStream_t s) {
+    const wg_layout& L = p.L;
+    const int nKb = L.K_pad / BM, nPb = L.P_pad / BN;
+    const long total = (long)L.alpha * L.alpha * nKb * nPb;
+    if (total > (1L << 30)) return fail(WG_EUNSUPPORTED, "hadamard gemm: too many tiles");
+    const int per_xcd = (int)((total + kXcds - 1) / kXcds);
+    const char* V = static_cast<const char*>(ws) + L.v_offset;
+    float* Mb = reinterpret_cast<float*>(static_cast<char*>(ws) + L.m_offset);
+    hipLaunchKernelGGL((hadamard_gemm_kernel<BM, BN, DT>), dim3((unsigned)(per_xcd * kXcds)), dim3(256), 0, s,
+                       static_cast<const char*>(U), V, Mb, L.K_pad, L.P_pad, L.C_pad, nKb, nPb, (int)total,
+                       per_xcd);
+    return hip_check((int)hipGetLastError(), "hadamard_gemm_kernel");
+}
+
+template <int DT>
+static int gemm_dtype(const Plan& p, const void* U, void* ws, hipStream_t s) {
+    if (p.gemm_bm == 128 && p.gemm_bn == 128) return gemm_launch<128, 128, DT>(p, U, ws, s);
+    if (p.gemm_bm == 64 && p.gemm_bn == 64) return gemm_launch<64, 64, DT>(p, U, ws, s);
+    return fail(WG_EUNSUPPORTED, "hadamard gemm: tile shape not compiled");
+}
+
+int launch_hadamard_gemm(const Plan& p, const void* U, void* ws, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((size_t)p.L.C_pad * p.L.elem_bytes % kStepBytes != 0)
+        return fail(WG_EINVAL, "hadamard gemm: padded channel count not a multiple of the step");
+    switch (p.L.dtype) {
+        case WG_F32: return gemm_dtype<kF32>(p, U, ws, s);
+        case WG_F16: return gemm_dtype<kF16>(p, U, ws, s);
+        default: return gemm_dtype<kBF16>(p, U, ws, s);
+    }
+}
+
+}  // namespace wg

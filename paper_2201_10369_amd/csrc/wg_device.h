@@ -1,0 +1,62 @@
+// Device-side helpers shared by the Winograd HIP kernels (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wg {
+
+// The float32 matrices of one F(M x M, R x R) algorithm, passed by value as a
+// kernel argument so that every entry is a wave-uniform scalar.
+template <int M_, int R_>
+struct Mats {
+    static constexpr int M = M_;
+    static constexpr int R = R_;
+    static constexpr int A = M_ + R_ - 1;
+    float AT[M_][A];
+    float G[A][R_];
+    float BT[A][A];
+};
+
+// Round-to-nearest-even float32 -> bfloat16 bits (NaN stays a quiet NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Round-to-nearest-even float32 -> float16 bits (hardware conversion).
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float f) {
+    _Float16 h = (_Float16)f;
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+// Element types of the Hadamard stage.
+enum : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+template <int DT>
+struct Elem;
+template <>
+struct Elem<kF32> {
+    using T = float;
+    __device__ static __forceinline__ float from_f32(float v) { return v; }
+};
+template <>
+struct Elem<kF16> {
+    using T = uint16_t;
+    __device__ static __forceinline__ uint16_t from_f32(float v) { return f32_to_f16_bits(v); }
+};
+template <>
+struct Elem<kBF16> {
+    using T = uint16_t;
+    __device__ static __forceinline__ uint16_t from_f32(float v) { return f32_to_bf16_bits(v); }
+};
+
+}  // namespace wg
+
+// The (m, r) pairs with compiled kernels: r in {3, 5}, 1 <= m <= 8.
+#define WG_FOR_EACH_SIZE(X) \
+    X(1, 3) X(2, 3) X(3, 3) X(4, 3) X(5, 3) X(6, 3) X(7, 3) X(8, 3) \
+    X(1, 5) X(2, 5) X(3, 5) X(4, 5) X(5, 5) X(6, 5) X(7, 5) X(8, 5)

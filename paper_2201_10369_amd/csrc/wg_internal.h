@@ -1,0 +1,56 @@
+// Internal declarations shared by the host code and the kernel launchers of
+// the Winograd library.  Not part of the ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/wg.h"
+
+namespace wg {
+
+constexpr int kMaxAlpha = 16;
+
+// Per-thread error state behind wg_last_error().
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+
+struct Plan {
+    wg_layout L;
+    // float32 matrices, row-major with their true sizes
+    float AT[kMaxAlpha * kMaxAlpha];   // m x alpha
+    float G[kMaxAlpha * kMaxAlpha];    // alpha x r
+    float BT[kMaxAlpha * kMaxAlpha];   // alpha x alpha
+    // binary exponents of the float64 row L1 norms of B^T and G
+    int eB[kMaxAlpha];
+    int eG[kMaxAlpha];
+    // GEMM tiling chosen at plan creation
+    int gemm_bm, gemm_bn, gemm_bk;
+};
+
+// Exact construction (exact_construct.cpp): entries rounded to nearest float64.
+bool construct_exact(int m, int r, const double* pts, int nf, bool modified, double* AT, double* G,
+                     double* BT);
+
+// HIP status -> WG_EHIP with message; returns WG_OK when hip_ok is true.
+int hip_check(int hip_err, const char* what);
+
+// Launchers implemented in the .hip translation units.  They assume the
+// arguments were validated by the ABI layer.
+int launch_filter_transform(const Plan& p, const float* w, const float* x_absmax, void* U,
+                            void* stream);
+int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws,
+                           void* stream);
+int launch_hadamard_gemm(const Plan& p, const void* U, void* ws, void* stream);
+int launch_output_transform(const Plan& p, const void* ws, float* y, void* stream);
+int launch_channel_absmax(const float* x, int N, int C, int HW, float* out, void* stream);
+int launch_direct_f64(const float* x, const float* w, double* y, int N, int C, int K, int H,
+                      int W, int r, int pad, int Hout, int Wout, void* stream);
+int launch_score(const float* y, const double* yref, size_t count, double* out2, void* ws,
+                 void* stream);
+size_t score_partials(size_t count);
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace wg

@@ -1,0 +1,326 @@
+"""ctypes binding of libwg.so (the C ABI declared in include/wg.h).
+
+Argument marshalling only: every computation happens in the HIP library.
+Device buffers are torch tensors on a ROCm device; work is enqueued on the
+current torch stream (or the stream passed in).  Raises WGError when the
+library reports a failure, and RuntimeError when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwg.so")
+
+WG_MODIFIED, WG_UNMODIFIED = 0, 1
+WG_SAME, WG_VALID = 0, 1
+WG_F32, WG_F16, WG_BF16 = 0, 1, 2
+DTYPES = {"f32": WG_F32, "f16": WG_F16, "bf16": WG_BF16}
+PADDINGS = {"same": WG_SAME, "valid": WG_VALID}
+STATUS = {0: "WG_OK", -1: "WG_EINVAL", -2: "WG_ESINGULAR", -3: "WG_EUNSUPPORTED",
+          -4: "WG_EWORKSPACE", -5: "WG_ENOMEM", -6: "WG_EHIP"}
+
+c_int, c_double, c_float, c_size_t, c_void_p = (ctypes.c_int, ctypes.c_double, ctypes.c_float,
+                                                ctypes.c_size_t, ctypes.c_void_p)
+P_double = ctypes.POINTER(c_double)
+P_float = ctypes.POINTER(c_float)
+P_int = ctypes.POINTER(c_int)
+P_size_t = ctypes.POINTER(c_size_t)
+
+
+class WGError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [(n, c_int) for n in ("alpha", "m", "r", "pad", "N", "C", "K", "H", "W", "Hout", "Wout",
+                                     "Th", "Tw", "P", "P_pad", "K_pad", "C_pad", "dtype", "elem_bytes")] + \
+               [(n, c_size_t) for n in ("scale_offset", "filter_bytes", "v_offset", "m_offset",
+                                        "workspace_bytes")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_SIGS = {
+    "wg_last_error": (ctypes.c_char_p, []),
+    "wg_version": (c_int, []),
+    "wg_supported": (c_int, [c_int, c_int]),
+    "wg_transforms": (c_int, [c_int, c_int, P_double, c_int, c_int, P_double, P_double, P_double]),
+    "wg_transforms_f32": (c_int, [c_int, c_int, P_double, c_int, c_int, P_float, P_float, P_float]),
+    "wg_family_points": (c_int, [c_int, c_double, c_double, P_double]),
+    "wg_plan_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, P_double, c_int, c_int,
+                               c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
+    "wg_plan_destroy": (c_int, [c_void_p]),
+    "wg_plan_sizes": (c_int, [c_void_p, P_size_t, P_size_t, P_int, P_int]),
+    "wg_plan_layout": (c_int, [c_void_p, ctypes.POINTER(Layout)]),
+    "wg_plan_matrices": (c_int, [c_void_p, P_float, P_float, P_float]),
+    "wg_transform_filters": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "wg_conv2d_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "wg_input_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "wg_hadamard_gemm": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "wg_output_transform": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "wg_channel_absmax": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p]),
+    "wg_direct_conv_f64": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int,
+                                   c_int, c_int, c_void_p]),
+    "wg_score_workspace_bytes": (c_size_t, [c_size_t]),
+    "wg_score_error": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_size_t, c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libwg.so (built in-tree); fails loudly when it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2201_10369_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status < 0:
+        raise WGError(status, lib().wg_last_error().decode())
+    return status
+
+
+def _dptr(arr):
+    return arr.ctypes.data_as(P_double)
+
+
+def _fptr(arr):
+    return arr.ctypes.data_as(P_float)
+
+
+# ----------------------------------------------------------------------------
+# device-buffer helpers
+# ----------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _tptr(t, dtype=None, name="tensor"):
+    """Device pointer of a contiguous torch tensor on a GPU (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+# ----------------------------------------------------------------------------
+# host functions
+# ----------------------------------------------------------------------------
+def transforms(m, r, pts, modified=True, f32=False):
+    """(A^T, G, B^T) from ordered finite points (numpy float64 or float32)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    alpha = m + r - 1
+    dt = np.float32 if f32 else np.float64
+    AT = np.zeros((m, alpha), dt)
+    G = np.zeros((alpha, r), dt)
+    BT = np.zeros((alpha, alpha), dt)
+    fn = lib().wg_transforms_f32 if f32 else lib().wg_transforms
+    conv = _fptr if f32 else _dptr
+    _check(fn(m, r, _dptr(pts), len(pts), WG_MODIFIED if modified else WG_UNMODIFIED,
+              conv(AT), conv(G), conv(BT)))
+    return AT, G, BT
+
+
+def family_points(alpha, c1, c2=1.0):
+    out = np.zeros(16, dtype=np.float64)
+    n = _check(lib().wg_family_points(alpha, float(c1), float(c2), _dptr(out)))
+    return out[:n].copy()
+
+
+def supported(m, r):
+    return bool(lib().wg_supported(m, r))
+
+
+class Plan:
+    """A Winograd layer plan: points, F(m x m, r x r), layer shape, dtype."""
+
+    def __init__(self, m, r, pts, N, C, K, H, W, padding="same", dtype="f32"):
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        h = c_void_p()
+        _check(lib().wg_plan_create(ctypes.byref(h), m, r, _dptr(pts), len(pts), WG_MODIFIED,
+                                    N, C, K, H, W, PADDINGS[padding], DTYPES[dtype]))
+        self._h = h
+        self.m, self.r, self.dtype, self.padding = m, r, dtype, padding
+        lay = Layout()
+        _check(lib().wg_plan_layout(self._h, ctypes.byref(lay)))
+        self.layout = lay.as_dict()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.wg_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def filter_bytes(self):
+        return self.layout["filter_bytes"]
+
+    @property
+    def workspace_bytes(self):
+        return self.layout["workspace_bytes"]
+
+    @property
+    def out_hw(self):
+        return self.layout["Hout"], self.layout["Wout"]
+
+    def matrices(self):
+        L = self.layout
+        a, m, r = L["alpha"], L["m"], L["r"]
+        AT = np.zeros((m, a), np.float32)
+        G = np.zeros((a, r), np.float32)
+        BT = np.zeros((a, a), np.float32)
+        _check(lib().wg_plan_matrices(self._h, _fptr(AT), _fptr(G), _fptr(BT)))
+        return AT, G, BT
+
+    # -- device buffers -----------------------------------------------------
+    def empty_filters(self, device="cuda"):
+        torch = _torch()
+        return torch.empty(self.filter_bytes, dtype=torch.uint8, device=device)
+
+    def empty_workspace(self, device="cuda"):
+        torch = _torch()
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def empty_output(self, device="cuda"):
+        torch = _torch()
+        L = self.layout
+        return torch.empty((L["N"], L["K"], L["Hout"], L["Wout"]), dtype=torch.float32, device=device)
+
+    # -- stages ---------------------------------------------------------------
+    def transform_filters(self, w, x_absmax=None, U=None, stream=None):
+        torch = _torch()
+        U = self.empty_filters(w.device) if U is None else U
+        _check(lib().wg_transform_filters(self._h, _tptr(w, torch.float32, "w"),
+                                          _tptr(x_absmax, torch.float32, "x_absmax"),
+                                          _tptr(U, None, "U"), _stream(stream)))
+        return U
+
+    def forward(self, x, U, y=None, ws=None, stream=None):
+        torch = _torch()
+        y = self.empty_output(x.device) if y is None else y
+        ws = self.empty_workspace(x.device) if ws is None else ws
+        _check(lib().wg_conv2d_forward(self._h, _tptr(x, torch.float32, "x"), _tptr(U, None, "U"),
+                                       _tptr(y, torch.float32, "y"), _tptr(ws, None, "ws"),
+                                       ws.numel() * ws.element_size(), _stream(stream)))
+        return y
+
+    def input_transform(self, x, U, ws, stream=None):
+        torch = _torch()
+        _check(lib().wg_input_transform(self._h, _tptr(x, torch.float32, "x"), _tptr(U, None, "U"),
+                                        _tptr(ws, None, "ws"), ws.numel() * ws.element_size(),
+                                        _stream(stream)))
+
+    def hadamard_gemm(self, U, ws, stream=None):
+        _check(lib().wg_hadamard_gemm(self._h, _tptr(U, None, "U"), _tptr(ws, None, "ws"),
+                                      ws.numel() * ws.element_size(), _stream(stream)))
+
+    def output_transform(self, ws, y, stream=None):
+        torch = _torch()
+        _check(lib().wg_output_transform(self._h, _tptr(ws, None, "ws"), ws.numel() * ws.element_size(),
+                                         _tptr(y, torch.float32, "y"), _stream(stream)))
+
+    # -- views of the buffers (for tests) --------------------------------------
+    def _elem_dtype(self):
+        torch = _torch()
+        return {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[self.dtype]
+
+    def view_U(self, U):
+        L = self.layout
+        E = L["alpha"] ** 2
+        n = E * L["K_pad"] * L["C_pad"] * L["elem_bytes"]
+        return U[:n].view(self._elem_dtype()).view(E, L["K_pad"], L["C_pad"])
+
+    def view_scales(self, U):
+        torch = _torch()
+        L = self.layout
+        E = L["alpha"] ** 2
+        off = L["scale_offset"]
+        return U[off:off + E * L["C_pad"] * 4].view(torch.int32).view(E, L["C_pad"])
+
+    def view_V(self, ws):
+        L = self.layout
+        E = L["alpha"] ** 2
+        n = E * L["P_pad"] * L["C_pad"] * L["elem_bytes"]
+        off = L["v_offset"]
+        return ws[off:off + n].view(self._elem_dtype()).view(E, L["P_pad"], L["C_pad"])
+
+    def view_M(self, ws):
+        torch = _torch()
+        L = self.layout
+        E = L["alpha"] ** 2
+        off = L["m_offset"]
+        return ws[off:off + E * L["K_pad"] * L["P_pad"] * 4].view(torch.float32).view(E, L["K_pad"], L["P_pad"])
+
+
+# ----------------------------------------------------------------------------
+# scoring
+# ----------------------------------------------------------------------------
+def direct_conv_f64(x, w, padding="same", y=None, stream=None):
+    torch = _torch()
+    N, C, H, W = x.shape
+    K, _, r, _ = w.shape
+    p = (r - 1) // 2 if padding == "same" else 0
+    Ho, Wo = H + 2 * p - r + 1, W + 2 * p - r + 1
+    y = torch.empty((N, K, Ho, Wo), dtype=torch.float64, device=x.device) if y is None else y
+    _check(lib().wg_direct_conv_f64(_tptr(x, torch.float32, "x"), _tptr(w, torch.float32, "w"),
+                                    _tptr(y, torch.float64, "y_ref"), N, C, K, H, W, r,
+                                    PADDINGS[padding], _stream(stream)))
+    return y
+
+
+def score_error(y, yref, out=None, ws=None, stream=None):
+    """Device tensor [sum|y - yref|, sum|yref|] (float64)."""
+    torch = _torch()
+    count = y.numel()
+    if yref.numel() != count:
+        raise ValueError("y and yref differ in size")
+    out = torch.empty(2, dtype=torch.float64, device=y.device) if out is None else out
+    need = lib().wg_score_workspace_bytes(count)
+    ws = torch.empty(need, dtype=torch.uint8, device=y.device) if ws is None else ws
+    _check(lib().wg_score_error(_tptr(y, torch.float32, "y"), _tptr(yref, torch.float64, "yref"), count,
+                                _tptr(out, torch.float64, "out"), _tptr(ws, None, "ws"),
+                                ws.numel() * ws.element_size(), _stream(stream)))
+    return out
+
+
+def channel_absmax(x, out=None, stream=None):
+    torch = _torch()
+    N, C, H, W = x.shape
+    out = torch.empty(C, dtype=torch.float32, device=x.device) if out is None else out
+    _check(lib().wg_channel_absmax(_tptr(x, torch.float32, "x"), N, C, H, W,
+                                   _tptr(out, torch.float32, "out"), _stream(stream)))
+    return out

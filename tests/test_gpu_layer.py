@@ -1,0 +1,295 @@
+"""GPU parity of the Winograd layer (C ABI through the ctypes binding) against
+the CPU oracle: stage by stage and end to end, at small sizes spanning several
+tiles with ragged edges, and at the full layer sizes on sampled tiles."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fp
+from oracle import toomcook as tc
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _wg():
+    from paper_2201_10369_amd import wg
+    return wg
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _oracle_mats(pts, m, r):
+    from fractions import Fraction as Fr
+    return fp.mats_f32([Fr(float(p)) for p in pts], m, r)
+
+
+def _as_f32(t):
+    return t.float() if t.dtype in (torch.float16, torch.bfloat16) else t
+
+
+def _setup(m, r, pts, N, C, K, H, W, padding, dtype, dist="normal", x_absmax=False):
+    wg = _wg()
+    x, w = synth.layer_inputs(N, C, K, H, W, r, dist)
+    plan = wg.Plan(m, r, pts, N, C, K, H, W, padding, dtype)
+    xd, wd = _dev(x), _dev(w)
+    ax = np.abs(x).max(axis=(0, 2, 3)).astype(np.float32) if x_absmax else None
+    U = plan.transform_filters(wd, _dev(ax) if ax is not None else None)
+    return plan, x, w, xd, wd, U, ax
+
+
+def _propagated_bound(mats, U, V, M):
+    """Elementwise bound on |y_gpu - y_oracle| for output tiles (K, P, m, m)
+    when both sides start from the same operands U (K,C,a,a), V (P,C,a,a):
+    the channel sums may differ by 2 gamma_C sum|U||V| (any summation order,
+    Higham eq. 3.5), which the output transform propagates through |A^T|,
+    plus a different rounding of the output transform itself."""
+    C = U.shape[1]
+    gam = C * U32 / (1 - C * U32)
+    aU, aV = np.abs(U.astype(np.float64)), np.abs(V.astype(np.float64))
+    K, P, a = U.shape[0], V.shape[0], U.shape[2]
+    absUV = np.einsum("kce,pce->kpe", aU.reshape(K, C, a * a), aV.reshape(P, C, a * a)).reshape(K, P, a, a)
+    AT = np.abs(mats[0].astype(np.float64))
+    bM = 2 * gam * absUV
+    bY = np.einsum("ik,nmkl,jl->nmij", AT, bM, AT)
+    bY += 4 * a * U32 * np.einsum("ik,nmkl,jl->nmij", AT, np.abs(M.astype(np.float64)), AT)
+    return bY
+
+
+# ----------------------------------------------------------------------------
+# stage parity
+# ----------------------------------------------------------------------------
+CASES = [
+    # m, r, alpha-family (c1, c2), N, C, K, H, W, padding
+    (2, 3, (4, 1.0, 1.0), 1, 16, 16, 32, 32, "same"),
+    (4, 3, (6, 2.0, 1.0), 2, 40, 72, 13, 11, "same"),
+    (6, 3, (8, 2.0, 1.0), 2, 70, 65, 17, 20, "same"),
+    (4, 3, (6, 1.622, 1.0), 1, 33, 17, 9, 14, "valid"),
+    (3, 5, (7, 1.3, 2.5), 1, 24, 20, 12, 13, "same"),
+    (6, 5, (10, 1.272, 2.099), 1, 8, 9, 15, 11, "valid"),
+]
+
+
+def _pts(fam):
+    wg = _wg()
+    alpha, c1, c2 = fam
+    if alpha == 4 and c1 == 1.0:
+        return np.array([0.0, 1.0, -1.0])          # the classic F(2,3) points
+    return wg.family_points(alpha, c1, c2)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", CASES)
+def test_transforms_bitexact(case, dtype):
+    """Filter and input transforms (and the 16-bit scaling) are bit-identical
+    to the oracle's fixed-order float32 evaluation."""
+    m, r, fam, N, C, K, H, W, padding = case
+    pts = _pts(fam)
+    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, padding, dtype, x_absmax=True)
+    mats = _oracle_mats(pts, m, r)
+    L = plan.layout
+    a = L["alpha"]
+    for mine, ref in zip(plan.matrices(), mats):
+        assert np.array_equal(mine, ref)
+    Uo, Vo = fp.transformed_operands(x, w, mats, m, padding, dtype, x_absmax=ax)
+    Ug = _host(_as_f32(plan.view_U(U)))                       # (E, K_pad, C_pad)
+    Ug = Ug.reshape(a, a, L["K_pad"], L["C_pad"]).transpose(2, 3, 0, 1)
+    assert np.array_equal(Ug[:K, :C], Uo)
+    assert not Ug[K:].any() and not Ug[:, C:].any()           # padding is zero
+    if dtype != "f32":
+        s = _host(plan.view_scales(U)).reshape(a, a, L["C_pad"])[:, :, :C]
+        assert np.array_equal(s, fp.scale_exponents(mats, w, ax))
+    ws = plan.empty_workspace()
+    plan.input_transform(xd, U, ws)
+    Vg = _host(_as_f32(plan.view_V(ws)))                       # (E, P_pad, C_pad)
+    Vg = Vg.reshape(a, a, L["P_pad"], L["C_pad"]).transpose(2, 3, 0, 1)
+    assert np.array_equal(Vg[:L["P"], :C], Vo)
+    assert not Vg[:L["P"], C:].any()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", CASES[:4])
+def test_gemm_and_output_transform(case, dtype):
+    """The MFMA channel-sum GEMM is within the summation-order bound of the
+    oracle's ascending sum; the output transform, fed the oracle's own M, is
+    bit-identical to the oracle's output transform."""
+    m, r, fam, N, C, K, H, W, padding = case
+    pts = _pts(fam)
+    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, padding, dtype)
+    mats = _oracle_mats(pts, m, r)
+    L = plan.layout
+    a, P = L["alpha"], L["P"]
+    Uo, Vo = fp.transformed_operands(x, w, mats, m, padding, dtype)
+    Mo = fp.hadamard_channel_sum(Uo, Vo)                         # (K, P, a, a)
+    ws = plan.empty_workspace()
+    plan.input_transform(xd, U, ws)
+    plan.hadamard_gemm(U, ws)
+    Mg = _host(plan.view_M(ws)).reshape(a, a, L["K_pad"], L["P_pad"]).transpose(2, 3, 0, 1)[:K, :P]
+    gam = C * U32 / (1 - C * U32)
+    absUV = np.einsum("kce,pce->kpe", np.abs(Uo.astype(np.float64)).reshape(K, C, a * a),
+                      np.abs(Vo.astype(np.float64)).reshape(P, C, a * a)).reshape(K, P, a, a)
+    assert np.all(np.abs(Mg.astype(np.float64) - Mo) <= 2 * gam * absUV + 1e-30)
+    # output transform on the oracle's M
+    Mv = plan.view_M(ws)
+    Mv[:, :K, :P] = _dev(Mo.transpose(2, 3, 0, 1).reshape(a * a, K, P))
+    y = plan.empty_output()
+    plan.output_transform(ws, y)
+    Yo = fp.assemble_tiles(fp.xform2d(mats[0], Mo), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
+    assert np.array_equal(_host(y), Yo)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", CASES)
+def test_forward_matches_oracle(case, dtype):
+    """End to end: elementwise within the propagated summation-order bound, and
+    relative L1 distance to the oracle below 1e-5 in float32."""
+    m, r, fam, N, C, K, H, W, padding = case
+    pts = _pts(fam)
+    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, padding, dtype)
+    mats = _oracle_mats(pts, m, r)
+    L = plan.layout
+    y = _host(plan.forward(xd, U))
+    Uo, Vo = fp.transformed_operands(x, w, mats, m, padding, dtype)
+    Mo = fp.hadamard_channel_sum(Uo, Vo)
+    yo = fp.assemble_tiles(fp.xform2d(mats[0], Mo), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
+    bound = fp.assemble_tiles(_propagated_bound(mats, Uo, Vo, Mo), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
+    diff = np.abs(y.astype(np.float64) - yo)
+    assert np.all(diff <= bound), (diff.max(), bound[diff > bound][:4])
+    e = fp.l1_errors(y, yo)
+    if dtype == "f32":
+        assert e["rel_l1"] <= 1e-5
+    # the error against float64 is what the oracle reports, within 5%
+    y64 = fp.direct_layer_f64(x, w, padding)
+    eg, eo = fp.l1_errors(y, y64)["rel_l1"], fp.l1_errors(yo, y64)["rel_l1"]
+    assert abs(eg - eo) <= 0.05 * eo + 1e-12
+
+
+def test_classic_f23_layer_is_exact_on_integers():
+    """F(2x2,3x3) with {0, 1, -1, inf} and small integer data: every value is
+    representable, so the GPU layer equals the exact direct convolution."""
+    wg = _wg()
+    N, C, K, H, W = 2, 20, 12, 15, 9
+    x = synth.exact_small_ints((N, C, H, W), 5, -3, 3)
+    w = synth.exact_small_ints((K, C, 3, 3), 6, -3, 3)
+    plan = wg.Plan(2, 3, [0.0, 1.0, -1.0], N, C, K, H, W, "same", "f32")
+    U = plan.transform_filters(_dev(w))
+    y = _host(plan.forward(_dev(x), U))
+    assert np.array_equal(y.astype(np.float64), fp.direct_layer_f64(x, w, "same"))
+
+
+# ----------------------------------------------------------------------------
+# scoring kernels
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,r,padding", [((2, 5, 7, 19, 23), 3, "same"), ((1, 3, 20, 40, 33), 5, "valid"),
+                                             ((3, 17, 9, 5, 6), 3, "valid"), ((1, 2, 1, 1, 1), 1, "same")])
+def test_direct_f64_matches_oracle(shape, r, padding):
+    wg = _wg()
+    N, C, K, H, W = shape
+    x, w = synth.layer_inputs(N, C, K, H, W, r, "normal")
+    y = _host(wg.direct_conv_f64(_dev(x), _dev(w), padding))
+    ref = fp.direct_layer_f64(x, w, padding)
+    assert np.allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_score_matches_oracle_and_is_reproducible():
+    wg = _wg()
+    rng = np.random.default_rng(3)
+    n = 1_000_003
+    yref = rng.standard_normal(n)
+    y = (yref + rng.standard_normal(n) * 1e-6).astype(np.float32)
+    out = _host(wg.score_error(_dev(y), _dev(yref)))
+    e = fp.l1_errors(y, yref)
+    assert out[0] == pytest.approx(e["abs_sum"], rel=1e-12)
+    assert out[1] == pytest.approx(e["ref_sum"], rel=1e-12)
+    again = _host(wg.score_error(_dev(y), _dev(yref)))
+    assert np.array_equal(out, again)
+
+
+def test_channel_absmax():
+    wg = _wg()
+    x, _ = synth.layer_inputs(3, 7, 1, 9, 11, 3, "normal")
+    got = _host(wg.channel_absmax(_dev(x)))
+    assert np.array_equal(got, np.abs(x).max(axis=(0, 2, 3)))
+
+
+def test_workspace_too_small_is_rejected():
+    wg = _wg()
+    plan = wg.Plan(4, 3, wg.family_points(6, 2.0), 1, 8, 8, 8, 8, "same", "f32")
+    ws = torch.empty(plan.workspace_bytes - 256, dtype=torch.uint8, device="cuda")
+    x = torch.zeros((1, 8, 8, 8), device="cuda")
+    U = plan.transform_filters(torch.zeros((8, 8, 3, 3), device="cuda"))
+    with pytest.raises(wg.WGError) as e:
+        plan.forward(x, U, ws=ws)
+    assert e.value.status == -4
+
+
+# ----------------------------------------------------------------------------
+# full layer sizes, sampled tiles
+# ----------------------------------------------------------------------------
+FULL = [
+    ("f4x4_n32_c256_k256_56x56", (6, 2.0, 1.0), "f32"),
+    ("f4x4_n32_c256_k256_56x56", (6, 1.622, 1.0), "f32"),
+    ("f6x6_n64_c256_k256_28x28", (8, 2.0, 1.0), "f32"),
+    ("f6x6_n64_c256_k256_28x28", (8, 2.0, 1.0), "f16"),
+    ("f6x6_n64_c256_k256_28x28", (8, 2.0, 1.0), "bf16"),
+]
+
+
+@pytest.mark.parametrize("name,fam,dtype", FULL)
+def test_full_size_sampled_tiles(name, fam, dtype):
+    """At the full layer sizes the GPU output on 48 sampled tiles (including the
+    first, the last and ragged edge tiles) is within the propagated bound of the
+    oracle and, in float32, within 1e-5 relative L1; the float64 direct
+    convolution agrees with the oracle at 200 sampled outputs."""
+    wg = _wg()
+    cfg = synth.LAYERS[name]
+    N, C, K, H, W, r, m = (cfg[k] for k in ("N", "C", "K", "H", "W", "r", "m"))
+    pts = wg.family_points(*fam)
+    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, "same", dtype, cfg["dist"])
+    L = plan.layout
+    y = plan.forward(xd, U)
+    rng = np.random.default_rng(17)
+    P = L["P"]
+    tiles = np.unique(np.concatenate([[0, P - 1, L["Tw"] - 1, P - L["Tw"]], rng.integers(0, P, 44)]))
+    mats = _oracle_mats(pts, m, r)
+    Uo, Vo = fp.transformed_operands(x, w, mats, m, "same", dtype, tiles=tiles)
+    Mo = fp.hadamard_channel_sum(Uo, Vo)
+    Yo = fp.xform2d(mats[0], Mo)                           # (K, S, m, m)
+    bound = _propagated_bound(mats, Uo, Vo, Mo)
+    yh = _host(y)
+    n = tiles // (L["Th"] * L["Tw"])
+    th = (tiles // L["Tw"]) % L["Th"]
+    tw = tiles % L["Tw"]
+    diffs, refs = [], []
+    for s in range(len(tiles)):
+        for i in range(m):
+            for j in range(m):
+                oi, oj = th[s] * m + i, tw[s] * m + j
+                if oi < L["Hout"] and oj < L["Wout"]:
+                    d = np.abs(yh[n[s], :, oi, oj].astype(np.float64) - Yo[:, s, i, j])
+                    assert np.all(d <= bound[:, s, i, j])
+                    diffs.append(d)
+                    refs.append(np.abs(Yo[:, s, i, j].astype(np.float64)))
+    rel = np.sum(diffs) / np.sum(refs)
+    if dtype == "f32":
+        assert rel <= 1e-5
+    # float64 direct convolution at sampled outputs
+    y64 = wg.direct_conv_f64(xd, wd, "same")
+    coords = np.stack([rng.integers(0, N, 200), rng.integers(0, K, 200), rng.integers(0, L["Hout"], 200),
+                       rng.integers(0, L["Wout"], 200)], axis=1)
+    coords[:4] = [[0, 0, 0, 0], [N - 1, K - 1, L["Hout"] - 1, L["Wout"] - 1], [0, 1, 0, L["Wout"] - 1],
+                  [N - 1, 0, L["Hout"] - 1, 0]]
+    ref = fp.direct_points_f64(x, w, "same", coords)
+    got = _host(y64)[coords[:, 0], coords[:, 1], coords[:, 2], coords[:, 3]]
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
