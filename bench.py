@@ -1,0 +1,190 @@
+"""Throughput of the Winograd layer F(6x6, 3x3) on one MI355X.
+
+Workload: N=64, C=K=256, H=W=28, stride 1, 'same' padding, points
+{0, inf, +-1, +-c, +-1/c} at c = 2, x ~ N(0,1), w ~ N(0, 1/sqrt(9C)).
+One step = filter transform + input transform + Hadamard/channel-sum GEMM +
+output transform, inputs resident in HBM.  The headline value is the
+effective TFLOP/s (direct-convolution FLOPs 2*N*K*C*Hout*Wout*r^2 per second)
+of the float16-MFMA form; the float32 form and the bfloat16 form are timed
+the same way and reported beside it, each with its relative L1 error against
+the float64 direct convolution (computed once, outside the timed region).
+
+Prints one JSON line (rank 0).  Usage: python bench.py [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "effective TFLOP/s F(6x6,3x3) FP16-MFMA vs FP32 plain at stated rel-L1 error"
+WORKLOAD = "f6x6_n64_c256_k256_28x28"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK = {"f16": 2500.0, "bf16": 2500.0, "f32": 157.3}     # dense TFLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--c", type=float, default=2.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-tiles", type=int, default=800)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(L, dtype):
+    """Bytes each stage must move at least (unpadded sizes)."""
+    E = L["alpha"] ** 2
+    eb = 2 if dtype != "f32" else 4
+    N, C, K, H, W, P = (L[k] for k in ("N", "C", "K", "H", "W", "P"))
+    x = N * C * H * W * 4
+    y = N * K * L["Hout"] * L["Wout"] * 4
+    V = E * P * C * eb
+    U = E * K * C * eb
+    M = E * K * P * 4
+    w = K * C * L["r"] ** 2 * 4
+    return {"filter": w + U, "input": x + V, "gemm": V + U + M, "output": M + y}
+
+
+def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup):
+    N, C, K, H, W = (L0[k] for k in ("N", "C", "K", "H", "W"))
+    plan = wg.Plan(6, 3, pts, N, C, K, H, W, "same", dtype)
+    ax = wg.channel_absmax(x) if dtype != "f32" else None
+    U = plan.empty_filters()
+    ws = plan.empty_workspace()
+    y = plan.empty_output()
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        plan.transform_filters(w, ax, U)
+        if ev:
+            ev[1].record(stream)
+        plan.input_transform(x, U, ws)
+        if ev:
+            ev[2].record(stream)
+        plan.hadamard_gemm(U, ws)
+        if ev:
+            ev[3].record(stream)
+        plan.output_transform(ws, y)
+        if ev:
+            ev[4].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    names = ["filter", "input", "gemm", "output"]
+    stage_ms = {n: float(np.mean([evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(steps)]))
+                for j, n in enumerate(names)}
+    return plan, U, y, elapsed / steps * 1e3, stage_ms
+
+
+def cpu_baseline(x, w, pts, ntiles):
+    """The oracle as it stands, float16 form, on the first `ntiles` tiles."""
+    from fractions import Fraction as Fr
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fp
+    mats = fp.mats_f32([Fr(float(p)) for p in pts], 6, 3)
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        for s0 in range(0, ntiles, 50):
+            fp.winograd_layer_tiles(x, w, mats, 6, "same", "f16", tiles=np.arange(s0, min(ntiles, s0 + 50)))
+    return time.perf_counter() - t0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the layer would shard along N or K with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2201_10369_amd import wg
+
+    cfg = synth.LAYERS[WORKLOAD]
+    N, C, K, H, W, r = (cfg[k] for k in ("N", "C", "K", "H", "W", "r"))
+    xh, wh = synth.layer_inputs(N, C, K, H, W, r, cfg["dist"])
+    x = torch.from_numpy(xh).cuda()
+    w = torch.from_numpy(wh).cuda()
+    pts = wg.family_points(8, args.c, 1.0)
+    L0 = dict(N=N, C=C, K=K, H=H, W=W)
+    flops = 2.0 * N * K * C * H * W * r * r               # 'same': Hout = H, Wout = W
+
+    forms = {}
+    for dtype in ("f16", "f32", "bf16"):
+        plan, U, y, ms, stage_ms = run_form(wg, torch, dtype, x, w, pts, L0, args.steps, args.warmup)
+        forms[dtype] = dict(plan=plan, y=y, ms=ms, stage_ms=stage_ms)
+
+    # errors against the float64 direct convolution (outside the timed region)
+    y64 = wg.direct_conv_f64(x, w, "same")
+    for dtype, f in forms.items():
+        s = wg.score_error(f["y"], y64).cpu().numpy()
+        f["rel_l1"] = float(s[0] / s[1])
+        f["mean_abs"] = float(s[0] / f["y"].numel())
+
+    L = forms["f16"]["plan"].layout
+    ab = algorithmic_bytes(L, "f16")
+    st = forms["f16"]["stage_ms"]
+    dom = max(st, key=st.get)
+    gemm_flops = 2.0 * L["alpha"] ** 2 * K * C * L["P"]
+    achieved_gbs = ab[dom] / (st[dom] * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes": ab[dom], "traffic": None}
+
+    f16 = forms["f16"]
+    value = flops / (f16["ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(f16["ms"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "points": f"0,inf,+-1,+-{args.c},+-1/{args.c}",
+                   "N": N, "C": C, "K": K, "H": H, "W": W, "m": 6, "r": 3, "padding": "same",
+                   "step": "filter+input+gemm+output transforms"},
+        "rel_l1": f16["rel_l1"],
+        "roofline": roofline,
+        "stages_ms": {d: {k: round(v, 5) for k, v in f["stage_ms"].items()} for d, f in forms.items()},
+        "stage_gbs_f16": {k: round(ab[k] / (st[k] * 1e-3) / 1e9, 1) for k in st},
+        "gemm_tflops": {d: round(gemm_flops / (f["stage_ms"]["gemm"] * 1e-3) / 1e12, 1) for d, f in forms.items()},
+        "forms": {d: {"value": round(flops / (f["ms"] * 1e-3) / 1e12, 2), "ms_per_step": round(f["ms"], 5),
+                      "rel_l1": f["rel_l1"], "mean_abs": f["mean_abs"]} for d, f in forms.items()},
+    }
+    if not args.no_cpu:
+        ntiles = min(args.cpu_tiles, L["P"])
+        secs = cpu_baseline(xh, wh, pts, ntiles)
+        cpu_flops = flops * ntiles / L["P"]
+        out["cpu_baseline"] = {"value": round(cpu_flops / secs / 1e12, 6), "unit": "TFLOP/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"float16 form of the oracle on the first {ntiles} of {L['P']} tiles "
+                                         f"(all 256 output channels), {secs:.1f} s on one core "
+                                         f"of {os.cpu_count()}"}
+    # a plain device copy of known size, for scaling hardware byte counters
+    a = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

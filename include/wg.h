@@ -135,7 +135,10 @@ int wg_plan_sizes(const wg_plan* plan, size_t* filter_bytes, size_t* workspace_b
 /* Buffer layout (all offsets in bytes from the start of the buffer named).
  *   U buffer:  U'[e][k][c], e < alpha^2, k < K_pad, c < C_pad, elem_bytes each;
  *              then (WG_F16 / WG_BF16 only) at scale_offset the int32 exponents
- *              s[e][c], c < C_pad.
+ *              s[e][c], c < C_pad; at chan_offset the int32 per-channel parts
+ *              t[c] = E(x_absmax[c]) - E(max|w[.][c]|), so that
+ *              s[e1*alpha+e2][c] = floor((dB[e1] + dB[e2] + t[c]) / 2) with
+ *              dB[i] = E(|B^T row i|_1) - E(|G row i|_1); then library scratch.
  *   workspace: V'[e][p][c] at v_offset (e < alpha^2, p < P_pad, c < C_pad,
  *              elem_bytes each) and M[e][k][p] float32 at m_offset
  *              (k < K_pad, p < P_pad).
@@ -147,7 +150,7 @@ typedef struct {
     int N, C, K, H, W, Hout, Wout, Th, Tw;
     int P, P_pad, K_pad, C_pad;
     int dtype, elem_bytes;
-    size_t scale_offset, filter_bytes;
+    size_t scale_offset, chan_offset, filter_bytes;
     size_t v_offset, m_offset, workspace_bytes;
 } wg_layout;
 int wg_plan_layout(const wg_plan* plan, wg_layout* out);

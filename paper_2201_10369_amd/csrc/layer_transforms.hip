@@ -15,6 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <set>
+#include <utility>
 
 #include "wg_device.h"
 #include "wg_internal.h"
@@ -32,282 +35,371 @@ static Geo make_geo(const wg_layout& L) {
 }
 
 struct RowExps {
-    int eB[kMaxAlpha];
-    int eG[kMaxAlpha];
+    int dB[kMaxAlpha];     // E(|B^T row i|_1) - E(|G row i|_1)
 };
 
-// ---------------------------------------------------------------------------
-// Power-of-two scale exponents of the 16-bit Hadamard stage, one block per
-// input channel c:  s[e][c] = floor((E_V - E_U) / 2).
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ int bin_exp(float v) {
     int e = 0;
     if (v != 0.0f) frexpf(v, &e);
     return e;
 }
 
-__global__ __launch_bounds__(256) void filter_scales_kernel(const float* __restrict__ w,
-                                                            const float* __restrict__ x_absmax,
-                                                            int32_t* __restrict__ scales, RowExps ex,
-                                                            int alpha, int K, int C, int C_pad, int rr) {
-    __shared__ float red[256];
-    const int c = blockIdx.x;
-    const int tid = threadIdx.x;
+// floor(d / 2): arithmetic right shift of a two's-complement int
+__device__ __forceinline__ int floor_half(int d) { return d >> 1; }
+
+// ---------------------------------------------------------------------------
+// 16-bit Hadamard stage, part 1: partial maxima of |w| over chunks of 32
+// filters for 64 channels per block (coalesced: a wave reads 64 consecutive
+// channels' r*r taps).  part[kc][c] for filter chunk kc.
+// ---------------------------------------------------------------------------
+constexpr int kKChunk = 8;
+
+template <int RR>
+__global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restrict__ w,
+                                                            float* __restrict__ part, int K, int C,
+                                                            int C_pad) {
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, kq = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
+    const int kc = blockIdx.y;
     float mx = 0.0f;
     if (c < C) {
-        const int per = K * rr;
-        for (int q = tid; q < per; q += 256) {
-            const int k = q / rr, uv = q - k * rr;
-            mx = fmaxf(mx, fabsf(w[((size_t)k * C + c) * rr + uv]));
+        float v[kKChunk / 4][RR];
+#pragma unroll
+        for (int i = 0; i < kKChunk / 4; ++i) {
+            const int k = kc * kKChunk + kq + 4 * i;
+#pragma unroll
+            for (int t = 0; t < RR; ++t) v[i][t] = k < K ? w[((size_t)k * C + c) * RR + t] : 0.0f;
         }
+#pragma unroll
+        for (int i = 0; i < kKChunk / 4; ++i)
+#pragma unroll
+            for (int t = 0; t < RR; ++t) mx = fmaxf(mx, fabsf(v[i][t]));
     }
-    red[tid] = mx;
+    red[kq][cl] = mx;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
-        __syncthreads();
-    }
-    const float aw = red[0];
-    const float ax = (x_absmax != nullptr && c < C) ? x_absmax[c] : 1.0f;
-    const int E = alpha * alpha;
-    for (int e = tid; e < E; e += 256) {
-        const int e1 = e / alpha, e2 = e - e1 * alpha;
-        int s = 0;
-        if (c < C) {
-            const int ev = ex.eB[e1] + ex.eB[e2] + bin_exp(ax);
-            const int eu = ex.eG[e1] + ex.eG[e2] + bin_exp(aw);
-            const int d = ev - eu;
-            s = d >= 0 ? d / 2 : -((1 - d) / 2);      // floor(d / 2)
-        }
-        scales[(size_t)e * C_pad + c] = s;
-    }
+    if (kq == 0 && c < C_pad)
+        part[(size_t)kc * C_pad + c] = fmaxf(fmaxf(red[0][cl], red[1][cl]), fmaxf(red[2][cl], red[3][cl]));
 }
 
 // ---------------------------------------------------------------------------
-// Filter transform U = G g G^T, one thread per (k, c) of the padded K x C.
+// 16-bit Hadamard stage, part 2: per channel c the exponent part
+// t[c] = E(x_absmax[c]) - E(max_k |w[k][c]|) and the table s[e][c].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void channel_exponent_kernel(const float* __restrict__ part,
+                                                               const float* __restrict__ x_absmax,
+                                                               int32_t* __restrict__ s_tab,
+                                                               int32_t* __restrict__ t_tab, RowExps ex,
+                                                               int alpha, int C, int C_pad, int kchunks) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= C_pad) return;
+    int tc = 0;
+    if (c < C) {
+        float aw = 0.0f;
+        int q = 0;
+        for (; q + 8 <= kchunks; q += 8) {         // eight loads in flight
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(q + u) * C_pad + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) aw = fmaxf(aw, v[u]);
+        }
+        for (; q < kchunks; ++q) aw = fmaxf(aw, part[(size_t)q * C_pad + c]);
+        const float ax = x_absmax != nullptr ? x_absmax[c] : 1.0f;
+        tc = bin_exp(ax) - bin_exp(aw);
+    }
+    t_tab[c] = tc;
+    for (int e1 = 0; e1 < alpha; ++e1)
+        for (int e2 = 0; e2 < alpha; ++e2)
+            s_tab[(size_t)(e1 * alpha + e2) * C_pad + c] = c < C ? floor_half(ex.dB[e1] + ex.dB[e2] + tc) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Filter transform U = G g G^T.  One thread per (row i of U, filter k,
+// channel c) of the padded K x C, channel fastest so every store of U'[e][k][.]
+// is a contiguous run of channels; for the 16-bit stage each row is scaled by
+// 2^s (s from the channel exponent table) before rounding.
 // ---------------------------------------------------------------------------
 template <int M, int R, int DT>
 __global__ __launch_bounds__(256) void filter_transform_kernel(const float* __restrict__ w,
                                                                void* __restrict__ Uout,
-                                                               const int32_t* __restrict__ scales,
-                                                               Mats<M, R> mt, Geo g) {
+                                                               const int32_t* __restrict__ t_tab,
+                                                               Mats<M, R> mt, NzMasks nzm, RowExps ex,
+                                                               Geo g) {
     constexpr int A = M + R - 1;
     using T = typename Elem<DT>::T;
+    __shared__ float sG[A][R];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int u = 0; u < R; ++u) sG[a][u] = mt.G[a][u];
+    }
+    __syncthreads();
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    const long total = (long)g.K_pad * g.C_pad;
+    const long total = (long)A * g.K_pad * g.C_pad;
     if (idx >= total) return;
-    const int k = (int)(idx / g.C_pad);
-    const int c = (int)(idx - (long)k * g.C_pad);
-    float gg[R][R];
+    const int c = (int)(idx % g.C_pad);
+    const long rest = idx / g.C_pad;
+    const int k = (int)(rest % g.K_pad);
+    const int i = (int)(rest / g.K_pad);
     const bool live = k < g.K && c < g.C;
+    float gg[R][R];
 #pragma unroll
     for (int u = 0; u < R; ++u)
 #pragma unroll
-        for (int v = 0; v < R; ++v)
-            gg[u][v] = live ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f;
-    // P1 = G g  (A x R)
-    float p1[A][R];
+        for (int v = 0; v < R; ++v) gg[u][v] = live ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f;
+    int si = 0;
+    if (DT != kF32) si = c < g.C ? t_tab[c] + ex.dB[i] : 0;
+    // row i of P1 = G g (the row index differs between threads: no skipping)
+    float p1[R];
 #pragma unroll
-    for (int i = 0; i < A; ++i)
+    for (int v = 0; v < R; ++v) p1[v] = 0.0f;
 #pragma unroll
-        for (int v = 0; v < R; ++v) p1[i][v] = 0.0f;
+    for (int u = 0; u < R; ++u) {
+        const float b = sG[i][u];
 #pragma unroll
-    for (int i = 0; i < A; ++i)
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-            const float b = mt.G[i][u];
-            if (b != 0.0f) {
-#pragma unroll
-                for (int v = 0; v < R; ++v) p1[i][v] = p1[i][v] + b * gg[u][v];
-            }
-        }
+        for (int v = 0; v < R; ++v) p1[v] = p1[v] + b * gg[u][v];
+    }
     T* U = reinterpret_cast<T*>(Uout);
+    const unsigned off = (unsigned)k * g.C_pad + c;
+    const size_t plane = in_vgpr((size_t)g.K_pad * g.C_pad);
 #pragma unroll
-    for (int i = 0; i < A; ++i)
+    for (int j = 0; j < A; ++j) {
+        float acc = 0.0f;
 #pragma unroll
-        for (int j = 0; j < A; ++j) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int v = 0; v < R; ++v) {
-                const float b = mt.G[j][v];
-                if (b != 0.0f) acc = acc + b * p1[i][v];
-            }
-            const int e = i * A + j;
-            if (DT != kF32) acc = ldexpf(acc, scales[(size_t)e * g.C_pad + c]);
-            U[((size_t)e * g.K_pad + k) * g.C_pad + c] = Elem<DT>::from_f32(acc);
-        }
+        for (int v = 0; v < R; ++v)
+            if (nz(nzm.g, j * R + v)) acc = acc + sG[j][v] * p1[v];
+        if (DT != kF32) acc = ldexpf(acc, c < g.C ? floor_half(si + ex.dB[j]) : 0);
+        T* Ue = U + (size_t)(i * A + j) * plane;
+        Ue[off] = Elem<DT>::from_f32(acc);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Input transform V = B^T d B.  A block covers one image n, one tile row th,
-// up to `twb` consecutive tiles of that row and 64 input channels: it stages
-// the alpha input rows of those channels in LDS with coalesced reads (zeros
-// outside the image), then each thread transforms one (channel, tile) pair;
-// a wave holds one tile and 64 consecutive channels, so every V' store is a
-// contiguous run of channels.
+// `twb` consecutive tiles of that row and 64 input channels (one wave per
+// tile).  It stages the alpha input rows of those channels in LDS (groups of
+// lanes read contiguous row segments, sixteen loads in flight per thread,
+// zeros outside the image), then each lane transforms one (channel, tile)
+// pair; the 64 lanes of a wave hold 64 consecutive channels of one tile, so
+// every V' store is one contiguous run.  The channel blocks of one tile row
+// are consecutive blocks of the grid, so the runs of one V' row are written
+// close together in time.
 // ---------------------------------------------------------------------------
 constexpr int kInCh = 64;
 
 template <int M, int R, int DT>
-__global__ __launch_bounds__(256) void input_transform_kernel(const float* __restrict__ x,
+__global__ __launch_bounds__(512) void input_transform_kernel(const float* __restrict__ x,
                                                               void* __restrict__ Vout,
-                                                              const int32_t* __restrict__ scales,
-                                                              Mats<M, R> mt, Geo g, int twb, int n_twb,
-                                                              int row_w, int ch_stride) {
+                                                              const int32_t* __restrict__ t_tab,
+                                                              Mats<M, R> mt, NzMasks nzm, RowExps ex, Geo g,
+                                                              int twb, int n_twb, int row_w, int ch_stride) {
     constexpr int A = M + R - 1;
+    constexpr int kBatch = 16;
+    const int nthr = blockDim.x;
     using T = typename Elem<DT>::T;
     extern __shared__ float lds[];
+    __shared__ float sBT[A][A];
     const int tid = threadIdx.x;
+    if (tid == 0) {
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int b = 0; b < A; ++b) sBT[a][b] = mt.BT[a][b];
+    }
+    const int n_cb = (g.C_pad + kInCh - 1) / kInCh;
     int bx = blockIdx.x;
+    const int c0 = (bx % n_cb) * kInCh;
+    bx /= n_cb;
     const int tb = bx % n_twb;
     bx /= n_twb;
     const int th = bx % g.Th;
     const int n = bx / g.Th;
-    const int c0 = blockIdx.y * kInCh;
     const int tw0 = tb * twb;
     const int ntw = min(twb, g.Tw - tw0);
     const int wl = ntw * M + R - 1;               // columns actually needed
     const int row0 = th * M - g.pad, col0 = tw0 * M - g.pad;
 
-    // stage: rows (c, a), columns 0..wl-1; groups of wl lanes read one row
+    // stage: each thread owns fixed (row a, column col) positions and walks
+    // the channels, so consecutive threads read contiguous row segments and
+    // the per-load address advances by one channel plane
     {
-        const int per = 256 / wl;                  // rows loaded per pass
-        const int lane_row = tid / wl, col = tid - lane_row * wl;
-        if (lane_row < per) {
-            const int gj = col0 + col;
-            const bool colok = gj >= 0 && gj < g.W;
-            for (int cr = lane_row; cr < kInCh * A; cr += per) {
-                const int c = cr / A, a = cr - c * A;
-                const int gc = c0 + c, gi = row0 + a;
-                float v = 0.0f;
-                if (colok && gc < g.C && gi >= 0 && gi < g.H)
-                    v = x[(((size_t)n * g.C + gc) * g.H + gi) * g.W + gj];
-                lds[c * ch_stride + a * row_w + col] = v;
+        const size_t hw = in_vgpr((size_t)g.H * g.W);
+        const int cstride = in_vgpr(ch_stride);
+        const int nch = min(kInCh, g.C - c0);      // channels present (may be <= 0)
+        for (int ac = tid; ac < A * wl; ac += nthr) {
+            const int a = ac / wl, col = ac - a * wl;
+            const int gi = row0 + a, gj = col0 + col;
+            const bool inside = gi >= 0 && gi < g.H && gj >= 0 && gj < g.W;
+            const float* src = x + (((size_t)n * g.C + c0) * g.H + (inside ? gi : 0)) * g.W + (inside ? gj : 0);
+            float* dst = lds + a * row_w + col;
+            for (int cb = 0; cb < kInCh; cb += kBatch) {
+                float v[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u)
+                    v[u] = (inside && cb + u < nch) ? src[(size_t)(cb + u) * hw] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) dst[(cb + u) * cstride] = v[u];
             }
         }
     }
     __syncthreads();
 
+    const int c = tid & (kInCh - 1), t = tid / kInCh;
+    const int gc = c0 + c;
+    if (t >= ntw || gc >= g.C_pad) return;
+    const int tcv = (DT != kF32 && gc < g.C) ? t_tab[gc] : 0;
+    const float* src = lds + c * ch_stride + t * M;
+    float d[A][A];
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+        for (int b = 0; b < A; ++b) d[a][b] = src[a * row_w + b];
+    // T1 = B^T d: row i of B^T (LDS broadcast), zero entries skipped
+    float t1[A][A];
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+#pragma unroll
+        for (int b = 0; b < A; ++b) t1[i][b] = 0.0f;
+        float brow[A];
+#pragma unroll
+        for (int l = 0; l < A; ++l) brow[l] = sBT[i][l];
+#pragma unroll
+        for (int l = 0; l < A; ++l)
+            if (nz(nzm.bt, i * A + l)) {
+#pragma unroll
+                for (int b = 0; b < A; ++b) t1[i][b] = t1[i][b] + brow[l] * d[l][b];
+            }
+    }
+    const unsigned p = ((unsigned)n * g.Th + th) * g.Tw + tw0 + t;
+    const unsigned off = p * (unsigned)g.C_pad + gc;            // offset inside one e plane
+    const size_t plane = in_vgpr((size_t)g.P_pad * g.C_pad);
     T* V = reinterpret_cast<T*>(Vout);
-    const int items = kInCh * ntw;
-    for (int it = tid; it < items; it += 256) {
-        const int c = it % kInCh, t = it / kInCh;
-        const int gc = c0 + c;
-        if (gc >= g.C_pad) continue;
-        const float* src = lds + c * ch_stride + t * M;
-        float d[A][A];
+    int sv[A];
 #pragma unroll
-        for (int a = 0; a < A; ++a)
+    for (int i = 0; i < A; ++i) sv[i] = gc < g.C ? ex.dB[i] + tcv : 0;
+    // V = T1 B one column j at a time: V[i][j] = sum_l T1[i][l] B^T[j][l]
 #pragma unroll
-            for (int b = 0; b < A; ++b) d[a][b] = src[a * row_w + b];
-        // T1 = B^T d
-        float t1[A][A];
+    for (int j = 0; j < A; ++j) {
+        float brow[A];
 #pragma unroll
-        for (int i = 0; i < A; ++i)
+        for (int l = 0; l < A; ++l) brow[l] = sBT[j][l];
+        float col[A];
 #pragma unroll
-            for (int b = 0; b < A; ++b) t1[i][b] = 0.0f;
+        for (int i = 0; i < A; ++i) col[i] = 0.0f;
 #pragma unroll
-        for (int i = 0; i < A; ++i)
+        for (int l = 0; l < A; ++l)
+            if (nz(nzm.bt, j * A + l)) {
 #pragma unroll
-            for (int l = 0; l < A; ++l) {
-                const float bv = mt.BT[i][l];
-                if (bv != 0.0f) {
-#pragma unroll
-                    for (int b = 0; b < A; ++b) t1[i][b] = t1[i][b] + bv * d[l][b];
-                }
+                for (int i = 0; i < A; ++i) col[i] = col[i] + t1[i][l] * brow[l];
             }
-        const size_t p = ((size_t)n * g.Th + th) * g.Tw + tw0 + t;
-        // V = T1 B, written element by element
 #pragma unroll
-        for (int i = 0; i < A; ++i)
-#pragma unroll
-            for (int j = 0; j < A; ++j) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int l = 0; l < A; ++l) {
-                    const float bv = mt.BT[j][l];
-                    if (bv != 0.0f) acc = acc + bv * t1[i][l];
-                }
-                const int e = i * A + j;
-                if (DT != kF32) acc = ldexpf(acc, -scales[(size_t)e * g.C_pad + gc]);
-                V[((size_t)e * g.P_pad + p) * g.C_pad + gc] = Elem<DT>::from_f32(acc);
-            }
+        for (int i = 0; i < A; ++i) {
+            float v = col[i];
+            if (DT != kF32) v = ldexpf(v, gc < g.C ? -floor_half(sv[i] + ex.dB[j]) : 0);
+            T* Ve = V + (size_t)(i * A + j) * plane;
+            Ve[off] = Elem<DT>::from_f32(v);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Output transform Y = A^T M A.  A block covers one output channel k and
 // `nb` consecutive tile rows ("bands", band = n*Th + th).  Each thread
-// transforms one tile into LDS; the block then writes every band, which is a
-// contiguous run of up to m*Wout floats of y, with consecutive threads.
+// transforms one tile and leaves its in-range outputs in LDS laid out exactly
+// like the image rows (pitch Wout); the rows of consecutive bands of one
+// image are contiguous in y, so the block then copies each image's run with
+// consecutive threads.
 // ---------------------------------------------------------------------------
 template <int M, int R>
 __global__ __launch_bounds__(256) void output_transform_kernel(const float* __restrict__ Mbuf,
                                                                float* __restrict__ y, Mats<M, R> mt,
-                                                               Geo g, int nb) {
+                                                               NzMasks nzm, Geo g, int nb,
+                                                               unsigned plane_stride) {
     constexpr int A = M + R - 1;
     extern __shared__ float lds[];
+    __shared__ float sAT[M][A];
     const int tid = threadIdx.x;
+    if (tid == 0) {
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int b = 0; b < A; ++b) sAT[a][b] = mt.AT[a][b];
+    }
+    __syncthreads();
     const int k = blockIdx.y;
     const int band0 = blockIdx.x * nb;
     const int nbands = g.N * g.Th;
     const int nbl = min(nb, nbands - band0);
-    const int row_w = g.Tw * M;
     const int items = nbl * g.Tw;
-    const size_t E = (size_t)A * A;
     for (int it = tid; it < items; it += 256) {
         const int bl = it / g.Tw, tw = it - bl * g.Tw;
-        const size_t p = (size_t)(band0 + bl) * g.Tw + tw;
+        // offset inside one plane of M; the alpha^2 planes are plane_stride apart
+        const unsigned off = (unsigned)k * g.P_pad + (unsigned)(band0 + bl) * g.Tw + tw;
+        const size_t pstride = in_vgpr((size_t)plane_stride);
         float mm[A][A];
 #pragma unroll
         for (int a = 0; a < A; ++a)
 #pragma unroll
-            for (int b = 0; b < A; ++b)
-                mm[a][b] = Mbuf[((size_t)(a * A + b) * g.K_pad + k) * g.P_pad + p];
-        (void)E;
-        // Z = A^T M  (M x A)
+            for (int b = 0; b < A; ++b) {
+                const float* Me = Mbuf + (size_t)(a * A + b) * pstride;
+                mm[a][b] = Me[off];
+            }
+        // Z = A^T M  (M x A), rows of A^T from LDS, zero entries skipped
         float z[M][A];
 #pragma unroll
-        for (int i = 0; i < M; ++i)
+        for (int i = 0; i < M; ++i) {
 #pragma unroll
             for (int b = 0; b < A; ++b) z[i][b] = 0.0f;
+            float arow[A];
 #pragma unroll
-        for (int i = 0; i < M; ++i)
+            for (int l = 0; l < A; ++l) arow[l] = sAT[i][l];
 #pragma unroll
-            for (int l = 0; l < A; ++l) {
-                const float av = mt.AT[i][l];
-                if (av != 0.0f) {
+            for (int l = 0; l < A; ++l)
+                if (nz(nzm.at, i * A + l)) {
 #pragma unroll
-                    for (int b = 0; b < A; ++b) z[i][b] = z[i][b] + av * mm[l][b];
+                    for (int b = 0; b < A; ++b) z[i][b] = z[i][b] + arow[l] * mm[l][b];
                 }
-            }
-        float* dst = lds + (bl * M) * row_w + tw * M;
+        }
+        const int th = (band0 + bl) % g.Th;
+        const int rows = min(M, g.Hout - th * M);
+        const int cols = min(M, g.Wout - tw * M);
+        float* dst = lds + (bl * M) * g.Wout + tw * M;
+        // Y = Z A one column j at a time: Y[i][j] = sum_l Z[i][l] A^T[j][l]
 #pragma unroll
-        for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+            float arow[A];
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                float acc = 0.0f;
+            for (int l = 0; l < A; ++l) arow[l] = sAT[j][l];
+            float col[M];
 #pragma unroll
-                for (int l = 0; l < A; ++l) {
-                    const float av = mt.AT[j][l];
-                    if (av != 0.0f) acc = acc + av * z[i][l];
+            for (int i = 0; i < M; ++i) col[i] = 0.0f;
+#pragma unroll
+            for (int l = 0; l < A; ++l)
+                if (nz(nzm.at, j * A + l)) {
+#pragma unroll
+                    for (int i = 0; i < M; ++i) col[i] = col[i] + z[i][l] * arow[l];
                 }
-                dst[i * row_w + j] = acc;
-            }
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+                if (i < rows && j < cols) dst[i * g.Wout + j] = col[i];
+        }
     }
     __syncthreads();
-    // write the bands: band (n, th) is rows th*M .. th*M+M-1 of plane (n, k)
-    const int per_band = M * g.Wout;
-    const int total = nbl * per_band;
-    for (int q = tid; q < total; q += 256) {
-        const int bl = q / per_band;
-        const int rem = q - bl * per_band;
-        const int i = rem / g.Wout, j = rem - i * g.Wout;
+    // copy runs: the bands of one image are consecutive rows of plane (n, k)
+    int bl = 0;
+    while (bl < nbl) {
         const int band = band0 + bl;
         const int n = band / g.Th, th = band - n * g.Th;
-        const int oi = th * M + i;
-        if (oi < g.Hout)
-            y[(((size_t)n * g.K + k) * g.Hout + oi) * g.Wout + j] = lds[(bl * M + i) * row_w + j];
+        const int last = min(nbl, bl + (g.Th - th));          // bands of image n in this block
+        const int row_first = th * M;
+        const int row_end = min(g.Hout, (th + (last - bl)) * M);
+        const int len = (row_end - row_first) * g.Wout;
+        const float* src = lds + bl * M * g.Wout;
+        float* dst = y + (((size_t)n * g.K + k) * g.Hout + row_first) * g.Wout;
+        for (int q = tid; q < len; q += 256) dst[q] = src[q];
+        bl = last;
     }
 }
 
@@ -335,6 +427,18 @@ __global__ __launch_bounds__(256) void channel_absmax_kernel(const float* __rest
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+static NzMasks pack_masks(const Plan& p) {
+    NzMasks z{};
+    const int A = p.L.alpha, m = p.L.m, r = p.L.r;
+    for (int q = 0; q < m * A; ++q)
+        if (p.AT[q] != 0.0f) z.at[q >> 6] |= 1ull << (q & 63);
+    for (int q = 0; q < A * r; ++q)
+        if (p.G[q] != 0.0f) z.g[q >> 6] |= 1ull << (q & 63);
+    for (int q = 0; q < A * A; ++q)
+        if (p.BT[q] != 0.0f) z.bt[q >> 6] |= 1ull << (q & 63);
+    return z;
+}
+
 template <int M, int R>
 static Mats<M, R> pack_mats(const Plan& p) {
     constexpr int A = M + R - 1;
@@ -357,32 +461,51 @@ static int filter_impl(const Plan& p, const float* w, const float* x_absmax, voi
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const Mats<M, R> mt = pack_mats<M, R>(p);
-    int32_t* scales = reinterpret_cast<int32_t*>(static_cast<char*>(U) + L.scale_offset);
+    const NzMasks nzm = pack_masks(p);
+    RowExps ex{};
+    for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
+    char* Ub = static_cast<char*>(U);
+    int32_t* s_tab = reinterpret_cast<int32_t*>(Ub + L.scale_offset);
+    int32_t* t_tab = reinterpret_cast<int32_t*>(Ub + L.chan_offset);
+    float* part = reinterpret_cast<float*>(Ub + L.chan_offset + round_up((size_t)L.C_pad * 4, 256));
+    const int kchunks = (L.K + kKChunk - 1) / kKChunk;
     if (L.dtype != WG_F32) {
-        RowExps ex{};
-        for (int i = 0; i < L.alpha; ++i) {
-            ex.eB[i] = p.eB[i];
-            ex.eG[i] = p.eG[i];
-        }
-        hipLaunchKernelGGL(filter_scales_kernel, dim3(L.C_pad), dim3(256), 0, s, w, x_absmax, scales,
-                           ex, L.alpha, L.K, L.C, L.C_pad, L.r * L.r);
-        int st = last_launch("filter_scales_kernel");
+        hipLaunchKernelGGL((filter_absmax_kernel<R * R>), dim3((unsigned)((L.C_pad + 63) / 64), (unsigned)kchunks),
+                           dim3(256), 0, s, w, part, L.K, L.C, L.C_pad);
+        int st = last_launch("filter_absmax_kernel");
+        if (st != WG_OK) return st;
+        hipLaunchKernelGGL(channel_exponent_kernel, dim3((unsigned)((L.C_pad + 255) / 256)), dim3(256), 0, s,
+                           part, x_absmax, s_tab, t_tab, ex, L.alpha, L.C, L.C_pad, kchunks);
+        st = last_launch("channel_exponent_kernel");
         if (st != WG_OK) return st;
     }
-    const long total = (long)L.K_pad * L.C_pad;
+    const long total = (long)L.alpha * L.K_pad * L.C_pad;
     const dim3 grid((unsigned)((total + 255) / 256));
     switch (L.dtype) {
         case WG_F32:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, w, U, scales, mt, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, w, U, t_tab, mt, nzm, ex, g);
             break;
         case WG_F16:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16>), grid, dim3(256), 0, s, w, U, scales, mt, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16>), grid, dim3(256), 0, s, w, U, t_tab, mt, nzm, ex, g);
             break;
         default:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16>), grid, dim3(256), 0, s, w, U, scales, mt, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16>), grid, dim3(256), 0, s, w, U, t_tab, mt, nzm, ex, g);
             break;
     }
     return last_launch("filter_transform_kernel");
+}
+
+// Raise a kernel's dynamic LDS limit above 64 KB (gfx950 has 160 KB per CU);
+// done once per kernel and size.
+template <typename F>
+static void allow_lds(F kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::set<std::pair<const void*, size_t>> done;
+    if (bytes <= 65536) return;
+    const void* key = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.insert({key, bytes}).second)
+        (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 template <int M, int R>
@@ -391,29 +514,39 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const Mats<M, R> mt = pack_mats<M, R>(p);
-    // tiles per block: as many of the tile row as fit 64 KB of LDS
-    const int max_w = (16384 / (kInCh * A)) - 1;            // floats per staged row
-    int twb = (max_w - (R - 1)) / M;
-    if (twb < 1) twb = 1;
-    if (twb > L.Tw) twb = L.Tw;
-    const int row_w = twb * M + R - 1;
-    int ch_stride = A * row_w;
-    if ((ch_stride & 1) == 0) ch_stride += 1;                // odd stride: no LDS bank conflicts
-    const size_t lds_bytes = (size_t)kInCh * ch_stride * sizeof(float);
+    const NzMasks nzm = pack_masks(p);
+    RowExps ex{};
+    for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
+    // at most 8 tiles of a tile row per block, split evenly, and at most
+    // 128 KB of staged rows
+    int nsplit = (L.Tw + 7) / 8, twb = 0, row_w = 0, ch_stride = 0;
+    size_t lds_bytes = 0;
+    for (;; ++nsplit) {
+        twb = (L.Tw + nsplit - 1) / nsplit;
+        row_w = twb * M + R - 1;
+        ch_stride = A * row_w;
+        if ((ch_stride & 1) == 0) ch_stride += 1;            // odd stride: no LDS bank conflicts
+        lds_bytes = (size_t)kInCh * ch_stride * sizeof(float);
+        if (lds_bytes <= 128 * 1024 || twb == 1) break;
+    }
+    if (lds_bytes > 128 * 1024) return fail(WG_EUNSUPPORTED, "input transform: tile too large for LDS");
     const int n_twb = (L.Tw + twb - 1) / twb;
-    const dim3 grid((unsigned)((long)L.N * L.Th * n_twb), (unsigned)((L.C_pad + kInCh - 1) / kInCh));
-    const int32_t* scales =
-        reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.scale_offset);
+    const dim3 grid((unsigned)((long)L.N * L.Th * n_twb * ((L.C_pad + kInCh - 1) / kInCh)));
+    const dim3 block((unsigned)((kInCh * twb + 63) / 64 * 64));
+    const int32_t* t_tab = reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.chan_offset);
     void* V = static_cast<char*>(ws) + L.v_offset;
     switch (L.dtype) {
         case WG_F32:
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kF32>), grid, dim3(256), lds_bytes, s, x, V, scales, mt, g, twb, n_twb, row_w, ch_stride);
+            allow_lds(input_transform_kernel<M, R, kF32>, lds_bytes);
+            hipLaunchKernelGGL((input_transform_kernel<M, R, kF32>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride);
             break;
         case WG_F16:
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kF16>), grid, dim3(256), lds_bytes, s, x, V, scales, mt, g, twb, n_twb, row_w, ch_stride);
+            allow_lds(input_transform_kernel<M, R, kF16>, lds_bytes);
+            hipLaunchKernelGGL((input_transform_kernel<M, R, kF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride);
             break;
         default:
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kBF16>), grid, dim3(256), lds_bytes, s, x, V, scales, mt, g, twb, n_twb, row_w, ch_stride);
+            allow_lds(input_transform_kernel<M, R, kBF16>, lds_bytes);
+            hipLaunchKernelGGL((input_transform_kernel<M, R, kBF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride);
             break;
     }
     return last_launch("input_transform_kernel");
@@ -424,16 +557,16 @@ static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const Mats<M, R> mt = pack_mats<M, R>(p);
+    const NzMasks nzm = pack_masks(p);
     int nb = 256 / L.Tw;
     if (nb < 1) nb = 1;
-    const size_t row_w = (size_t)L.Tw * M;
-    while (nb > 1 && (size_t)nb * M * row_w * sizeof(float) > 65536) --nb;
-    const size_t lds_bytes = (size_t)nb * M * row_w * sizeof(float);
+    while (nb > 1 && (size_t)nb * M * L.Wout * sizeof(float) > 65536) --nb;
+    const size_t lds_bytes = (size_t)nb * M * L.Wout * sizeof(float);
     if (lds_bytes > 65536) return fail(WG_EUNSUPPORTED, "output transform: output rows too wide");
     const int nbands = L.N * L.Th;
     const dim3 grid((unsigned)((nbands + nb - 1) / nb), (unsigned)L.K);
     const float* Mbuf = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.m_offset);
-    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(256), lds_bytes, s, Mbuf, y, mt, g, nb);
+    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(256), lds_bytes, s, Mbuf, y, mt, nzm, g, nb, (unsigned)((size_t)L.K_pad * L.P_pad));
     return last_launch("output_transform_kernel");
 }
 

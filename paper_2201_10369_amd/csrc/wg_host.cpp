@@ -175,6 +175,7 @@ int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, in
         for (int k = 0; k < r; ++k) ng += std::fabs((double)plan->G[i * r + k]);
         plan->eB[i] = binary_exponent(nb);
         plan->eG[i] = binary_exponent(ng);
+        plan->dB[i] = plan->eB[i] - plan->eG[i];
     }
 
     // GEMM tiling: 128 x 128 (K x P) blocks when the layer is wide enough,
@@ -196,11 +197,23 @@ int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, in
     L.C_pad = (int)round_up(C, plan->gemm_bk);
     L.dtype = dtype;
     L.elem_bytes = dtype == WG_F32 ? 4 : 2;
+    // kernels address one plane of U', V' and M with 32-bit element offsets
+    const unsigned long long lim = 1ull << 32;
+    if ((unsigned long long)L.P_pad * L.C_pad >= lim || (unsigned long long)L.K_pad * L.P_pad >= lim ||
+        (unsigned long long)L.K_pad * L.C_pad >= lim) {
+        delete plan;
+        return fail(WG_EUNSUPPORTED, "wg_plan_create: a transformed plane exceeds 2^32 elements");
+    }
     const size_t E = (size_t)alpha * alpha;
     const size_t ubytes = E * L.K_pad * L.C_pad * L.elem_bytes;
     L.scale_offset = round_up(ubytes, 256);
-    L.filter_bytes = dtype == WG_F32 ? round_up(ubytes, 256)
-                                     : round_up(L.scale_offset + E * L.C_pad * sizeof(int32_t), 256);
+    L.chan_offset = round_up(L.scale_offset + E * L.C_pad * sizeof(int32_t), 256);
+    // scratch after the per-channel table: partial maxima of |w| per 8 filters
+    const size_t kchunks = (size_t)(K + 7) / 8;
+    L.filter_bytes = dtype == WG_F32
+                         ? round_up(ubytes, 256)
+                         : round_up(L.chan_offset + L.C_pad * sizeof(int32_t) + 256 +
+                                        kchunks * L.C_pad * sizeof(float), 256);
     L.v_offset = 0;
     L.m_offset = round_up(E * L.P_pad * L.C_pad * L.elem_bytes, 256);
     L.workspace_bytes = round_up(L.m_offset + E * L.K_pad * L.P_pad * sizeof(float), 256);

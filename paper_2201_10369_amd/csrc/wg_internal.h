@@ -25,6 +25,7 @@ struct Plan {
     // binary exponents of the float64 row L1 norms of B^T and G
     int eB[kMaxAlpha];
     int eG[kMaxAlpha];
+    int dB[kMaxAlpha];                 // eB - eG
     // GEMM tiling chosen at plan creation
     int gemm_bm, gemm_bn, gemm_bk;
 };

@@ -40,7 +40,7 @@ class WGError(RuntimeError):
 class Layout(ctypes.Structure):
     _fields_ = [(n, c_int) for n in ("alpha", "m", "r", "pad", "N", "C", "K", "H", "W", "Hout", "Wout",
                                      "Th", "Tw", "P", "P_pad", "K_pad", "C_pad", "dtype", "elem_bytes")] + \
-               [(n, c_size_t) for n in ("scale_offset", "filter_bytes", "v_offset", "m_offset",
+               [(n, c_size_t) for n in ("scale_offset", "chan_offset", "filter_bytes", "v_offset", "m_offset",
                                         "workspace_bytes")]
 
     def as_dict(self):
