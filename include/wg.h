@@ -225,6 +225,63 @@ size_t wg_score_workspace_bytes(size_t count);
 int wg_score_error(const float* y, const double* y_ref, size_t count, double* out2,
                    void* ws, size_t ws_bytes, wg_stream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched error sweep (device).  Section 6.1 traces the error of a point
+ * family as a function of c; Section 6.3 scores many combinations.  For each
+ * candidate (c1[i], c2[i]) the family of wg_family_points for
+ * alpha = m + r - 1 is built, its matrices are constructed in float64 on the
+ * device (float64 values whose magnitude is below the rounding noise of their
+ * own computation are set to zero, so exact cancellations give zeros) and
+ * rounded to float32, and float32 Winograd tiles (1D eq. conv_1d or 2D
+ * eq. conv_2d, evaluated as the layer's transforms are) are scored on the
+ * first counts[i] samples of a shared pool against the float64 direct
+ * correlation of each sample.
+ * ---------------------------------------------------------------------- */
+typedef struct wg_sweep wg_sweep;
+
+/* Creates a sweep for F(m, r) (dims = 1) or F(m x m, r x r) (dims = 2) with
+ * alpha = m + r - 1 in 4..10 and r in {3, 5}.
+ * d_pool: device, n_pool x alpha (x alpha) float32 input tiles; g_pool:
+ * device, n_pool x r (x r) float32 filters; both are read by every run and
+ * must stay valid until the sweep is destroyed (the sweep does not copy
+ * them).  max_cand bounds n_cand of every run.  The float64 reference of the
+ * pool is computed on `stream` and waited for before returning.  The sweep
+ * owns device buffers of about max_cand * (1 KB + 8 * n_pool / 64 B) plus
+ * 8 * n_pool * (outputs per sample + 2) bytes.
+ * Errors: WG_EINVAL, WG_EUNSUPPORTED, WG_ENOMEM, WG_EHIP. */
+int wg_sweep_create(wg_sweep** out, int m, int r, int dims, const float* d_pool,
+                    const float* g_pool, int n_pool, int max_cand, wg_stream_t stream);
+int wg_sweep_destroy(wg_sweep* sweep);      /* NULL is accepted */
+
+/* Scores n_cand candidates (1 <= n_cand <= max_cand).  c1, c2: device
+ * float64 arrays (c2 may be NULL: 1.0 for every candidate; ignored for
+ * alpha <= 6); counts: device int32, pool prefix sizes (clamped to
+ * [0, n_pool]).  out: device float64 [n_cand][4] =
+ *   { sum |y - y_ref| (+inf when flagged), sum |y_ref|,
+ *     number of outputs scored, flag (1: c not finite or zero, points
+ *     coincide, |N_i| < 1e-300 or an entry overflows float32) }.
+ * mean absolute error = out[0]/out[2]; relative L1 = out[0]/out[1].
+ * The three launches of a run (construct, persistent evaluation, finalize)
+ * are captured in a hipGraph on the first call with a given argument set
+ * and replayed on later calls with the same arguments; the result is
+ * bitwise reproducible for a given tuning.  Runs on one sweep object must
+ * not overlap. */
+int wg_sweep_run(wg_sweep* sweep, const double* c1, const double* c2, const int* counts,
+                 int n_cand, double* out, wg_stream_t stream);
+
+/* Times the evaluation over a fixed set of launch shapes (block size,
+ * samples per work item, persistent blocks per compute unit) on the given
+ * arguments, keeps the fastest for later runs and synchronises `stream`.
+ * out receives the last result.  wg_sweep_tuning reports the shape in use;
+ * it returns 1 after autotuning, 0 before (default shape). */
+int wg_sweep_autotune(wg_sweep* sweep, const double* c1, const double* c2, const int* counts,
+                      int n_cand, double* out, wg_stream_t stream);
+int wg_sweep_tuning(const wg_sweep* sweep, int* block, int* chunk, int* blocks_per_cu);
+
+/* The float32 matrices the last run built for candidate `cand` (host
+ * outputs, sizes as wg_transforms) and its flag; synchronous. */
+int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, float* BT, int* flag);
+
 #ifdef __cplusplus
 }
 #endif

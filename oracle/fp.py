@@ -10,9 +10,11 @@ What is computed
   Y = A^T[(Gg) (.) (B^T d)] (eq. conv_1d) and the nested 2D form
   Y = A^T[(G g G^T) (.) (B^T d B)] A (eq. conv_2d), evaluated as nested
   matrix products, never as a Kronecker product (Section 7 found that worse).
-  Every inner product is summed in ascending index order and every product
-  and every sum is rounded to float32 separately (no fused multiply-add).
-  A 2D product P X P^T is evaluated as (P X) first, then (P X) P^T.
+  Every inner product is accumulated in ascending index order, each term
+  added with a fused multiply-add (acc <- RN32(m * x + acc), one rounding per
+  term, starting from acc = 0).  A 2D product P X P^T is evaluated as (P X)
+  first, then (P X) P^T.  (The paper does not state the operation order; this
+  is the order every float32 Winograd result here follows.)
 * The convolution layer (eq. conv with the channel sum): the image is cut
   into tiles of m x m outputs; the Hadamard products of the transformed
   filters and inputs are summed over the input channels c in ascending
@@ -56,18 +58,45 @@ def mats_f32(points, m, r, modified=True):
 
 
 # ----------------------------------------------------------------------------
-# Fixed-order float32 matrix application
+# Fused multiply-add and fixed-order float32 matrix application
 # ----------------------------------------------------------------------------
+def fma32(a, b, c):
+    """Correctly rounded float32 a*b + c (a single rounding, ties to even).
+
+    p = a*b is exact in float64.  s = p + c rounds once in float64, and the
+    TwoSum error term e (Knuth) makes p + c = s + e exact.  Rounding s to
+    float32 gives the correctly rounded result unless s lies exactly halfway
+    between two float32 values and e != 0; then the exact value lies on the
+    side of the midpoint that e points to."""
+    scalar = np.ndim(a) == 0 and np.ndim(b) == 0 and np.ndim(c) == 0
+    a64 = np.atleast_1d(np.asarray(a, dtype=F32)).astype(F64)
+    b64 = np.atleast_1d(np.asarray(b, dtype=F32)).astype(F64)
+    c64 = np.atleast_1d(np.asarray(c, dtype=F32)).astype(F64)
+    p = a64 * b64
+    s = p + c64
+    bv = s - p
+    e = (p - (s - bv)) + (c64 - bv)
+    r = s.astype(F32)
+    d = s - r.astype(F64)
+    toward = np.where(d > 0, np.float32(np.inf), np.float32(-np.inf)).astype(F32)
+    nb = np.nextafter(r, toward)
+    with np.errstate(invalid="ignore", over="ignore"):
+        mid = (d != 0) & (s == (r.astype(F64) + nb.astype(F64)) / 2)
+    fix = mid & (e != 0) & (np.sign(e) == np.sign(d))
+    r = np.where(fix, nb, r)
+    return r[0] if scalar else r
+
+
 def apply_left(Mat, X, axis):
-    """Z[..i..] = sum_l Mat[i,l] X[..l..] along `axis`: float32, ascending l,
-    each product and each partial sum rounded separately."""
+    """Z[..i..] = sum_l Mat[i,l] X[..l..] along `axis` in float32: ascending l,
+    acc <- fma(Mat[i,l], X[l], acc) from acc = 0."""
     Mat = np.asarray(Mat, dtype=F32)
     X = np.moveaxis(np.asarray(X, dtype=F32), axis, 0)
     out = np.empty((Mat.shape[0],) + X.shape[1:], dtype=F32)
     for i in range(Mat.shape[0]):
-        acc = Mat[i, 0] * X[0]
-        for l in range(1, Mat.shape[1]):
-            acc = acc + Mat[i, l] * X[l]
+        acc = np.zeros(X.shape[1:], dtype=F32)
+        for l in range(Mat.shape[1]):
+            acc = fma32(Mat[i, l], X[l], acc)
         out[i] = acc
     return np.moveaxis(out, 0, axis)
 

@@ -1,0 +1,618 @@
+// Batched error sweep over point-family parameters on gfx950.
+//
+// For thousands of candidate point sets (the families of Section 5 of
+// arXiv:2201.10369, parameterised by c1 and c2) the sweep builds each set's
+// transform matrices in float64 on the device (Sections 4.1, 4.2), rounds
+// them to float32, evaluates float32 Winograd tiles (1D eq. conv_1d or 2D
+// eq. conv_2d) on the first n_i samples of a shared pool, and sums the L1
+// error against the float64 direct correlation of each sample (Section 6;
+// Section 6.1 sweeps c over a range, Section 6.3 scores many combinations).
+//
+// Launch structure (one hipGraph, replayed):
+//   construct : one thread per candidate, float64 construction -> float32
+//   evaluate  : persistent blocks stride over work items (candidate, chunk
+//               of `chunk` samples); per item a fixed-tree block reduction
+//               writes one float64 partial sum
+//   finalize  : one thread per candidate adds its partials in index order
+// so the result is bitwise reproducible for a given tuning.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "wg_device.h"
+#include "wg_internal.h"
+#include "wg_sweep_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace wg {
+
+constexpr int kMatStride = 256;     // floats per candidate: A^T | G | B^T
+constexpr int kMaskStride = 8;      // uint64 per candidate: at[2] g[1] bt[2]
+
+// ---------------------------------------------------------------------------
+// Family points (same definition as wg_family_points)
+// ---------------------------------------------------------------------------
+__device__ int family_points_dev(int alpha, double c1, double c2, double* p) {
+    const double ic = 1.0 / c1;
+    int n = 0;
+    if (alpha == 4) {
+        p[n++] = -c1; p[n++] = 0.0; p[n++] = c1;
+        return n;
+    }
+    if (alpha == 5) {
+        p[n++] = 0.0; p[n++] = -c1; p[n++] = c1; p[n++] = ic;
+        return n;
+    }
+    p[n++] = -ic; p[n++] = -c1; p[n++] = 0.0; p[n++] = c1; p[n++] = ic;
+    const double id = 1.0 / c2;
+    if (alpha == 7) { p[n++] = c2; }
+    if (alpha == 8) { p[n++] = -c2; p[n++] = c2; }
+    if (alpha == 9) { p[n++] = -id; p[n++] = -c2; p[n++] = c2; }
+    if (alpha == 10) { p[n++] = -id; p[n++] = -c2; p[n++] = c2; p[n++] = id; }
+    return n;
+}
+
+// Coefficients of prod (x - a_j) over the roots, with the coefficients of
+// prod (x + |a_j|) as magnitude bounds; a coefficient no larger than the
+// float64 rounding noise of its own computation is set to zero (the point
+// families are built so that such coefficients cancel exactly).
+template <int A>
+__device__ void product_poly_snapped(const double* roots, int n, double* coef) {
+    double bnd[A + 1];
+    coef[0] = 1.0;
+    bnd[0] = 1.0;
+    for (int i = 1; i <= n; ++i) coef[i] = bnd[i] = 0.0;
+    for (int t = 0; t < n; ++t) {
+        const double a = roots[t], aa = fabs(roots[t]);
+        for (int i = t + 1; i >= 1; --i) {
+            coef[i] = coef[i - 1] - a * coef[i];
+            bnd[i] = bnd[i - 1] + aa * bnd[i];
+        }
+        coef[0] = -a * coef[0];
+        bnd[0] = aa * bnd[0];
+    }
+    const double tol = 4.0 * (n + 1) * 1.1102230246251565e-16;   // 4 (n+1) 2^-53
+    for (int i = 0; i <= n; ++i)
+        if (fabs(coef[i]) <= tol * bnd[i]) coef[i] = 0.0;
+}
+
+template <int M, int R>
+__global__ __launch_bounds__(64) void sweep_construct_kernel(const double* __restrict__ c1,
+                                                             const double* __restrict__ c2, int n_cand,
+                                                             float* __restrict__ mats,
+                                                             uint64_t* __restrict__ masks,
+                                                             int* __restrict__ flags) {
+    constexpr int A = M + R - 1;
+    constexpr int NF = A - 1;
+    const int cand = blockIdx.x * 64 + threadIdx.x;
+    if (cand >= n_cand) return;
+    float* out = mats + (size_t)cand * kMatStride;
+    float* AT = out;
+    float* G = out + M * A;
+    float* BT = out + M * A + A * R;
+    const double x1 = c1[cand], x2 = c2 != nullptr ? c2[cand] : 1.0;
+    int flag = 0;
+    if (!isfinite(x1) || x1 == 0.0 || (A > 6 && (!isfinite(x2) || x2 == 0.0))) flag = 1;
+    double pts[NF];
+    if (!flag) family_points_dev(A, x1, x2, pts);
+    double norm[NF];
+    if (!flag) {
+        for (int i = 0; i < NF && !flag; ++i) {
+            double prod = 1.0;
+            for (int j = 0; j < NF; ++j)
+                if (j != i) prod *= (pts[i] - pts[j]);
+            if (!(fabs(prod) >= 1e-300) || !isfinite(prod)) flag = 1;
+            norm[i] = prod;
+        }
+    }
+    for (int q = 0; q < M * A + A * R + A * A; ++q) out[q] = 0.0f;
+    uint64_t mk[kMaskStride] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (!flag) {
+        double others[NF], coef[A + 1];
+        for (int i = 0; i < NF; ++i) {
+            const double a = pts[i];
+            double pw = 1.0;
+            for (int j = 0; j < M; ++j) {
+                AT[j * A + i] = (float)pw;
+                pw *= a;
+            }
+            pw = 1.0;
+            for (int k = 0; k < R; ++k) {
+                G[i * R + k] = (float)(pw / norm[i]);
+                pw *= a;
+            }
+            int no = 0;
+            for (int j = 0; j < NF; ++j)
+                if (j != i) others[no++] = pts[j];
+            product_poly_snapped<A>(others, no, coef);
+            for (int l = 0; l <= no; ++l) BT[i * A + l] = (float)coef[l];
+        }
+        AT[(M - 1) * A + (A - 1)] = 1.0f;
+        G[(A - 1) * R + (R - 1)] = 1.0f;
+        product_poly_snapped<A>(pts, NF, coef);
+        for (int l = 0; l <= NF; ++l) BT[(A - 1) * A + l] = (float)coef[l];
+        for (int q = 0; q < M * A + A * R + A * A; ++q)
+            if (!isfinite(out[q])) flag = 1;
+        for (int q = 0; q < M * A; ++q)
+            if (AT[q] != 0.0f) mk[0 + (q >> 6)] |= 1ull << (q & 63);
+        for (int q = 0; q < A * R; ++q)
+            if (G[q] != 0.0f) mk[2] |= 1ull << q;
+        for (int q = 0; q < A * A; ++q)
+            if (BT[q] != 0.0f) mk[3 + (q >> 6)] |= 1ull << (q & 63);
+    }
+    for (int q = 0; q < kMaskStride; ++q) masks[(size_t)cand * kMaskStride + q] = mk[q];
+    flags[cand] = flag;
+}
+
+// ---------------------------------------------------------------------------
+// float64 reference of the pool (once per sweep object)
+// ---------------------------------------------------------------------------
+template <int M, int R, int DIMS>
+__global__ __launch_bounds__(256) void sweep_reference_kernel(const float* __restrict__ d_pool,
+                                                              const float* __restrict__ g_pool, int n_pool,
+                                                              double* __restrict__ yref,
+                                                              double* __restrict__ ref_abs) {
+    constexpr int A = M + R - 1;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n_pool) return;
+    double tot = 0.0;
+    if (DIMS == 1) {
+        const float* d = d_pool + (size_t)s * A;
+        const float* g = g_pool + (size_t)s * R;
+        for (int j = 0; j < M; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < R; ++k) acc = fma((double)d[j + k], (double)g[k], acc);
+            yref[(size_t)s * M + j] = acc;
+            tot += fabs(acc);
+        }
+    } else {
+        const float* d = d_pool + (size_t)s * A * A;
+        const float* g = g_pool + (size_t)s * R * R;
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                double acc = 0.0;
+                for (int u = 0; u < R; ++u)
+                    for (int v = 0; v < R; ++v) acc = fma((double)d[(i + u) * A + j + v], (double)g[u * R + v], acc);
+                yref[(size_t)s * M * M + i * M + j] = acc;
+                tot += fabs(acc);
+            }
+    }
+    ref_abs[s] = tot;
+}
+
+__global__ void sweep_prefix_kernel(const double* __restrict__ ref_abs, int n_pool, double* __restrict__ prefix) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double acc = 0.0;
+    prefix[0] = 0.0;
+    for (int s = 0; s < n_pool; ++s) {
+        acc += ref_abs[s];
+        prefix[s + 1] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation.  Each thread evaluates whole tiles; the matrices of the block's
+// current candidate sit in LDS, their nonzero masks in scalar registers.
+// ---------------------------------------------------------------------------
+template <int M, int R, int DIMS>
+__device__ __forceinline__ double tile_error(const float* __restrict__ d_pool, const float* __restrict__ g_pool,
+                                             const double* __restrict__ yref, int s, const float* sAT,
+                                             const float* sG, const float* sBT, uint64_t mat0, uint64_t mat1,
+                                             uint64_t mg, uint64_t mbt0, uint64_t mbt1) {
+    constexpr int A = M + R - 1;
+    const uint64_t mat[2] = {mat0, mat1};
+    const uint64_t mbt[2] = {mbt0, mbt1};
+    const uint64_t mgg[1] = {mg};
+    double err = 0.0;
+    if (DIMS == 1) {
+        const float* d = d_pool + (size_t)s * A;
+        const float* g = g_pool + (size_t)s * R;
+        float gv[R], dv[A];
+#pragma unroll
+        for (int k = 0; k < R; ++k) gv[k] = g[k];
+#pragma unroll
+        for (int l = 0; l < A; ++l) dv[l] = d[l];
+        float mh[A];
+#pragma unroll
+        for (int i = 0; i < A; ++i) {
+            float u = 0.0f, v = 0.0f;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (nz(mgg, i * R + k)) u = __builtin_fmaf(sG[i * R + k], gv[k], u);
+#pragma unroll
+            for (int l = 0; l < A; ++l)
+                if (nz(mbt, i * A + l)) v = __builtin_fmaf(sBT[i * A + l], dv[l], v);
+            mh[i] = u * v;
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            float y = 0.0f;
+#pragma unroll
+            for (int i = 0; i < A; ++i)
+                if (nz(mat, j * A + i)) y = __builtin_fmaf(sAT[j * A + i], mh[i], y);
+            err += fabs((double)y - yref[(size_t)s * M + j]);
+        }
+        return err;
+    }
+    const float* d = d_pool + (size_t)s * A * A;
+    const float* g = g_pool + (size_t)s * R * R;
+    float gg[R][R];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+        for (int v = 0; v < R; ++v) gg[u][v] = g[u * R + v];
+    // T1 = B^T d, streaming the rows of d
+    float t1[A][A];
+#pragma unroll
+    for (int i = 0; i < A; ++i)
+#pragma unroll
+        for (int b = 0; b < A; ++b) t1[i][b] = 0.0f;
+#pragma unroll
+    for (int l = 0; l < A; ++l) {
+        float drow[A];
+#pragma unroll
+        for (int b = 0; b < A; ++b) drow[b] = d[l * A + b];
+#pragma unroll
+        for (int i = 0; i < A; ++i)
+            if (nz(mbt, i * A + l)) {
+                const float bv = sBT[i * A + l];
+#pragma unroll
+                for (int b = 0; b < A; ++b) t1[i][b] = __builtin_fmaf(bv, drow[b], t1[i][b]);
+            }
+    }
+    // row by row: U row i, V row i, Hadamard, accumulate Z = A^T Mh
+    float z[M][A];
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int j = 0; j < A; ++j) z[k][j] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+        float p1[R];
+#pragma unroll
+        for (int v = 0; v < R; ++v) p1[v] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (nz(mgg, i * R + u)) {
+#pragma unroll
+                for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(sG[i * R + u], gg[u][v], p1[v]);
+            }
+        float mh[A];
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            float uij = 0.0f, vij = 0.0f;
+#pragma unroll
+            for (int v = 0; v < R; ++v)
+                if (nz(mgg, j * R + v)) uij = __builtin_fmaf(sG[j * R + v], p1[v], uij);
+#pragma unroll
+            for (int l = 0; l < A; ++l)
+                if (nz(mbt, j * A + l)) vij = __builtin_fmaf(sBT[j * A + l], t1[i][l], vij);
+            mh[j] = uij * vij;
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+            if (nz(mat, k * A + i)) {
+                const float av = sAT[k * A + i];
+#pragma unroll
+                for (int j = 0; j < A; ++j) z[k][j] = __builtin_fmaf(av, mh[j], z[k][j]);
+            }
+    }
+    const double* yr = yref + (size_t)s * M * M;
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            float y = 0.0f;
+#pragma unroll
+            for (int j = 0; j < A; ++j)
+                if (nz(mat, q * A + j)) y = __builtin_fmaf(sAT[q * A + j], z[k][j], y);
+            err += fabs((double)y - yr[k * M + q]);
+        }
+    return err;
+}
+
+template <int M, int R, int DIMS>
+__global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict__ d_pool,
+                                                         const float* __restrict__ g_pool,
+                                                         const double* __restrict__ yref,
+                                                         const float* __restrict__ mats,
+                                                         const uint64_t* __restrict__ masks,
+                                                         const int* __restrict__ flags,
+                                                         const int* __restrict__ counts, int n_cand, int n_pool,
+                                                         int ipc, int chunk, double* __restrict__ partial) {
+    constexpr int A = M + R - 1;
+    constexpr int NM = M * A + A * R + A * A;
+    __shared__ float sm[NM];
+    __shared__ double red[256];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const long items = (long)n_cand * ipc;
+    for (long item = blockIdx.x; item < items; item += gridDim.x) {
+        const int cand = (int)(item / ipc), ch = (int)(item - (long)cand * ipc);
+        int n = counts[cand];
+        n = n < 0 ? 0 : (n > n_pool ? n_pool : n);
+        const int start = ch * chunk;
+        const bool live = flags[cand] == 0 && start < n;      // uniform over the block
+        if (!live) {
+            if (tid == 0) partial[item] = 0.0;
+            continue;
+        }
+        __syncthreads();                                      // previous item done with sm
+        for (int q = tid; q < NM; q += nthr) sm[q] = mats[(size_t)cand * kMatStride + q];
+        const uint64_t* mk = masks + (size_t)cand * kMaskStride;
+        const uint64_t mat0 = mk[0], mat1 = mk[1], mg = mk[2], mbt0 = mk[3], mbt1 = mk[4];
+        __syncthreads();
+        const int stop = min(n, start + chunk);
+        double err = 0.0;
+        for (int s = start + tid; s < stop; s += nthr)
+            err += tile_error<M, R, DIMS>(d_pool, g_pool, yref, s, sm, sm + M * A, sm + M * A + A * R, mat0,
+                                          mat1, mg, mbt0, mbt1);
+        red[tid] = err;
+        __syncthreads();
+        for (int st = nthr / 2; st > 0; st >>= 1) {
+            if (tid < st) red[tid] += red[tid + st];
+            __syncthreads();
+        }
+        if (tid == 0) partial[item] = red[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void sweep_finalize_kernel(const double* __restrict__ partial,
+                                                             const double* __restrict__ prefix,
+                                                             const int* __restrict__ flags,
+                                                             const int* __restrict__ counts, int n_cand,
+                                                             int n_pool, int ipc, int outs_per_sample,
+                                                             double* __restrict__ out) {
+    const int cand = blockIdx.x * 256 + threadIdx.x;
+    if (cand >= n_cand) return;
+    int n = counts[cand];
+    n = n < 0 ? 0 : (n > n_pool ? n_pool : n);
+    double e = 0.0;
+    for (int q = 0; q < ipc; ++q) e += partial[(size_t)cand * ipc + q];
+    const int fl = flags[cand];
+    out[(size_t)cand * 4 + 0] = fl ? INFINITY : e;
+    out[(size_t)cand * 4 + 1] = prefix[n];
+    out[(size_t)cand * 4 + 2] = (double)n * outs_per_sample;
+    out[(size_t)cand * 4 + 3] = (double)fl;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static int hipc(hipError_t e, const char* what) { return hip_check((int)e, what); }
+
+template <int M, int R, int DIMS>
+struct SweepOps {
+    static void reference(const Sweep& S, hipStream_t st) {
+        hipLaunchKernelGGL((sweep_reference_kernel<M, R, DIMS>), dim3((S.n_pool + 255) / 256), dim3(256), 0, st,
+                           S.d_pool, S.g_pool, S.n_pool, S.yref, S.ref_abs);
+        hipLaunchKernelGGL(sweep_prefix_kernel, dim3(1), dim3(64), 0, st, S.ref_abs, S.n_pool, S.prefix);
+    }
+    static void run(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st) {
+        const int ipc = (S.n_pool + t.chunk - 1) / t.chunk;
+        hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + 63) / 64), dim3(64), 0, st, a.c1,
+                           a.c2, a.n_cand, S.mats, S.masks, S.flags);
+        const long items = (long)a.n_cand * ipc;
+        long grid = (long)S.n_cu * t.blocks_per_cu;
+        if (grid > items) grid = items;
+        if (grid < 1) grid = 1;
+        hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS>), dim3((unsigned)grid), dim3(t.block), 0, st, S.d_pool,
+                           S.g_pool, S.yref, S.mats, S.masks, S.flags, a.counts, a.n_cand, S.n_pool, ipc, t.chunk,
+                           S.partial);
+        hipLaunchKernelGGL(sweep_finalize_kernel, dim3((a.n_cand + 255) / 256), dim3(256), 0, st, S.partial,
+                           S.prefix, S.flags, a.counts, a.n_cand, S.n_pool, ipc, DIMS == 1 ? M : M * M, a.out);
+    }
+};
+
+#define WG_SWEEP_SIZES(X) \
+    X(2, 3) X(3, 3) X(4, 3) X(5, 3) X(6, 3) X(7, 3) X(8, 3) X(2, 5) X(3, 5) X(4, 5) X(5, 5) X(6, 5)
+
+static bool sweep_supported(int m, int r) {
+    switch (m * 16 + r) {
+#define WG_SW_CASE(MM, RR) case MM * 16 + RR: return true;
+        WG_SWEEP_SIZES(WG_SW_CASE)
+#undef WG_SW_CASE
+        default: return false;
+    }
+}
+
+static void dispatch_reference(const Sweep& S, hipStream_t st) {
+    switch (S.m * 16 + S.r) {
+#define WG_SW_CASE(MM, RR)                                                              \
+    case MM * 16 + RR:                                                                  \
+        if (S.dims == 1) SweepOps<MM, RR, 1>::reference(S, st);                         \
+        else SweepOps<MM, RR, 2>::reference(S, st);                                      \
+        return;
+        WG_SWEEP_SIZES(WG_SW_CASE)
+#undef WG_SW_CASE
+        default: return;
+    }
+}
+
+static void dispatch_run(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st) {
+    switch (S.m * 16 + S.r) {
+#define WG_SW_CASE(MM, RR)                                                              \
+    case MM * 16 + RR:                                                                  \
+        if (S.dims == 1) SweepOps<MM, RR, 1>::run(S, a, t, st);                         \
+        else SweepOps<MM, RR, 2>::run(S, a, t, st);                                      \
+        return;
+        WG_SWEEP_SIZES(WG_SW_CASE)
+#undef WG_SW_CASE
+        default: return;
+    }
+}
+
+static const SweepTune kCandidates[] = {
+    {64, 64, 8}, {64, 128, 8}, {128, 128, 4}, {128, 256, 4}, {256, 256, 2},
+    {256, 512, 2}, {128, 128, 8}, {256, 256, 4}, {64, 256, 8}, {128, 512, 4},
+};
+
+static void release(Sweep* S) {
+    if (!S) return;
+    if (S->exec) (void)hipGraphExecDestroy(S->exec);
+    if (S->graph) (void)hipGraphDestroy(S->graph);
+    if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+    void* bufs[] = {S->yref, S->ref_abs, S->prefix, S->mats, S->masks, S->flags, S->partial};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete S;
+}
+
+}  // namespace wg
+
+using namespace wg;
+
+extern "C" {
+
+int wg_sweep_create(wg_sweep** out, int m, int r, int dims, const float* d_pool, const float* g_pool,
+                    int n_pool, int max_cand, wg_stream_t stream) {
+    if (!out || !d_pool || !g_pool) return fail(WG_EINVAL, "wg_sweep_create: null pointer");
+    if (dims != 1 && dims != 2) return fail(WG_EINVAL, "wg_sweep_create: dims must be 1 or 2");
+    if (n_pool <= 0 || max_cand <= 0) return fail(WG_EINVAL, "wg_sweep_create: sizes must be positive");
+    if (!sweep_supported(m, r))
+        return fail(WG_EUNSUPPORTED, "wg_sweep_create: F(" + std::to_string(m) + "," + std::to_string(r) +
+                                         ") has no point family here (alpha = m+r-1 must be 4..10, r 3 or 5)");
+    Sweep* S = new (std::nothrow) Sweep();
+    if (!S) return fail(WG_ENOMEM, "wg_sweep_create: out of host memory");
+    S->m = m; S->r = r; S->dims = dims; S->alpha = m + r - 1;
+    S->n_pool = n_pool; S->max_cand = max_cand;
+    S->d_pool = d_pool; S->g_pool = g_pool;
+    int dev = 0;
+    int st = hipc(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    if (st == WG_OK) st = hipc(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (st != WG_OK) { release(S); return st; }
+    S->n_cu = prop.multiProcessorCount;
+    const int outs = dims == 1 ? m : m * m;
+    const size_t max_ipc = (size_t)(n_pool + 63) / 64;
+    struct { void** p; size_t bytes; } allocs[] = {
+        {(void**)&S->yref, sizeof(double) * (size_t)n_pool * outs},
+        {(void**)&S->ref_abs, sizeof(double) * (size_t)n_pool},
+        {(void**)&S->prefix, sizeof(double) * (size_t)(n_pool + 1)},
+        {(void**)&S->mats, sizeof(float) * (size_t)max_cand * kMatStride},
+        {(void**)&S->masks, sizeof(uint64_t) * (size_t)max_cand * kMaskStride},
+        {(void**)&S->flags, sizeof(int) * (size_t)max_cand},
+        {(void**)&S->partial, sizeof(double) * (size_t)max_cand * max_ipc},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            release(S);
+            return fail(WG_ENOMEM, "wg_sweep_create: device allocation failed");
+        }
+    }
+    st = hipc(hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (st != WG_OK) { release(S); return st; }
+    dispatch_reference(*S, static_cast<hipStream_t>(stream));
+    st = hipc(hipGetLastError(), "sweep reference");
+    if (st == WG_OK) st = hipc(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "sweep reference");
+    if (st != WG_OK) { release(S); return st; }
+    S->tune = SweepTune{128, 128, 4};
+    *out = reinterpret_cast<wg_sweep*>(S);
+    return WG_OK;
+}
+
+int wg_sweep_destroy(wg_sweep* sweep) {
+    release(reinterpret_cast<Sweep*>(sweep));
+    return WG_OK;
+}
+
+static int check_args(const Sweep& S, const double* c1, const int* counts, int n_cand, double* out) {
+    if (!c1 || !counts || !out) return fail(WG_EINVAL, "wg_sweep_run: null pointer");
+    if (n_cand <= 0 || n_cand > S.max_cand)
+        return fail(WG_EINVAL, "wg_sweep_run: n_cand must be 1.." + std::to_string(S.max_cand));
+    return WG_OK;
+}
+
+int wg_sweep_autotune(wg_sweep* sweep, const double* c1, const double* c2, const int* counts, int n_cand,
+                      double* out, wg_stream_t stream) {
+    if (!sweep) return fail(WG_EINVAL, "wg_sweep_autotune: null sweep");
+    Sweep& S = *reinterpret_cast<Sweep*>(sweep);
+    int st = check_args(S, c1, counts, n_cand, out);
+    if (st != WG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const SweepArgs a{c1, c2, counts, n_cand, out};
+    hipEvent_t e0, e1;
+    if ((st = hipc(hipEventCreate(&e0), "hipEventCreate")) != WG_OK) return st;
+    if ((st = hipc(hipEventCreate(&e1), "hipEventCreate")) != WG_OK) { (void)hipEventDestroy(e0); return st; }
+    float best = 1e30f;
+    SweepTune best_t = S.tune;
+    for (const SweepTune& t : kCandidates) {
+        if ((size_t)((S.n_pool + t.chunk - 1) / t.chunk) > (size_t)(S.n_pool + 63) / 64) continue;
+        dispatch_run(S, a, t, s);                         // warm
+        (void)hipEventRecord(e0, s);
+        dispatch_run(S, a, t, s);
+        dispatch_run(S, a, t, s);
+        (void)hipEventRecord(e1, s);
+        if ((st = hipc(hipEventSynchronize(e1), "sweep autotune")) != WG_OK) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != WG_OK) return st;
+    S.tune = best_t;
+    S.tuned = true;
+    if (S.exec) { (void)hipGraphExecDestroy(S.exec); S.exec = nullptr; }
+    if (S.graph) { (void)hipGraphDestroy(S.graph); S.graph = nullptr; }
+    return WG_OK;
+}
+
+int wg_sweep_tuning(const wg_sweep* sweep, int* block, int* chunk, int* blocks_per_cu) {
+    if (!sweep) return fail(WG_EINVAL, "wg_sweep_tuning: null sweep");
+    const Sweep& S = *reinterpret_cast<const Sweep*>(sweep);
+    if (block) *block = S.tune.block;
+    if (chunk) *chunk = S.tune.chunk;
+    if (blocks_per_cu) *blocks_per_cu = S.tune.blocks_per_cu;
+    return S.tuned ? 1 : 0;
+}
+
+int wg_sweep_run(wg_sweep* sweep, const double* c1, const double* c2, const int* counts, int n_cand,
+                 double* out, wg_stream_t stream) {
+    if (!sweep) return fail(WG_EINVAL, "wg_sweep_run: null sweep");
+    Sweep& S = *reinterpret_cast<Sweep*>(sweep);
+    int st = check_args(S, c1, counts, n_cand, out);
+    if (st != WG_OK) return st;
+    const SweepArgs a{c1, c2, counts, n_cand, out};
+    if (!S.exec || !(a == S.captured)) {
+        if (S.exec) { (void)hipGraphExecDestroy(S.exec); S.exec = nullptr; }
+        if (S.graph) { (void)hipGraphDestroy(S.graph); S.graph = nullptr; }
+        st = hipc(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        if (st != WG_OK) return st;
+        dispatch_run(S, a, S.tune, S.cap_stream);
+        const int launch = hipc(hipGetLastError(), "sweep capture");
+        st = hipc(hipStreamEndCapture(S.cap_stream, &S.graph), "hipStreamEndCapture");
+        if (launch != WG_OK) return launch;
+        if (st != WG_OK) return st;
+        st = hipc(hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        if (st != WG_OK) return st;
+        S.captured = a;
+    }
+    return hipc(hipGraphLaunch(S.exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, float* BT, int* flag) {
+    if (!sweep || !AT || !G || !BT || !flag) return fail(WG_EINVAL, "wg_sweep_matrices: null pointer");
+    const Sweep& S = *reinterpret_cast<const Sweep*>(sweep);
+    if (cand < 0 || cand >= S.max_cand) return fail(WG_EINVAL, "wg_sweep_matrices: candidate out of range");
+    const int m = S.m, r = S.r, A = S.alpha;
+    float buf[kMatStride];
+    int st = hipc(hipMemcpy(buf, S.mats + (size_t)cand * kMatStride, sizeof(buf), hipMemcpyDeviceToHost),
+                  "hipMemcpy");
+    if (st == WG_OK) st = hipc(hipMemcpy(flag, S.flags + cand, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (st != WG_OK) return st;
+    std::memcpy(AT, buf, sizeof(float) * m * A);
+    std::memcpy(G, buf + m * A, sizeof(float) * A * r);
+    std::memcpy(BT, buf + m * A + A * r, sizeof(float) * A * A);
+    return WG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// Internal state of a sweep object (see wg_sweep_* in wg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wg {
+
+struct SweepTune {
+    int block;          // threads per block of the evaluation kernel
+    int chunk;          // pool samples per work item
+    int blocks_per_cu;  // persistent blocks per compute unit
+};
+
+struct SweepArgs {
+    const double* c1;
+    const double* c2;
+    const int* counts;
+    int n_cand;
+    double* out;
+    bool operator==(const SweepArgs& o) const {
+        return c1 == o.c1 && c2 == o.c2 && counts == o.counts && n_cand == o.n_cand && out == o.out;
+    }
+};
+
+struct Sweep {
+    int m = 0, r = 0, dims = 0, alpha = 0, n_pool = 0, max_cand = 0, n_cu = 0;
+    const float* d_pool = nullptr;
+    const float* g_pool = nullptr;
+    double* yref = nullptr;      // float64 reference outputs of every pool sample
+    double* ref_abs = nullptr;   // sum |yref| per sample
+    double* prefix = nullptr;    // prefix sums of ref_abs (n_pool + 1)
+    float* mats = nullptr;       // per candidate float32 A^T | G | B^T
+    uint64_t* masks = nullptr;   // per candidate nonzero masks
+    int* flags = nullptr;        // per candidate: 1 = invalid or singular
+    double* partial = nullptr;   // per work item error sums
+    SweepTune tune{128, 128, 4};
+    bool tuned = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SweepArgs captured{};
+};
+
+}  // namespace wg

@@ -69,6 +69,13 @@ _SIGS = {
     "wg_direct_conv_f64": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int,
                                    c_int, c_int, c_void_p]),
     "wg_score_workspace_bytes": (c_size_t, [c_size_t]),
+    "wg_sweep_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_int, c_void_p, c_void_p, c_int, c_int,
+                                c_void_p]),
+    "wg_sweep_destroy": (c_int, [c_void_p]),
+    "wg_sweep_run": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "wg_sweep_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "wg_sweep_tuning": (c_int, [c_void_p, P_int, P_int, P_int]),
+    "wg_sweep_matrices": (c_int, [c_void_p, c_int, P_float, P_float, P_float, P_int]),
     "wg_score_error": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
@@ -324,3 +331,70 @@ def channel_absmax(x, out=None, stream=None):
     _check(lib().wg_channel_absmax(_tptr(x, torch.float32, "x"), N, C, H, W,
                                    _tptr(out, torch.float32, "out"), _stream(stream)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# batched error sweep
+# ----------------------------------------------------------------------------
+class Sweep:
+    """Error sweep of F(m, r) (dims 1) or F(m x m, r x r) (dims 2) over the
+    point family of alpha = m + r - 1, on a pool of (tile, filter) samples."""
+
+    def __init__(self, m, r, dims, d_pool, g_pool, max_cand, stream=None):
+        torch = _torch()
+        self.m, self.r, self.dims = m, r, dims
+        self.alpha = m + r - 1
+        self.n_pool = d_pool.shape[0]
+        self.max_cand = max_cand
+        self._pool = (d_pool, g_pool)                    # kept alive: the sweep reads them
+        h = c_void_p()
+        _check(lib().wg_sweep_create(ctypes.byref(h), m, r, dims, _tptr(d_pool, torch.float32, "d_pool"),
+                                     _tptr(g_pool, torch.float32, "g_pool"), self.n_pool, max_cand,
+                                     _stream(stream)))
+        self._h = h
+        self._args = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.wg_sweep_destroy(h)
+            self._h = None
+
+    def _prep(self, c1, c2, counts, out):
+        torch = _torch()
+        n = c1.numel()
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float64, device=c1.device)
+        # the captured graph holds these pointers: keep the tensors alive
+        self._args = (c1, c2, counts, out)
+        return n, out
+
+    def run(self, c1, c2, counts, out=None, stream=None):
+        torch = _torch()
+        n, out = self._prep(c1, c2, counts, out)
+        _check(lib().wg_sweep_run(self._h, _tptr(c1, torch.float64, "c1"), _tptr(c2, torch.float64, "c2"),
+                                  _tptr(counts, torch.int32, "counts"), n, _tptr(out, torch.float64, "out"),
+                                  _stream(stream)))
+        return out
+
+    def autotune(self, c1, c2, counts, out=None, stream=None):
+        torch = _torch()
+        n, out = self._prep(c1, c2, counts, out)
+        _check(lib().wg_sweep_autotune(self._h, _tptr(c1, torch.float64, "c1"), _tptr(c2, torch.float64, "c2"),
+                                       _tptr(counts, torch.int32, "counts"), n,
+                                       _tptr(out, torch.float64, "out"), _stream(stream)))
+        return out
+
+    def tuning(self):
+        b, c, k = c_int(), c_int(), c_int()
+        tuned = _check(lib().wg_sweep_tuning(self._h, ctypes.byref(b), ctypes.byref(c), ctypes.byref(k)))
+        return dict(block=b.value, chunk=c.value, blocks_per_cu=k.value, tuned=bool(tuned))
+
+    def matrices(self, cand):
+        a, m, r = self.alpha, self.m, self.r
+        AT = np.zeros((m, a), np.float32)
+        G = np.zeros((a, r), np.float32)
+        BT = np.zeros((a, a), np.float32)
+        flag = c_int()
+        _check(lib().wg_sweep_matrices(self._h, cand, _fptr(AT), _fptr(G), _fptr(BT), ctypes.byref(flag)))
+        return AT, G, BT, flag.value

@@ -33,18 +33,39 @@ def test_matrices_are_rounded_exact_values():
                 assert abs(Fr(float(f[i, j])) - v) <= abs(v) * Fr(1, 2 ** 23)
 
 
-def test_ascending_order_and_no_fma():
-    """apply_left sums in ascending index order with every operation rounded."""
+def test_fma32_is_correctly_rounded():
+    """fma32 rounds a*b + c once: brute force against exact rational
+    arithmetic on random data and on constructed midpoint cases (where
+    rounding the float64 sum first would give the wrong answer)."""
+    rng = np.random.default_rng(0)
+    a, b, c = ((rng.standard_normal(4000) * 10.0 ** rng.integers(-8, 8, 4000)).astype(np.float32)
+               for _ in range(3))
+    r = fp.fma32(a, b, c)
+    for i in range(0, 4000, 7):
+        ex = Fr(float(a[i])) * Fr(float(b[i])) + Fr(float(c[i]))
+        cands = [np.nextafter(r[i], np.float32(-np.inf)), r[i], np.nextafter(r[i], np.float32(np.inf))]
+        errs = [abs(Fr(float(v)) - ex) for v in cands]
+        assert errs[1] <= min(errs)
+    # (1 + 2^-12)^2 = 1 + 2^-11 + 2^-24 is a float32 midpoint; a tiny c decides
+    x = np.float32(1 + 2 ** -12)
+    lo, hi = np.float32(1 + 2 ** -11), np.float32(1 + 2 ** -11 + 2 ** -23)
+    assert fp.fma32(x, x, np.float32(0.0)) == lo                      # tie: even
+    assert fp.fma32(x, x, np.float32(2.0 ** -60)) == hi
+    assert fp.fma32(x, x, np.float32(-2.0 ** -60)) == lo
+
+
+def test_ascending_fused_order():
+    """apply_left accumulates in ascending index order with one rounding per
+    term: acc <- fma(m_l, x_l, acc) from acc = 0."""
     X = np.array([[1e8], [1.0], [-1e8]], dtype=np.float32)
     ones = np.ones((1, 3), dtype=np.float32)
     # (1e8 + 1) rounds to 1e8 in float32, so the ascending sum is exactly 0
     assert fp.apply_left(ones, X, 0)[0, 0] == 0.0
-    assert fp.apply_left(ones[:, ::-1].copy(), X[::-1].copy(), 0)[0, 0] == 0.0
-    # product rounded before the add: a*b + c with a*b inexact in float32
+    # the second term is fused: a*b + c rounded once
     a, b, c = np.float32(1 + 2 ** -12), np.float32(1 + 2 ** -12), np.float32(-1.0)
-    got = fp.apply_left(np.array([[a, 1]], dtype=np.float32), np.array([[b], [c]], dtype=np.float32), 0)[0, 0]
-    assert got == np.float32(np.float32(a * b) + c)
-    assert got != np.float32(float(a) * float(b) + float(c))       # what a fused multiply-add gives
+    got = fp.apply_left(np.array([[1, a]], dtype=np.float32), np.array([[c], [b]], dtype=np.float32), 0)[0, 0]
+    assert got == np.float32(float(a) * float(b) + float(c))            # exact here
+    assert got != np.float32(np.float32(a * b) + c)                     # what separate rounding gives
 
 
 def test_bf16_rounding_matches_torch():
