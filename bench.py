@@ -95,6 +95,38 @@ def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup):
     return plan, U, y, elapsed / steps * 1e3, stage_ms
 
 
+def bench_sweep(wg, torch, reps=5):
+    """4096 candidate c values log-spaced over [0.05, 20] (family {0, inf, +-1,
+    +-c, +-1/c}), each scored on its own uneven count of 500-2000 pool samples,
+    1D F(6,3) and 2D F(6x6,3x3): one graph launch per sweep."""
+    res = {}
+    n = 4096
+    c1 = torch.from_numpy(synth.candidate_grid(n)).cuda()
+    c2 = torch.ones(n, dtype=torch.float64, device="cuda")
+    counts = torch.from_numpy(synth.sample_counts(n)).cuda()
+    tiles = int(counts.sum().item())
+    for dims in (1, 2):
+        d, g = synth.tile_pool(2000, 8, 3, dims)
+        S = wg.Sweep(6, 3, dims, torch.from_numpy(d).cuda(), torch.from_numpy(g).cuda(), n)
+        out = S.autotune(c1, c2, counts)
+        S.run(c1, c2, counts, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            S.run(c1, c2, counts, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        o = out.cpu().numpy()
+        mean = o[:, 0] / np.maximum(o[:, 2], 1)
+        best = int(np.nanargmin(np.where(o[:, 3] > 0, np.inf, mean)))
+        res[f"{dims}d"] = {"ms": round(ms, 4), "candidates_per_s": round(n / (ms * 1e-3)),
+                           "tiles_per_s": round(tiles / (ms * 1e-3)), "tuning": S.tuning(),
+                           "best_c": float(c1[best]), "best_mean_abs": float(mean[best])}
+    return res
+
+
 def cpu_baseline(x, w, pts, ntiles):
     """The oracle as it stands, float16 form, on the first `ntiles` tiles."""
     from fractions import Fraction as Fr
@@ -169,6 +201,7 @@ def main():
         "forms": {d: {"value": round(flops / (f["ms"] * 1e-3) / 1e12, 2), "ms_per_step": round(f["ms"], 5),
                       "rel_l1": f["rel_l1"], "mean_abs": f["mean_abs"]} for d, f in forms.items()},
     }
+    out["sweep"] = bench_sweep(wg, torch)
     if not args.no_cpu:
         ntiles = min(args.cpu_tiles, L["P"])
         secs = cpu_baseline(xh, wh, pts, ntiles)

@@ -282,6 +282,57 @@ int wg_sweep_tuning(const wg_sweep* sweep, int* block, int* chunk, int* blocks_p
  * outputs, sizes as wg_transforms) and its flag; synchronous. */
 int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, float* BT, int* flag);
 
+/* ------------------------------------------------------------------------
+ * Error surrogate (device).  A fully connected network 4 -> 128 -> 128 ->
+ * 128 -> 1 with GELU (z * Phi(z), exact erf form) maps a point-family
+ * description to a predicted log10 mean absolute error, so that the smooth
+ * error curve (Sections 1 and 6.1) can be searched with few exact sweep
+ * evaluations.  Input encoding of a sample (c1, c2, m, r):
+ *   (ln c1 / ln 20, ln c2 / ln 20, (m - 5) / 3, r - 4)   (c2 NULL: ln c2 = 0).
+ * Parameters: device float32[wg_mlp_param_count()] = 33793, caller owned,
+ * layout W1[128][4], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
+ * W4[1][128], b4[1] (row-major W[out][in]).  Loss: mean over the batch of
+ * (prediction - target)^2.  All reductions run in a fixed order, so results
+ * are bitwise reproducible.
+ * ---------------------------------------------------------------------- */
+typedef struct wg_mlp wg_mlp;
+int wg_mlp_param_count(void);
+
+/* Training context for batches of at most max_batch samples; owns a device
+ * scratch of about max_batch / 16 * 135 KB.  Errors: WG_EINVAL, WG_ENOMEM. */
+int wg_mlp_create(wg_mlp** out, int max_batch);
+int wg_mlp_destroy(wg_mlp* mlp);            /* NULL is accepted */
+
+/* Data arrays (device): c1, c2 float64 (c2 may be NULL), m, r int32,
+ * target float32, all of length n. */
+
+/* Loss gradient over all n samples (n <= max_batch): grad_out (device
+ * float32[33793]) and loss_out (device float32[1], may be NULL). */
+int wg_mlp_gradient(wg_mlp* mlp, const float* params, const double* c1, const double* c2,
+                    const int* m, const int* r, const float* target, int n,
+                    float* grad_out, float* loss_out, wg_stream_t stream);
+
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; Kingma and Ba) for
+ * `epochs` passes over the n samples in the orders given by perm (device
+ * int32[epochs][n]), minibatches of `batch` consecutive entries of perm (the
+ * last n % batch entries of each pass are skipped), step counter starting at
+ * step0 >= 1.  adam_state: device float32[2 * 33793] (first then second
+ * moments; zero before the first step).  losses: device float32
+ * [epochs * (n / batch)], the loss of every step before its update. */
+int wg_mlp_train(wg_mlp* mlp, float* params, float* adam_state, int step0, float lr,
+                 const double* c1, const double* c2, const int* m, const int* r,
+                 const float* target, int n, const int* perm, int epochs, int batch,
+                 float* losses, wg_stream_t stream);
+
+/* Predictions out (device float32[n]). */
+int wg_mlp_predict(const float* params, const double* c1, const double* c2, const int* m,
+                   const int* r, int n, float* out, wg_stream_t stream);
+
+/* Indices (device int32[k], ascending values, ties to the smaller index,
+ * NaN never chosen, -1 when fewer than k candidates) of the k <= 64
+ * smallest entries of v (device float32[n]). */
+int wg_topk_min(const float* v, int n, int k, int* idx_out, wg_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,15 @@ _SIGS = {
     "wg_sweep_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_tuning": (c_int, [c_void_p, P_int, P_int, P_int]),
     "wg_sweep_matrices": (c_int, [c_void_p, c_int, P_float, P_float, P_float, P_int]),
+    "wg_mlp_param_count": (c_int, []),
+    "wg_mlp_create": (c_int, [ctypes.POINTER(c_void_p), c_int]),
+    "wg_mlp_destroy": (c_int, [c_void_p]),
+    "wg_mlp_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                c_void_p, c_void_p, c_void_p]),
+    "wg_mlp_train": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_int, c_void_p, c_int, c_int, c_void_p, c_void_p]),
+    "wg_mlp_predict": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "wg_topk_min": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "wg_score_error": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
@@ -398,3 +407,85 @@ class Sweep:
         flag = c_int()
         _check(lib().wg_sweep_matrices(self._h, cand, _fptr(AT), _fptr(G), _fptr(BT), ctypes.byref(flag)))
         return AT, G, BT, flag.value
+
+
+# ----------------------------------------------------------------------------
+# error surrogate
+# ----------------------------------------------------------------------------
+def mlp_param_count():
+    return lib().wg_mlp_param_count()
+
+
+def mlp_pack(params):
+    """[(W, b), ...] (numpy) -> flat float32 vector in the library's layout."""
+    return np.concatenate([np.concatenate([np.ravel(W), np.ravel(b)]) for W, b in params]).astype(np.float32)
+
+
+def mlp_unpack(flat, widths=(4, 128, 128, 128, 1)):
+    out, o = [], 0
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        W = flat[o:o + fi * fo].reshape(fo, fi)
+        o += fi * fo
+        b = flat[o:o + fo]
+        o += fo
+        out.append((W, b))
+    return out
+
+
+class Mlp:
+    """Training context of the surrogate network (parameters are tensors the
+    caller owns)."""
+
+    def __init__(self, max_batch):
+        h = c_void_p()
+        _check(lib().wg_mlp_create(ctypes.byref(h), max_batch))
+        self._h = h
+        self.max_batch = max_batch
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.wg_mlp_destroy(h)
+            self._h = None
+
+    def gradient(self, params, c1, c2, m, r, target, stream=None):
+        torch = _torch()
+        grad = torch.empty_like(params)
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+        _check(lib().wg_mlp_gradient(self._h, _tptr(params, torch.float32, "params"), _tptr(c1, torch.float64, "c1"),
+                                     _tptr(c2, torch.float64, "c2"), _tptr(m, torch.int32, "m"),
+                                     _tptr(r, torch.int32, "r"), _tptr(target, torch.float32, "target"),
+                                     c1.numel(), _tptr(grad, torch.float32, "grad"),
+                                     _tptr(loss, torch.float32, "loss"), _stream(stream)))
+        return grad, loss
+
+    def train(self, params, adam_state, step0, lr, c1, c2, m, r, target, perm, batch, stream=None):
+        torch = _torch()
+        n = c1.numel()
+        epochs = perm.shape[0]
+        losses = torch.empty(epochs * (n // batch), dtype=torch.float32, device=params.device)
+        _check(lib().wg_mlp_train(self._h, _tptr(params, torch.float32, "params"),
+                                  _tptr(adam_state, torch.float32, "adam_state"), step0, float(lr),
+                                  _tptr(c1, torch.float64, "c1"), _tptr(c2, torch.float64, "c2"),
+                                  _tptr(m, torch.int32, "m"), _tptr(r, torch.int32, "r"),
+                                  _tptr(target, torch.float32, "target"), n, _tptr(perm, torch.int32, "perm"),
+                                  epochs, batch, _tptr(losses, torch.float32, "losses"), _stream(stream)))
+        return losses
+
+
+def mlp_predict(params, c1, c2, m, r, out=None, stream=None):
+    torch = _torch()
+    n = c1.numel()
+    out = torch.empty(n, dtype=torch.float32, device=c1.device) if out is None else out
+    _check(lib().wg_mlp_predict(_tptr(params, torch.float32, "params"), _tptr(c1, torch.float64, "c1"),
+                                _tptr(c2, torch.float64, "c2"), _tptr(m, torch.int32, "m"), _tptr(r, torch.int32, "r"),
+                                n, _tptr(out, torch.float32, "out"), _stream(stream)))
+    return out
+
+
+def topk_min(v, k, stream=None):
+    torch = _torch()
+    idx = torch.empty(k, dtype=torch.int32, device=v.device)
+    _check(lib().wg_topk_min(_tptr(v, torch.float32, "v"), v.numel(), k, _tptr(idx, torch.int32, "idx"),
+                             _stream(stream)))
+    return idx
