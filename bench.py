@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--c", type=float, default=2.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tiles", type=int, default=800)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate search")
     return ap.parse_args()
 
 
@@ -127,6 +128,62 @@ def bench_sweep(wg, torch, reps=5):
     return res
 
 
+def bench_surrogate(torch):
+    """Leave-one-size-out surrogate search for F(4x4,3x3): training data are 1M
+    sweep-scored (c1, c2) pairs of the other 11 tile sizes (83,334 each) plus
+    64 of the held-out size; 32 proposals + 3 x 32 refinements are scored
+    exactly and compared with the plain 4096-point sweep and with random
+    search at the same budget."""
+    from paper_2201_10369_amd import surrogate as sg
+    m, r = 4, 3
+    t0 = time.perf_counter()
+    others = [s for s in synth.SURROGATE_SIZES if s != (m, r)]
+    data = sg.make_dataset(others, 83334)
+    shots = sg.make_dataset([(m, r)], 64, seed=11)
+    both = {k: np.concatenate([data[k], shots[k]]) for k in data}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    model, losses = sg.train(both, epochs=20, batch=4096)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    S = sg.sweep_for(m, r)
+    grid = synth.candidate_grid(4096)
+    ones = np.ones_like(grid)
+    plain = sg.score(S, grid, ones, np.full(4096, sg.POOL))
+    err, c1, _, used = sg.guided_search(model, S, m, r, grid, ones)
+    used += 64
+    rng = np.random.default_rng(12)
+    rand = sg.score(S, grid[rng.choice(4096, used, replace=False)], np.ones(used), np.full(used, sg.POOL))
+    return {"held_out": "F(4x4,3x3) 2D", "train_samples": len(both["c1"]),
+            "data_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
+            "final_loss": float(losses[-20:].mean().item()),
+            "surrogate_best": float(err), "surrogate_c": float(c1), "evaluations": int(used),
+            "plain_best": float(np.min(plain)), "plain_c": float(grid[int(np.argmin(plain))]),
+            "plain_evaluations": 4096, "random_best": float(np.min(rand)),
+            "within_1pct": bool(err <= 1.01 * np.min(plain))}
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch of a kernel from the committed counter summary, or
+    None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_f6x6_n64_fp16.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    k = rec.get("kernels", {}).get(kernel_key)
+    if k is None:
+        return None
+    src = os.path.join(ROOT, "paper_2201_10369_amd", "csrc", k["source"])
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != k["source_sha256"]:
+            return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def cpu_baseline(x, w, pts, ntiles):
     """The oracle as it stands, float16 form, on the first `ntiles` tiles."""
     from fractions import Fraction as Fr
@@ -181,7 +238,7 @@ def main():
     achieved_gbs = ab[dom] / (st[dom] * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes": ab[dom], "traffic": None}
+                "algorithmic_bytes": ab[dom], "traffic": traffic_for(dom)}
 
     f16 = forms["f16"]
     value = flops / (f16["ms"] * 1e-3) / 1e12
@@ -202,6 +259,8 @@ def main():
                       "rel_l1": f["rel_l1"], "mean_abs": f["mean_abs"]} for d, f in forms.items()},
     }
     out["sweep"] = bench_sweep(wg, torch)
+    if not args.no_surrogate:
+        out["surrogate"] = bench_surrogate(torch)
     if not args.no_cpu:
         ntiles = min(args.cpu_tiles, L["P"])
         secs = cpu_baseline(xh, wh, pts, ntiles)
