@@ -245,9 +245,10 @@ typedef struct wg_sweep wg_sweep;
  * device, n_pool x r (x r) float32 filters; both are read by every run and
  * must stay valid until the sweep is destroyed (the sweep does not copy
  * them).  max_cand bounds n_cand of every run.  The float64 reference of the
- * pool is computed on `stream` and waited for before returning.  The sweep
- * owns device buffers of about max_cand * (1 KB + 8 * n_pool / 64 B) plus
- * 8 * n_pool * (outputs per sample + 2) bytes.
+ * pool (and an element-major copy of the pool) is computed on `stream` and
+ * waited for before returning.  The sweep owns device buffers of about
+ * max_cand * (1 KB + 8 * n_pool / 64 B) plus n_pool * (4 * (tile + filter
+ * elements) + 8 * (outputs per sample + 2)) bytes.
  * Errors: WG_EINVAL, WG_EUNSUPPORTED, WG_ENOMEM, WG_EHIP. */
 int wg_sweep_create(wg_sweep** out, int m, int r, int dims, const float* d_pool,
                     const float* g_pool, int n_pool, int max_cand, wg_stream_t stream);

@@ -33,7 +33,6 @@
 namespace wg {
 
 constexpr int kMatStride = 256;     // floats per candidate: A^T | G | B^T
-constexpr int kMaskStride = 8;      // uint64 per candidate: at[2] g[1] bt[2]
 
 // ---------------------------------------------------------------------------
 // Family points (same definition as wg_family_points)
@@ -86,7 +85,6 @@ template <int M, int R>
 __global__ __launch_bounds__(64) void sweep_construct_kernel(const double* __restrict__ c1,
                                                              const double* __restrict__ c2, int n_cand,
                                                              float* __restrict__ mats,
-                                                             uint64_t* __restrict__ masks,
                                                              int* __restrict__ flags) {
     constexpr int A = M + R - 1;
     constexpr int NF = A - 1;
@@ -112,7 +110,6 @@ __global__ __launch_bounds__(64) void sweep_construct_kernel(const double* __res
         }
     }
     for (int q = 0; q < M * A + A * R + A * A; ++q) out[q] = 0.0f;
-    uint64_t mk[kMaskStride] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (!flag) {
         double others[NF], coef[A + 1];
         for (int i = 0; i < NF; ++i) {
@@ -139,23 +136,20 @@ __global__ __launch_bounds__(64) void sweep_construct_kernel(const double* __res
         for (int l = 0; l <= NF; ++l) BT[(A - 1) * A + l] = (float)coef[l];
         for (int q = 0; q < M * A + A * R + A * A; ++q)
             if (!isfinite(out[q])) flag = 1;
-        for (int q = 0; q < M * A; ++q)
-            if (AT[q] != 0.0f) mk[0 + (q >> 6)] |= 1ull << (q & 63);
-        for (int q = 0; q < A * R; ++q)
-            if (G[q] != 0.0f) mk[2] |= 1ull << q;
-        for (int q = 0; q < A * A; ++q)
-            if (BT[q] != 0.0f) mk[3 + (q >> 6)] |= 1ull << (q & 63);
     }
-    for (int q = 0; q < kMaskStride; ++q) masks[(size_t)cand * kMaskStride + q] = mk[q];
     flags[cand] = flag;
 }
 
 // ---------------------------------------------------------------------------
 // float64 reference of the pool (once per sweep object)
 // ---------------------------------------------------------------------------
+// Also copies the pool into element-major arrays so that consecutive
+// threads (consecutive samples) of the evaluation read consecutive addresses.
 template <int M, int R, int DIMS>
 __global__ __launch_bounds__(256) void sweep_reference_kernel(const float* __restrict__ d_pool,
                                                               const float* __restrict__ g_pool, int n_pool,
+                                                              float* __restrict__ d_soa,
+                                                              float* __restrict__ g_soa,
                                                               double* __restrict__ yref,
                                                               double* __restrict__ ref_abs) {
     constexpr int A = M + R - 1;
@@ -165,21 +159,25 @@ __global__ __launch_bounds__(256) void sweep_reference_kernel(const float* __res
     if (DIMS == 1) {
         const float* d = d_pool + (size_t)s * A;
         const float* g = g_pool + (size_t)s * R;
+        for (int q = 0; q < A; ++q) d_soa[(size_t)q * n_pool + s] = d[q];
+        for (int q = 0; q < R; ++q) g_soa[(size_t)q * n_pool + s] = g[q];
         for (int j = 0; j < M; ++j) {
             double acc = 0.0;
             for (int k = 0; k < R; ++k) acc = fma((double)d[j + k], (double)g[k], acc);
-            yref[(size_t)s * M + j] = acc;
+            yref[(size_t)j * n_pool + s] = acc;
             tot += fabs(acc);
         }
     } else {
         const float* d = d_pool + (size_t)s * A * A;
         const float* g = g_pool + (size_t)s * R * R;
+        for (int q = 0; q < A * A; ++q) d_soa[(size_t)q * n_pool + s] = d[q];
+        for (int q = 0; q < R * R; ++q) g_soa[(size_t)q * n_pool + s] = g[q];
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) {
                 double acc = 0.0;
                 for (int u = 0; u < R; ++u)
                     for (int v = 0; v < R; ++v) acc = fma((double)d[(i + u) * A + j + v], (double)g[u * R + v], acc);
-                yref[(size_t)s * M * M + i * M + j] = acc;
+                yref[(size_t)(i * M + j) * n_pool + s] = acc;
                 tot += fabs(acc);
             }
     }
@@ -197,57 +195,64 @@ __global__ void sweep_prefix_kernel(const double* __restrict__ ref_abs, int n_po
 }
 
 // ---------------------------------------------------------------------------
-// Evaluation.  Each thread evaluates whole tiles; the matrices of the block's
-// current candidate sit in LDS, their nonzero masks in scalar registers.
+// Evaluation.  Each thread evaluates whole tiles.  The block's current
+// candidate is staged in LDS as columns of B^T, columns and rows of G and
+// columns and rows of A^T (each padded to a multiple of 4 floats, read as
+// broadcast 16-byte loads).  Every term is a fused multiply-add in ascending
+// index order from zero; zero matrix entries are not skipped, which changes
+// nothing because fma(0, x, acc) == acc for the finite values involved
+// (flagged candidates, the only ones that could hold non-finite entries, are
+// never evaluated).
 // ---------------------------------------------------------------------------
-template <int M, int R, int DIMS>
-__device__ __forceinline__ double tile_error(const float* __restrict__ d_pool, const float* __restrict__ g_pool,
-                                             const double* __restrict__ yref, int s, const float* sAT,
-                                             const float* sG, const float* sBT, uint64_t mat0, uint64_t mat1,
-                                             uint64_t mg, uint64_t mbt0, uint64_t mbt1) {
-    constexpr int A = M + R - 1;
-    const uint64_t mat[2] = {mat0, mat1};
-    const uint64_t mbt[2] = {mbt0, mbt1};
-    const uint64_t mgg[1] = {mg};
-    double err = 0.0;
-    if (DIMS == 1) {
-        const float* d = d_pool + (size_t)s * A;
-        const float* g = g_pool + (size_t)s * R;
-        float gv[R], dv[A];
-#pragma unroll
-        for (int k = 0; k < R; ++k) gv[k] = g[k];
-#pragma unroll
-        for (int l = 0; l < A; ++l) dv[l] = d[l];
-        float mh[A];
-#pragma unroll
-        for (int i = 0; i < A; ++i) {
-            float u = 0.0f, v = 0.0f;
-#pragma unroll
-            for (int k = 0; k < R; ++k)
-                if (nz(mgg, i * R + k)) u = __builtin_fmaf(sG[i * R + k], gv[k], u);
-#pragma unroll
-            for (int l = 0; l < A; ++l)
-                if (nz(mbt, i * A + l)) v = __builtin_fmaf(sBT[i * A + l], dv[l], v);
-            mh[i] = u * v;
-        }
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            float y = 0.0f;
-#pragma unroll
-            for (int i = 0; i < A; ++i)
-                if (nz(mat, j * A + i)) y = __builtin_fmaf(sAT[j * A + i], mh[i], y);
-            err += fabs((double)y - yref[(size_t)s * M + j]);
-        }
-        return err;
+template <int M, int R>
+struct EvalLds {
+    static constexpr int A = M + R - 1;
+    static constexpr int AP = (A + 3) & ~3, MP = (M + 3) & ~3, RP = (R + 3) & ~3;
+    static constexpr int kBc = 0;                  // [A][AP]  B^T column l at l*AP
+    static constexpr int kGc = kBc + A * AP;       // [R][AP]  G column v at v*AP
+    static constexpr int kGr = kGc + R * AP;       // [A][RP]  G row i at i*RP
+    static constexpr int kAc = kGr + A * RP;       // [A][MP]  A^T column i at i*MP
+    static constexpr int kAr = kAc + A * MP;       // [M][AP]  A^T row q at q*AP
+    static constexpr int kSize = kAr + M * AP;
+
+    // value of LDS slot q from the candidate's row-major A^T | G | B^T
+    __device__ static float slot(const float* __restrict__ m, int q) {
+        const float* AT = m;
+        const float* G = m + M * A;
+        const float* BT = m + M * A + A * R;
+        if (q < kGc) { const int l = q / AP, i = q % AP; return i < A ? BT[i * A + l] : 0.0f; }
+        if (q < kGr) { q -= kGc; const int v = q / AP, j = q % AP; return j < A ? G[j * R + v] : 0.0f; }
+        if (q < kAc) { q -= kGr; const int i = q / RP, u = q % RP; return u < R ? G[i * R + u] : 0.0f; }
+        if (q < kAr) { q -= kAc; const int i = q / MP, k = q % MP; return k < M ? AT[k * A + i] : 0.0f; }
+        q -= kAr;
+        const int qq = q / AP, j = q % AP;
+        return j < A ? AT[qq * A + j] : 0.0f;
     }
-    const float* d = d_pool + (size_t)s * A * A;
-    const float* g = g_pool + (size_t)s * R * R;
+};
+
+template <int N>
+__device__ __forceinline__ void lds_vec(const float* p, float (&v)[N]) {
+    static_assert(N % 4 == 0, "padded length");
+#pragma unroll
+    for (int q = 0; q < N; q += 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p + q);
+        v[q] = t.x; v[q + 1] = t.y; v[q + 2] = t.z; v[q + 3] = t.w;
+    }
+}
+
+// One 2D tile: Y = A^T [(G g G^T) .* (B^T d B)] A against the float64
+// reference; `lds` is the staged candidate.
+template <int M, int R>
+__device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
+                                                const double* __restrict__ yref, int s, int np, const float* lds) {
+    using L = EvalLds<M, R>;
+    constexpr int A = L::A, AP = L::AP, MP = L::MP, RP = L::RP;
     float gg[R][R];
 #pragma unroll
     for (int u = 0; u < R; ++u)
 #pragma unroll
-        for (int v = 0; v < R; ++v) gg[u][v] = g[u * R + v];
-    // T1 = B^T d, streaming the rows of d
+        for (int v = 0; v < R; ++v) gg[u][v] = g_soa[(size_t)(u * R + v) * np + s];
+    // T1 = B^T d, one row of d at a time
     float t1[A][A];
 #pragma unroll
     for (int i = 0; i < A; ++i)
@@ -255,18 +260,31 @@ __device__ __forceinline__ double tile_error(const float* __restrict__ d_pool, c
         for (int b = 0; b < A; ++b) t1[i][b] = 0.0f;
 #pragma unroll
     for (int l = 0; l < A; ++l) {
-        float drow[A];
+        float drow[A], bc[AP];
 #pragma unroll
-        for (int b = 0; b < A; ++b) drow[b] = d[l * A + b];
+        for (int b = 0; b < A; ++b) drow[b] = d_soa[(size_t)(l * A + b) * np + s];
+        lds_vec(lds + L::kBc + l * AP, bc);
 #pragma unroll
         for (int i = 0; i < A; ++i)
-            if (nz(mbt, i * A + l)) {
-                const float bv = sBT[i * A + l];
 #pragma unroll
-                for (int b = 0; b < A; ++b) t1[i][b] = __builtin_fmaf(bv, drow[b], t1[i][b]);
-            }
+            for (int b = 0; b < A; ++b) t1[i][b] = __builtin_fmaf(bc[i], drow[b], t1[i][b]);
     }
-    // row by row: U row i, V row i, Hadamard, accumulate Z = A^T Mh
+    // V = T1 B, one column of B^T at a time
+    float vv[A][A];
+#pragma unroll
+    for (int i = 0; i < A; ++i)
+#pragma unroll
+        for (int j = 0; j < A; ++j) vv[i][j] = 0.0f;
+#pragma unroll
+    for (int l = 0; l < A; ++l) {
+        float bc[AP];
+        lds_vec(lds + L::kBc + l * AP, bc);
+#pragma unroll
+        for (int i = 0; i < A; ++i)
+#pragma unroll
+            for (int j = 0; j < A; ++j) vv[i][j] = __builtin_fmaf(t1[i][l], bc[j], vv[i][j]);
+    }
+    // row i of U = G g G^T, Hadamard with row i of V, accumulate Z = A^T Mh
     float z[M][A];
 #pragma unroll
     for (int k = 0; k < M; ++k)
@@ -274,61 +292,123 @@ __device__ __forceinline__ double tile_error(const float* __restrict__ d_pool, c
         for (int j = 0; j < A; ++j) z[k][j] = 0.0f;
 #pragma unroll
     for (int i = 0; i < A; ++i) {
-        float p1[R];
+        float gr[RP], p1[R], urow[A], ac[MP];
+        lds_vec(lds + L::kGr + i * RP, gr);
 #pragma unroll
         for (int v = 0; v < R; ++v) p1[v] = 0.0f;
 #pragma unroll
         for (int u = 0; u < R; ++u)
-            if (nz(mgg, i * R + u)) {
 #pragma unroll
-                for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(sG[i * R + u], gg[u][v], p1[v]);
-            }
-        float mh[A];
+            for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(gr[u], gg[u][v], p1[v]);
+#pragma unroll
+        for (int j = 0; j < A; ++j) urow[j] = 0.0f;
+#pragma unroll
+        for (int v = 0; v < R; ++v) {
+            float gc[AP];
+            lds_vec(lds + L::kGc + v * AP, gc);
+#pragma unroll
+            for (int j = 0; j < A; ++j) urow[j] = __builtin_fmaf(gc[j], p1[v], urow[j]);
+        }
+        lds_vec(lds + L::kAc + i * MP, ac);
 #pragma unroll
         for (int j = 0; j < A; ++j) {
-            float uij = 0.0f, vij = 0.0f;
+            const float mh = urow[j] * vv[i][j];
 #pragma unroll
-            for (int v = 0; v < R; ++v)
-                if (nz(mgg, j * R + v)) uij = __builtin_fmaf(sG[j * R + v], p1[v], uij);
-#pragma unroll
-            for (int l = 0; l < A; ++l)
-                if (nz(mbt, j * A + l)) vij = __builtin_fmaf(sBT[j * A + l], t1[i][l], vij);
-            mh[j] = uij * vij;
+            for (int k = 0; k < M; ++k) z[k][j] = __builtin_fmaf(ac[k], mh, z[k][j]);
         }
-#pragma unroll
-        for (int k = 0; k < M; ++k)
-            if (nz(mat, k * A + i)) {
-                const float av = sAT[k * A + i];
-#pragma unroll
-                for (int j = 0; j < A; ++j) z[k][j] = __builtin_fmaf(av, mh[j], z[k][j]);
-            }
     }
-    const double* yr = yref + (size_t)s * M * M;
+    // Y = Z A, one row of A^T at a time
+    double err = 0.0;
 #pragma unroll
-    for (int k = 0; k < M; ++k)
+    for (int q = 0; q < M; ++q) {
+        float ar[AP];
+        lds_vec(lds + L::kAr + q * AP, ar);
 #pragma unroll
-        for (int q = 0; q < M; ++q) {
+        for (int k = 0; k < M; ++k) {
             float y = 0.0f;
 #pragma unroll
-            for (int j = 0; j < A; ++j)
-                if (nz(mat, q * A + j)) y = __builtin_fmaf(sAT[q * A + j], z[k][j], y);
-            err += fabs((double)y - yr[k * M + q]);
+            for (int j = 0; j < A; ++j) y = __builtin_fmaf(z[k][j], ar[j], y);
+            err += fabs((double)y - yref[(size_t)(k * M + q) * np + s]);
         }
+    }
     return err;
 }
 
+// T 1D tiles per thread (samples s[t]; invalid ones are evaluated on a
+// clamped index and not counted), sharing each matrix value read.
+template <int M, int R, int T>
+__device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
+                                                const double* __restrict__ yref, const int (&s)[T],
+                                                const bool (&ok)[T], int np, const float* lds) {
+    using L = EvalLds<M, R>;
+    constexpr int A = L::A, AP = L::AP, MP = L::MP;
+    float gv[T][R], dv[T][A], u[T][A], v[T][A];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) gv[t][k] = g_soa[(size_t)k * np + s[t]];
+#pragma unroll
+        for (int l = 0; l < A; ++l) dv[t][l] = d_soa[(size_t)l * np + s[t]];
+#pragma unroll
+        for (int i = 0; i < A; ++i) u[t][i] = v[t][i] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {                       // U = G g, column k of G
+        float gc[AP];
+        lds_vec(lds + L::kGc + k * AP, gc);
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int i = 0; i < A; ++i) u[t][i] = __builtin_fmaf(gc[i], gv[t][k], u[t][i]);
+    }
+#pragma unroll
+    for (int l = 0; l < A; ++l) {                       // V = B^T d, column l of B^T
+        float bc[AP];
+        lds_vec(lds + L::kBc + l * AP, bc);
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int i = 0; i < A; ++i) v[t][i] = __builtin_fmaf(bc[i], dv[t][l], v[t][i]);
+    }
+    float y[T][M];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int j = 0; j < M; ++j) y[t][j] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < A; ++i) {                       // Y = A^T Mh, column i of A^T
+        float ac[MP];
+        lds_vec(lds + L::kAc + i * MP, ac);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const float mh = u[t][i] * v[t][i];
+#pragma unroll
+            for (int j = 0; j < M; ++j) y[t][j] = __builtin_fmaf(ac[j], mh, y[t][j]);
+        }
+    }
+    double err = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        double e = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) e += fabs((double)y[t][j] - yref[(size_t)j * np + s[t]]);
+        err += ok[t] ? e : 0.0;
+    }
+    return err;
+}
+
+constexpr int kTiles1d = 4;
+
 template <int M, int R, int DIMS>
-__global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict__ d_pool,
-                                                         const float* __restrict__ g_pool,
+__global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict__ d_soa,
+                                                         const float* __restrict__ g_soa,
                                                          const double* __restrict__ yref,
                                                          const float* __restrict__ mats,
-                                                         const uint64_t* __restrict__ masks,
                                                          const int* __restrict__ flags,
                                                          const int* __restrict__ counts, int n_cand, int n_pool,
                                                          int ipc, int chunk, double* __restrict__ partial) {
-    constexpr int A = M + R - 1;
-    constexpr int NM = M * A + A * R + A * A;
-    __shared__ float sm[NM];
+    using L = EvalLds<M, R>;
+    __shared__ __align__(16) float sm[L::kSize];
     __shared__ double red[256];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const long items = (long)n_cand * ipc;
@@ -343,15 +423,32 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
             continue;
         }
         __syncthreads();                                      // previous item done with sm
-        for (int q = tid; q < NM; q += nthr) sm[q] = mats[(size_t)cand * kMatStride + q];
-        const uint64_t* mk = masks + (size_t)cand * kMaskStride;
-        const uint64_t mat0 = mk[0], mat1 = mk[1], mg = mk[2], mbt0 = mk[3], mbt1 = mk[4];
+        for (int q = tid; q < L::kSize; q += nthr) sm[q] = L::slot(mats + (size_t)cand * kMatStride, q);
         __syncthreads();
         const int stop = min(n, start + chunk);
         double err = 0.0;
-        for (int s = start + tid; s < stop; s += nthr)
-            err += tile_error<M, R, DIMS>(d_pool, g_pool, yref, s, sm, sm + M * A, sm + M * A + A * R, mat0,
-                                          mat1, mg, mbt0, mbt1);
+        if (DIMS == 1) {
+            for (int s0 = start + tid; s0 < stop; s0 += kTiles1d * nthr) {
+                // an opaque zero offset keeps the matrix reads inside the loop
+                int z0 = 0;
+                asm volatile("" : "+v"(z0));
+                int ss[kTiles1d];
+                bool ok[kTiles1d];
+#pragma unroll
+                for (int t = 0; t < kTiles1d; ++t) {
+                    const int si = s0 + t * nthr;
+                    ok[t] = si < stop;
+                    ss[t] = ok[t] ? si : s0;
+                }
+                err += tile_error_1d<M, R, kTiles1d>(d_soa, g_soa, yref, ss, ok, n_pool, sm + z0);
+            }
+        } else {
+            for (int s = start + tid; s < stop; s += nthr) {
+                int z0 = 0;
+                asm volatile("" : "+v"(z0));
+                err += tile_error_2d<M, R>(d_soa, g_soa, yref, s, n_pool, sm + z0);
+            }
+        }
         red[tid] = err;
         __syncthreads();
         for (int st = nthr / 2; st > 0; st >>= 1) {
@@ -390,19 +487,19 @@ template <int M, int R, int DIMS>
 struct SweepOps {
     static void reference(const Sweep& S, hipStream_t st) {
         hipLaunchKernelGGL((sweep_reference_kernel<M, R, DIMS>), dim3((S.n_pool + 255) / 256), dim3(256), 0, st,
-                           S.d_pool, S.g_pool, S.n_pool, S.yref, S.ref_abs);
+                           S.d_pool, S.g_pool, S.n_pool, S.d_soa, S.g_soa, S.yref, S.ref_abs);
         hipLaunchKernelGGL(sweep_prefix_kernel, dim3(1), dim3(64), 0, st, S.ref_abs, S.n_pool, S.prefix);
     }
     static void run(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st) {
         const int ipc = (S.n_pool + t.chunk - 1) / t.chunk;
         hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + 63) / 64), dim3(64), 0, st, a.c1,
-                           a.c2, a.n_cand, S.mats, S.masks, S.flags);
+                           a.c2, a.n_cand, S.mats, S.flags);
         const long items = (long)a.n_cand * ipc;
         long grid = (long)S.n_cu * t.blocks_per_cu;
         if (grid > items) grid = items;
         if (grid < 1) grid = 1;
-        hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS>), dim3((unsigned)grid), dim3(t.block), 0, st, S.d_pool,
-                           S.g_pool, S.yref, S.mats, S.masks, S.flags, a.counts, a.n_cand, S.n_pool, ipc, t.chunk,
+        hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS>), dim3((unsigned)grid), dim3(t.block), 0, st, S.d_soa,
+                           S.g_soa, S.yref, S.mats, S.flags, a.counts, a.n_cand, S.n_pool, ipc, t.chunk,
                            S.partial);
         hipLaunchKernelGGL(sweep_finalize_kernel, dim3((a.n_cand + 255) / 256), dim3(256), 0, st, S.partial,
                            S.prefix, S.flags, a.counts, a.n_cand, S.n_pool, ipc, DIMS == 1 ? M : M * M, a.out);
@@ -457,7 +554,7 @@ static void release(Sweep* S) {
     if (S->exec) (void)hipGraphExecDestroy(S->exec);
     if (S->graph) (void)hipGraphDestroy(S->graph);
     if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
-    void* bufs[] = {S->yref, S->ref_abs, S->prefix, S->mats, S->masks, S->flags, S->partial};
+    void* bufs[] = {S->d_soa, S->g_soa, S->yref, S->ref_abs, S->prefix, S->mats, S->flags, S->partial};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete S;
@@ -490,12 +587,14 @@ int wg_sweep_create(wg_sweep** out, int m, int r, int dims, const float* d_pool,
     S->n_cu = prop.multiProcessorCount;
     const int outs = dims == 1 ? m : m * m;
     const size_t max_ipc = (size_t)(n_pool + 63) / 64;
+    const int a2 = dims == 1 ? S->alpha : S->alpha * S->alpha, r2 = dims == 1 ? r : r * r;
     struct { void** p; size_t bytes; } allocs[] = {
+        {(void**)&S->d_soa, sizeof(float) * (size_t)n_pool * a2},
+        {(void**)&S->g_soa, sizeof(float) * (size_t)n_pool * r2},
         {(void**)&S->yref, sizeof(double) * (size_t)n_pool * outs},
         {(void**)&S->ref_abs, sizeof(double) * (size_t)n_pool},
         {(void**)&S->prefix, sizeof(double) * (size_t)(n_pool + 1)},
         {(void**)&S->mats, sizeof(float) * (size_t)max_cand * kMatStride},
-        {(void**)&S->masks, sizeof(uint64_t) * (size_t)max_cand * kMaskStride},
         {(void**)&S->flags, sizeof(int) * (size_t)max_cand},
         {(void**)&S->partial, sizeof(double) * (size_t)max_cand * max_ipc},
     };

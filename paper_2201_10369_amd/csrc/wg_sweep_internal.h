@@ -28,11 +28,12 @@ struct Sweep {
     int m = 0, r = 0, dims = 0, alpha = 0, n_pool = 0, max_cand = 0, n_cu = 0;
     const float* d_pool = nullptr;
     const float* g_pool = nullptr;
-    double* yref = nullptr;      // float64 reference outputs of every pool sample
+    float* d_soa = nullptr;      // pool tiles, element-major: [alpha(^2)][n_pool]
+    float* g_soa = nullptr;      // pool filters, element-major: [r(^2)][n_pool]
+    double* yref = nullptr;      // float64 reference outputs, element-major: [outs][n_pool]
     double* ref_abs = nullptr;   // sum |yref| per sample
     double* prefix = nullptr;    // prefix sums of ref_abs (n_pool + 1)
     float* mats = nullptr;       // per candidate float32 A^T | G | B^T
-    uint64_t* masks = nullptr;   // per candidate nonzero masks
     int* flags = nullptr;        // per candidate: 1 = invalid or singular
     double* partial = nullptr;   // per work item error sums
     SweepTune tune{128, 128, 4};
