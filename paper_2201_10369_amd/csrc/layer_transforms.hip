@@ -49,7 +49,7 @@ __device__ __forceinline__ int bin_exp(float v) {
 __device__ __forceinline__ int floor_half(int d) { return d >> 1; }
 
 // ---------------------------------------------------------------------------
-// 16-bit Hadamard stage, part 1: partial maxima of |w| over chunks of 32
+// 16-bit Hadamard stage: partial maxima of |w| over chunks of kKChunk
 // filters for 64 channels per block (coalesced: a wave reads 64 consecutive
 // channels' r*r taps).  part[kc][c] for filter chunk kc.
 // ---------------------------------------------------------------------------
@@ -84,133 +84,176 @@ __global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restr
 }
 
 // ---------------------------------------------------------------------------
-// 16-bit Hadamard stage, part 2: per channel c the exponent part
-// t[c] = E(x_absmax[c]) - E(max_k |w[k][c]|) and the table s[e][c].
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void channel_exponent_kernel(const float* __restrict__ part,
-                                                               const float* __restrict__ x_absmax,
-                                                               int32_t* __restrict__ s_tab,
-                                                               int32_t* __restrict__ t_tab, RowExps ex,
-                                                               int alpha, int C, int C_pad, int kchunks) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= C_pad) return;
-    int tc = 0;
-    if (c < C) {
-        float aw = 0.0f;
-        int q = 0;
-        for (; q + 8 <= kchunks; q += 8) {         // eight loads in flight
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(q + u) * C_pad + c];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) aw = fmaxf(aw, v[u]);
-        }
-        for (; q < kchunks; ++q) aw = fmaxf(aw, part[(size_t)q * C_pad + c]);
-        const float ax = x_absmax != nullptr ? x_absmax[c] : 1.0f;
-        tc = bin_exp(ax) - bin_exp(aw);
-    }
-    t_tab[c] = tc;
-    for (int e1 = 0; e1 < alpha; ++e1)
-        for (int e2 = 0; e2 < alpha; ++e2)
-            s_tab[(size_t)(e1 * alpha + e2) * C_pad + c] = c < C ? floor_half(ex.dB[e1] + ex.dB[e2] + tc) : 0;
-}
-
-// ---------------------------------------------------------------------------
-// Filter transform U = G g G^T.  One thread per (row i of U, filter k,
-// channel c) of the padded K x C, channel fastest so every store of U'[e][k][.]
-// is a contiguous run of channels; for the 16-bit stage each row is scaled by
-// 2^s (s from the channel exponent table) before rounding.
+// Filter transform U = G g G^T.  A block covers 64 channels (the lanes of a
+// wave) and four filters (one per wave); each thread transforms one filter
+// channel g = w[k][c] into all alpha x alpha entries, so every store of
+// U'[e][k][.] is a contiguous run of 64 channels.
+//
+// For the 16-bit stage the block first finishes the per-channel exponent
+// part t[c] = E(x_absmax[c]) - E(max_k |w[k][c]|) from the partial maxima of
+// all filter chunks (every block of a channel group repeats this small
+// reduction, so no second launch is needed), scales entry (i, j) by 2^s with
+// s = floor((dB[i] + dB[j] + t[c]) / 2) before rounding, and the blocks of
+// the first filter group also write t and the table s[e][c].
 // ---------------------------------------------------------------------------
 template <int M, int R, int DT>
 __global__ __launch_bounds__(256) void filter_transform_kernel(const float* __restrict__ w,
                                                                void* __restrict__ Uout,
-                                                               const int32_t* __restrict__ t_tab,
-                                                               Mats<M, R> mt, NzMasks nzm, RowExps ex,
-                                                               Geo g) {
+                                                               const float* __restrict__ part,
+                                                               const float* __restrict__ x_absmax,
+                                                               int32_t* __restrict__ s_tab,
+                                                               int32_t* __restrict__ t_tab, int kchunks,
+                                                               Mats<M, R> mt, NzMasks nzm, RowExps ex, Geo g) {
     constexpr int A = M + R - 1;
     using T = typename Elem<DT>::T;
     __shared__ float sG[A][R];
+    __shared__ float sred[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int k = blockIdx.y * 4 + wv;
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int a = 0; a < A; ++a)
 #pragma unroll
             for (int u = 0; u < R; ++u) sG[a][u] = mt.G[a][u];
     }
+    int tc = 0;
+    if (DT != kF32) {
+        float aw = 0.0f;
+        if (c < g.C) {
+#pragma unroll 8
+            for (int q = wv; q < kchunks; q += 4) aw = fmaxf(aw, part[(size_t)q * g.C_pad + c]);
+        }
+        sred[wv][lane] = aw;
+    }
     __syncthreads();
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    const long total = (long)A * g.K_pad * g.C_pad;
-    if (idx >= total) return;
-    const int c = (int)(idx % g.C_pad);
-    const long rest = idx / g.C_pad;
-    const int k = (int)(rest % g.K_pad);
-    const int i = (int)(rest / g.K_pad);
+    if (DT != kF32 && c < g.C) {
+        const float mw = fmaxf(fmaxf(sred[0][lane], sred[1][lane]), fmaxf(sred[2][lane], sred[3][lane]));
+        tc = bin_exp(x_absmax != nullptr ? x_absmax[c] : 1.0f) - bin_exp(mw);
+    }
+    if (DT != kF32 && blockIdx.y == 0 && c < g.C_pad) {
+        if (wv == 0) t_tab[c] = tc;
+#pragma unroll
+        for (int e1 = 0; e1 < A; ++e1)
+            if ((e1 & 3) == wv) {
+#pragma unroll
+                for (int e2 = 0; e2 < A; ++e2)
+                    s_tab[(size_t)(e1 * A + e2) * g.C_pad + c] = c < g.C ? floor_half(ex.dB[e1] + ex.dB[e2] + tc) : 0;
+            }
+    }
+    if (c >= g.C_pad) return;
     const bool live = k < g.K && c < g.C;
     float gg[R][R];
 #pragma unroll
     for (int u = 0; u < R; ++u)
 #pragma unroll
         for (int v = 0; v < R; ++v) gg[u][v] = live ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f;
-    int si = 0;
-    if (DT != kF32) si = c < g.C ? t_tab[c] + ex.dB[i] : 0;
-    // row i of P1 = G g (the row index differs between threads: no skipping)
-    float p1[R];
-#pragma unroll
-    for (int v = 0; v < R; ++v) p1[v] = 0.0f;
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-        const float b = sG[i][u];
-#pragma unroll
-        for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(b, gg[u][v], p1[v]);
-    }
     T* U = reinterpret_cast<T*>(Uout);
     const unsigned off = (unsigned)k * g.C_pad + c;
     const size_t plane = in_vgpr((size_t)g.K_pad * g.C_pad);
 #pragma unroll
-    for (int j = 0; j < A; ++j) {
-        float acc = 0.0f;
+    for (int i = 0; i < A; ++i) {
+        // row i of P1 = G g
+        float p1[R];
 #pragma unroll
-        for (int v = 0; v < R; ++v)
-            if (nz(nzm.g, j * R + v)) acc = __builtin_fmaf(sG[j][v], p1[v], acc);
-        if (DT != kF32) acc = ldexpf(acc, c < g.C ? floor_half(si + ex.dB[j]) : 0);
-        T* Ue = U + (size_t)(i * A + j) * plane;
-        Ue[off] = Elem<DT>::from_f32(acc);
+        for (int v = 0; v < R; ++v) p1[v] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (nz(nzm.g, i * R + u)) {
+                const float b = sG[i][u];
+#pragma unroll
+                for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(b, gg[u][v], p1[v]);
+            }
+        const int si = tc + ex.dB[i];
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int v = 0; v < R; ++v)
+                if (nz(nzm.g, j * R + v)) acc = __builtin_fmaf(sG[j][v], p1[v], acc);
+            if (DT != kF32) acc = ldexpf(acc, c < g.C ? floor_half(si + ex.dB[j]) : 0);
+            T* Ue = U + (size_t)(i * A + j) * plane;
+            Ue[off] = Elem<DT>::from_f32(acc);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Input transform V = B^T d B.  A block covers one image n, one tile row th,
-// `twb` consecutive tiles of that row and 64 input channels (one wave per
-// tile).  It stages the alpha input rows of those channels in LDS (groups of
-// lanes read contiguous row segments, sixteen loads in flight per thread,
-// zeros outside the image), then each lane transforms one (channel, tile)
-// pair; the 64 lanes of a wave hold 64 consecutive channels of one tile, so
-// every V' store is one contiguous run.  The channel blocks of one tile row
-// are consecutive blocks of the grid, so the runs of one V' row are written
-// close together in time.
+// `twb` consecutive tiles of that row and kInCh input channels.  It stages the
+// alpha input rows of those channels in LDS (threads own fixed positions of
+// the band and walk the channels, so consecutive threads read contiguous row
+// segments; zeros outside the image), then transforms in two passes over LDS:
+//   pass 1: every staged column b of every channel, T1[:, b] = B^T d[:, b],
+//           written back in place (columns shared by neighbouring tiles are
+//           transformed once);
+//   pass 2: every (channel, tile, row i), V[i][j] = sum_l T1[i][l] B^T[j][l],
+//           scaled and rounded to the GEMM type and stored; consecutive lanes
+//           hold consecutive channels, so every V' store is a contiguous run.
+// Zero entries of B^T are not skipped: fma(0, x, acc) == acc for finite x,
+// and a per-term branch costs more than the multiply-add.  Block indices are
+// mapped so
+// that each XCD runs a contiguous range of bands, keeping the channel blocks
+// of one tile row (which write the halves of the same V' lines) and
+// neighbouring tile rows (which share R-1 input rows) in one L2.
 // ---------------------------------------------------------------------------
-constexpr int kInCh = 64;
+constexpr int kInCh = 32;
+constexpr int kInThreads = 256;
+constexpr int kXcdCount = 8;
+
+template <int A, bool kFull>
+__device__ __forceinline__ void stage_band(const float* __restrict__ x, float* lds, const Geo& g, int n, int c0,
+                                           int nch, int row0, int col0, int wl, int row_w, int ch_stride) {
+    constexpr int kBatch = 16;
+    const size_t hw = in_vgpr((size_t)g.H * g.W);
+    const int cstride = in_vgpr(ch_stride);
+    const int last = in_vgpr(max(nch - 1, 0));
+    for (int ac = threadIdx.x; ac < A * wl; ac += kInThreads) {
+        const int a = ac / wl, col = ac - a * wl;
+        const int gi = row0 + a, gj = col0 + col;
+        const bool inside = gi >= 0 && gi < g.H && gj >= 0 && gj < g.W && nch > 0;
+        // loads are unconditional (from a valid address) and masked after,
+        // so a whole batch is in flight at once
+        const float* src = inside ? x + (((size_t)n * g.C + c0) * g.H + gi) * g.W + gj : x;
+        float* dst = lds + a * row_w + col;
+#pragma unroll
+        for (int cb = 0; cb < kInCh; cb += kBatch) {
+            float v[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                v[u] = *src;                        // channel min(cb + u, last)
+                if (kFull || cb + u < last) src += hw;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) v[u] = (inside && (kFull || cb + u <= last)) ? v[u] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                *dst = v[u];
+                dst += cstride;
+            }
+        }
+    }
+}
 
 template <int M, int R, int DT>
-__global__ __launch_bounds__(512) void input_transform_kernel(const float* __restrict__ x,
-                                                              void* __restrict__ Vout,
-                                                              const int32_t* __restrict__ t_tab,
-                                                              Mats<M, R> mt, NzMasks nzm, RowExps ex, Geo g,
-                                                              int twb, int n_twb, int row_w, int ch_stride) {
+__global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float* __restrict__ x,
+                                                                     void* __restrict__ Vout,
+                                                                     const int32_t* __restrict__ t_tab,
+                                                                     Mats<M, R> mt, NzMasks nzm, RowExps ex,
+                                                                     Geo g, int twb, int n_twb, int row_w,
+                                                                     int ch_stride, int n_blocks) {
     constexpr int A = M + R - 1;
-    constexpr int kBatch = 16;
-    const int nthr = blockDim.x;
     using T = typename Elem<DT>::T;
     extern __shared__ float lds[];
     __shared__ float sBT[A][A];
+    __shared__ int sdB[A];
+    __shared__ int stc[kInCh];
     const int tid = threadIdx.x;
-    if (tid == 0) {
-#pragma unroll
-        for (int a = 0; a < A; ++a)
-#pragma unroll
-            for (int b = 0; b < A; ++b) sBT[a][b] = mt.BT[a][b];
-    }
-    const int n_cb = (g.C_pad + kInCh - 1) / kInCh;
-    int bx = blockIdx.x;
+    const int per_xcd = (int)(gridDim.x / kXcdCount);
+    const int w = (int)(blockIdx.x % kXcdCount) * per_xcd + (int)(blockIdx.x / kXcdCount);
+    if (w >= n_blocks) return;                      // whole block: before any barrier
+    const int n_cb = g.C_pad / kInCh;
+    int bx = w;
     const int c0 = (bx % n_cb) * kInCh;
     bx /= n_cb;
     const int tb = bx % n_twb;
@@ -221,86 +264,67 @@ __global__ __launch_bounds__(512) void input_transform_kernel(const float* __res
     const int ntw = min(twb, g.Tw - tw0);
     const int wl = ntw * M + R - 1;               // columns actually needed
     const int row0 = th * M - g.pad, col0 = tw0 * M - g.pad;
-
-    // stage: each thread owns fixed (row a, column col) positions and walks
-    // the channels, so consecutive threads read contiguous row segments and
-    // the per-load address advances by one channel plane
-    {
-        const size_t hw = in_vgpr((size_t)g.H * g.W);
-        const int cstride = in_vgpr(ch_stride);
-        const int nch = min(kInCh, g.C - c0);      // channels present (may be <= 0)
-        for (int ac = tid; ac < A * wl; ac += nthr) {
-            const int a = ac / wl, col = ac - a * wl;
-            const int gi = row0 + a, gj = col0 + col;
-            const bool inside = gi >= 0 && gi < g.H && gj >= 0 && gj < g.W;
-            const float* src = x + (((size_t)n * g.C + c0) * g.H + (inside ? gi : 0)) * g.W + (inside ? gj : 0);
-            float* dst = lds + a * row_w + col;
-            for (int cb = 0; cb < kInCh; cb += kBatch) {
-                float v[kBatch];
+    if (tid == 0) {
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u)
-                    v[u] = (inside && cb + u < nch) ? src[(size_t)(cb + u) * hw] : 0.0f;
+        for (int a = 0; a < A; ++a) {
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) dst[(cb + u) * cstride] = v[u];
-            }
+            for (int b = 0; b < A; ++b) sBT[a][b] = mt.BT[a][b];
+            sdB[a] = ex.dB[a];
         }
+    }
+    if (DT != kF32 && tid < kInCh) stc[tid] = c0 + tid < g.C ? t_tab[c0 + tid] : 0;
+
+    // stage the band (channel tail handled apart so that the full case
+    // carries no per-channel conditions)
+    const int nch = min(kInCh, g.C - c0);          // channels present (may be <= 0)
+    if (nch == kInCh)
+        stage_band<A, true>(x, lds, g, n, c0, nch, row0, col0, wl, row_w, ch_stride);
+    else
+        stage_band<A, false>(x, lds, g, n, c0, nch, row0, col0, wl, row_w, ch_stride);
+    __syncthreads();
+
+    // pass 1: T1 = B^T d, column by column, in place
+    for (int q = tid; q < kInCh * wl; q += kInThreads) {
+        const int ch = q / wl, col = q - ch * wl;
+        float* colp = lds + ch * ch_stride + col;
+        float d[A];
+#pragma unroll
+        for (int l = 0; l < A; ++l) d[l] = colp[l * row_w];
+        float t1[A];
+#pragma unroll
+        for (int i = 0; i < A; ++i) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int l = 0; l < A; ++l) acc = __builtin_fmaf(sBT[i][l], d[l], acc);
+            t1[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < A; ++i) colp[i * row_w] = t1[i];
     }
     __syncthreads();
 
-    const int c = tid & (kInCh - 1), t = tid / kInCh;
-    const int gc = c0 + c;
-    if (t >= ntw || gc >= g.C_pad) return;
-    const int tcv = (DT != kF32 && gc < g.C) ? t_tab[gc] : 0;
-    const float* src = lds + c * ch_stride + t * M;
-    float d[A][A];
-#pragma unroll
-    for (int a = 0; a < A; ++a)
-#pragma unroll
-        for (int b = 0; b < A; ++b) d[a][b] = src[a * row_w + b];
-    // T1 = B^T d: row i of B^T (LDS broadcast), zero entries skipped
-    float t1[A][A];
-#pragma unroll
-    for (int i = 0; i < A; ++i) {
-#pragma unroll
-        for (int b = 0; b < A; ++b) t1[i][b] = 0.0f;
-        float brow[A];
-#pragma unroll
-        for (int l = 0; l < A; ++l) brow[l] = sBT[i][l];
-#pragma unroll
-        for (int l = 0; l < A; ++l)
-            if (nz(nzm.bt, i * A + l)) {
-#pragma unroll
-                for (int b = 0; b < A; ++b) t1[i][b] = __builtin_fmaf(brow[l], d[l][b], t1[i][b]);
-            }
-    }
-    const unsigned p = ((unsigned)n * g.Th + th) * g.Tw + tw0 + t;
-    const unsigned off = p * (unsigned)g.C_pad + gc;            // offset inside one e plane
-    const size_t plane = in_vgpr((size_t)g.P_pad * g.C_pad);
+    // pass 2: V = T1 B, row by row; scaling, rounding, stores
     T* V = reinterpret_cast<T*>(Vout);
-    int sv[A];
+    const size_t plane = in_vgpr((size_t)g.P_pad * g.C_pad);
+    for (int q = tid; q < kInCh * ntw * A; q += kInThreads) {
+        const int ch = q % kInCh, rest = q / kInCh;
+        const int t = rest / A, i = rest - t * A;
+        const int gc = c0 + ch;
+        const float* rowp = lds + ch * ch_stride + i * row_w + t * M;
+        float r[A];
 #pragma unroll
-    for (int i = 0; i < A; ++i) sv[i] = gc < g.C ? ex.dB[i] + tcv : 0;
-    // V = T1 B one column j at a time: V[i][j] = sum_l T1[i][l] B^T[j][l]
+        for (int l = 0; l < A; ++l) r[l] = rowp[l];
+        const int sv = (DT != kF32 && gc < g.C) ? sdB[i] + stc[ch] : 0;
+        const unsigned p = ((unsigned)n * g.Th + th) * g.Tw + tw0 + t;
+        T* Vp = V + (size_t)(i * A) * plane + ((size_t)p * g.C_pad + gc);
 #pragma unroll
-    for (int j = 0; j < A; ++j) {
-        float brow[A];
+        for (int j = 0; j < A; ++j) {
+            float acc = 0.0f;
 #pragma unroll
-        for (int l = 0; l < A; ++l) brow[l] = sBT[j][l];
-        float col[A];
-#pragma unroll
-        for (int i = 0; i < A; ++i) col[i] = 0.0f;
-#pragma unroll
-        for (int l = 0; l < A; ++l)
-            if (nz(nzm.bt, j * A + l)) {
-#pragma unroll
-                for (int i = 0; i < A; ++i) col[i] = __builtin_fmaf(brow[l], t1[i][l], col[i]);
-            }
-#pragma unroll
-        for (int i = 0; i < A; ++i) {
-            float v = col[i];
-            if (DT != kF32) v = ldexpf(v, gc < g.C ? -floor_half(sv[i] + ex.dB[j]) : 0);
-            T* Ve = V + (size_t)(i * A + j) * plane;
-            Ve[off] = Elem<DT>::from_f32(v);
+            for (int l = 0; l < A; ++l) acc = __builtin_fmaf(sBT[j][l], r[l], acc);
+            if (DT != kF32) acc = ldexpf(acc, gc < g.C ? -floor_half(sv + ex.dB[j]) : 0);
+            *Vp = Elem<DT>::from_f32(acc);
+            Vp += plane;
         }
     }
 }
@@ -473,24 +497,22 @@ static int filter_impl(const Plan& p, const float* w, const float* x_absmax, voi
     if (L.dtype != WG_F32) {
         hipLaunchKernelGGL((filter_absmax_kernel<R * R>), dim3((unsigned)((L.C_pad + 63) / 64), (unsigned)kchunks),
                            dim3(256), 0, s, w, part, L.K, L.C, L.C_pad);
-        int st = last_launch("filter_absmax_kernel");
-        if (st != WG_OK) return st;
-        hipLaunchKernelGGL(channel_exponent_kernel, dim3((unsigned)((L.C_pad + 255) / 256)), dim3(256), 0, s,
-                           part, x_absmax, s_tab, t_tab, ex, L.alpha, L.C, L.C_pad, kchunks);
-        st = last_launch("channel_exponent_kernel");
+        const int st = last_launch("filter_absmax_kernel");
         if (st != WG_OK) return st;
     }
-    const long total = (long)L.alpha * L.K_pad * L.C_pad;
-    const dim3 grid((unsigned)((total + 255) / 256));
+    const dim3 grid((unsigned)((L.C_pad + 63) / 64), (unsigned)(L.K_pad / 4));
     switch (L.dtype) {
         case WG_F32:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, w, U, t_tab, mt, nzm, ex, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, w, U, part, x_absmax,
+                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
             break;
         case WG_F16:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16>), grid, dim3(256), 0, s, w, U, t_tab, mt, nzm, ex, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16>), grid, dim3(256), 0, s, w, U, part, x_absmax,
+                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
             break;
         default:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16>), grid, dim3(256), 0, s, w, U, t_tab, mt, nzm, ex, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16>), grid, dim3(256), 0, s, w, U, part, x_absmax,
+                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
             break;
     }
     return last_launch("filter_transform_kernel");
@@ -518,36 +540,42 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const NzMasks nzm = pack_masks(p);
     RowExps ex{};
     for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
-    // at most 8 tiles of a tile row per block, split evenly, and at most
-    // 128 KB of staged rows
-    int nsplit = (L.Tw + 7) / 8, twb = 0, row_w = 0, ch_stride = 0;
+    // as many tiles of a tile row per block as fit in 40 KB of staged rows,
+    // split evenly; the channel stride is 33 mod 64 words, so neither the
+    // column pass (lanes along columns) nor the row pass (lanes along
+    // channels) has LDS bank conflicts
+    int nsplit = 1, twb = 0, row_w = 0, ch_stride = 0;
     size_t lds_bytes = 0;
     for (;; ++nsplit) {
         twb = (L.Tw + nsplit - 1) / nsplit;
         row_w = twb * M + R - 1;
         ch_stride = A * row_w;
-        if ((ch_stride & 1) == 0) ch_stride += 1;            // odd stride: no LDS bank conflicts
+        ch_stride += (33 - ch_stride % 64 + 64) % 64;
         lds_bytes = (size_t)kInCh * ch_stride * sizeof(float);
-        if (lds_bytes <= 128 * 1024 || twb == 1) break;
+        if (lds_bytes <= 40 * 1024 || twb == 1) break;
     }
     if (lds_bytes > 128 * 1024) return fail(WG_EUNSUPPORTED, "input transform: tile too large for LDS");
+    if (L.C_pad % kInCh != 0) return fail(WG_EUNSUPPORTED, "input transform: channel padding");
     const int n_twb = (L.Tw + twb - 1) / twb;
-    const dim3 grid((unsigned)((long)L.N * L.Th * n_twb * ((L.C_pad + kInCh - 1) / kInCh)));
-    const dim3 block((unsigned)((kInCh * twb + 63) / 64 * 64));
+    const long n_blocks = (long)L.N * L.Th * n_twb * (L.C_pad / kInCh);
+    if (n_blocks > (1L << 30)) return fail(WG_EUNSUPPORTED, "input transform: grid too large");
+    const dim3 grid((unsigned)((n_blocks + kXcdCount - 1) / kXcdCount * kXcdCount));
+    const dim3 block(kInThreads);
     const int32_t* t_tab = reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.chan_offset);
     void* V = static_cast<char*>(ws) + L.v_offset;
+    const int nb = (int)n_blocks;
     switch (L.dtype) {
         case WG_F32:
             allow_lds(input_transform_kernel<M, R, kF32>, lds_bytes);
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kF32>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride);
+            hipLaunchKernelGGL((input_transform_kernel<M, R, kF32>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride, nb);
             break;
         case WG_F16:
             allow_lds(input_transform_kernel<M, R, kF16>, lds_bytes);
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride);
+            hipLaunchKernelGGL((input_transform_kernel<M, R, kF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride, nb);
             break;
         default:
             allow_lds(input_transform_kernel<M, R, kBF16>, lds_bytes);
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kBF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride);
+            hipLaunchKernelGGL((input_transform_kernel<M, R, kBF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride, nb);
             break;
     }
     return last_launch("input_transform_kernel");
