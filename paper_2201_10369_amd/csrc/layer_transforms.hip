@@ -332,10 +332,12 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
 // ---------------------------------------------------------------------------
 // Output transform Y = A^T M A.  A block covers one output channel k and
 // `nb` consecutive tile rows ("bands", band = n*Th + th).  Each thread
-// transforms one tile and leaves its in-range outputs in LDS laid out exactly
-// like the image rows (pitch Wout); the rows of consecutive bands of one
-// image are contiguous in y, so the block then copies each image's run with
-// consecutive threads.
+// transforms one tile (reading it one row of M at a time, consecutive
+// threads at consecutive tiles of each plane) and leaves its in-range
+// outputs in LDS laid out exactly like the image rows (pitch Wout); the rows
+// of consecutive bands of one image are contiguous in y, so the block then
+// copies each image's run with consecutive threads.  Zero entries of A^T are
+// not skipped (fma(0, x, acc) == acc for finite x).
 // ---------------------------------------------------------------------------
 template <int M, int R>
 __global__ __launch_bounds__(256) void output_transform_kernel(const float* __restrict__ Mbuf,
@@ -362,30 +364,28 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
         const int bl = it / g.Tw, tw = it - bl * g.Tw;
         // offset inside one plane of M; the alpha^2 planes are plane_stride apart
         const unsigned off = (unsigned)k * g.P_pad + (unsigned)(band0 + bl) * g.Tw + tw;
+        // Z = A^T M, streaming the rows of M (plane a*A + b holds M[a][b])
         const size_t pstride = in_vgpr((size_t)plane_stride);
-        float mm[A][A];
-#pragma unroll
-        for (int a = 0; a < A; ++a)
-#pragma unroll
-            for (int b = 0; b < A; ++b) {
-                const float* Me = Mbuf + (size_t)(a * A + b) * pstride;
-                mm[a][b] = Me[off];
-            }
-        // Z = A^T M  (M x A), rows of A^T from LDS, zero entries skipped
+        const float* mp = Mbuf + off;
         float z[M][A];
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
+        for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int b = 0; b < A; ++b) z[i][b] = 0.0f;
-            float arow[A];
 #pragma unroll
-            for (int l = 0; l < A; ++l) arow[l] = sAT[i][l];
+        for (int a = 0; a < A; ++a) {
+            float row[A];
 #pragma unroll
-            for (int l = 0; l < A; ++l)
-                if (nz(nzm.at, i * A + l)) {
+            for (int b = 0; b < A; ++b) {
+                row[b] = *mp;
+                mp += pstride;
+            }
 #pragma unroll
-                    for (int b = 0; b < A; ++b) z[i][b] = __builtin_fmaf(arow[l], mm[l][b], z[i][b]);
-                }
+            for (int i = 0; i < M; ++i) {
+                const float av = sAT[i][a];
+#pragma unroll
+                for (int b = 0; b < A; ++b) z[i][b] = __builtin_fmaf(av, row[b], z[i][b]);
+            }
         }
         const int th = (band0 + bl) % g.Th;
         const int rows = min(M, g.Hout - th * M);
@@ -402,10 +402,8 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
             for (int i = 0; i < M; ++i) col[i] = 0.0f;
 #pragma unroll
             for (int l = 0; l < A; ++l)
-                if (nz(nzm.at, j * A + l)) {
 #pragma unroll
-                    for (int i = 0; i < M; ++i) col[i] = __builtin_fmaf(arow[l], z[i][l], col[i]);
-                }
+                for (int i = 0; i < M; ++i) col[i] = __builtin_fmaf(arow[l], z[i][l], col[i]);
 #pragma unroll
             for (int i = 0; i < M; ++i)
                 if (i < rows && j < cols) dst[i * g.Wout + j] = col[i];
