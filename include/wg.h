@@ -158,6 +158,24 @@ int wg_plan_layout(const wg_plan* plan, wg_layout* out);
 /* The float32 matrices of the plan (host outputs, sizes as wg_transforms). */
 int wg_plan_matrices(const wg_plan* plan, float* AT, float* G, float* BT);
 
+/* Tuning of a plan's Hadamard GEMM (host only, no effect on results): each
+ * thread block takes `tiles_per_block` consecutive output tiles (1..16) and
+ * keeps its load pipeline running across them.  wg_plan_gemm_tiles returns
+ * the current value (>= 1), or an error code.  Default 1.
+ * Errors: WG_EINVAL (null plan, value outside 1..16). */
+int wg_plan_set_gemm_tiles(wg_plan* plan, int tiles_per_block);
+int wg_plan_gemm_tiles(const wg_plan* plan);
+
+/* Autotuner for the same knob: runs the plan's Hadamard GEMM on the caller's
+ * transformed operands (U from wg_transform_filters, V' in `ws` from
+ * wg_input_transform) for each candidate in {1, 2, 3, 4, 6, 8}, `reps` timed
+ * launches each after one warm-up, and keeps the fastest.  Synchronous on
+ * `stream`; overwrites the M part of the workspace (run wg_hadamard_gemm
+ * again afterwards).  Writes the chosen value to *chosen if non-null.
+ * Errors: WG_EINVAL, WG_EWORKSPACE, WG_EHIP. */
+int wg_plan_autotune_gemm(wg_plan* plan, const void* U, void* ws, size_t ws_bytes, int reps,
+                          int* chosen, wg_stream_t stream);
+
 /* ------------------------------------------------------------------------
  * Layer (device, asynchronous).  Section 4 eq. conv_2d applied tile by tile
  * to the layer of eq. conv; Section 4.1 notes that the filter and input

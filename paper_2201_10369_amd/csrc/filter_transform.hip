@@ -1,0 +1,229 @@
+// Filter transform U = G g G^T of the Winograd layer on gfx950
+// (arXiv:2201.10369, Section 4, eq. conv_2d), with the per-channel exponent
+// part of the 16-bit scaling, and the per-channel max |x| helper.
+//
+// Each two-sided product P X P^T is evaluated as (P X) first and then
+// (P X) P^T, every inner product accumulated in ascending index order with one
+// fused multiply-add per term (acc <- fma(p, x, acc) from acc = 0).  The
+// float32 error of this evaluation is what gets scored against the float64
+// direct convolution (arXiv:2201.10369, Section 6).
+//
+// Layout: U'[e][k][c], e = tile element, c contiguous.
+#include <hip/hip_runtime.h>
+
+#include "wg_layer_common.h"
+
+#pragma clang fp contract(off)
+
+namespace wg {
+
+// ---------------------------------------------------------------------------
+// 16-bit Hadamard stage: partial maxima of |w| over chunks of kKChunk
+// filters for 64 channels per block (coalesced: a wave reads 64 consecutive
+// channels' r*r taps).  part[kc][c] for filter chunk kc.
+// ---------------------------------------------------------------------------
+constexpr int kKChunk = 8;
+
+template <int RR>
+__global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restrict__ w,
+                                                            float* __restrict__ part, int K, int C,
+                                                            int C_pad) {
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, kq = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
+    const int kc = blockIdx.y;
+    float mx = 0.0f;
+    if (c < C) {
+        float v[kKChunk / 4][RR];
+#pragma unroll
+        for (int i = 0; i < kKChunk / 4; ++i) {
+            const int k = kc * kKChunk + kq + 4 * i;
+#pragma unroll
+            for (int t = 0; t < RR; ++t) v[i][t] = k < K ? w[((size_t)k * C + c) * RR + t] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < kKChunk / 4; ++i)
+#pragma unroll
+            for (int t = 0; t < RR; ++t) mx = fmaxf(mx, fabsf(v[i][t]));
+    }
+    red[kq][cl] = mx;
+    __syncthreads();
+    if (kq == 0 && c < C_pad)
+        part[(size_t)kc * C_pad + c] = fmaxf(fmaxf(red[0][cl], red[1][cl]), fmaxf(red[2][cl], red[3][cl]));
+}
+
+// ---------------------------------------------------------------------------
+// Filter transform U = G g G^T.  A block covers 64 channels (the lanes of a
+// wave) and four filters (one per wave); each thread transforms one filter
+// channel g = w[k][c] into all alpha x alpha entries, so every store of
+// U'[e][k][.] is a contiguous run of 64 channels.
+//
+// For the 16-bit stage the block first finishes the per-channel exponent
+// part t[c] = E(x_absmax[c]) - E(max_k |w[k][c]|) from the partial maxima of
+// all filter chunks (every block of a channel group repeats this small
+// reduction, so no second launch is needed), scales entry (i, j) by 2^s with
+// s = floor((dB[i] + dB[j] + t[c]) / 2) before rounding, and the blocks of
+// the first filter group also write t and the table s[e][c].
+// ---------------------------------------------------------------------------
+template <int M, int R, int DT>
+__global__ __launch_bounds__(256) void filter_transform_kernel(const float* __restrict__ w,
+                                                               void* __restrict__ Uout,
+                                                               const float* __restrict__ part,
+                                                               const float* __restrict__ x_absmax,
+                                                               int32_t* __restrict__ s_tab,
+                                                               int32_t* __restrict__ t_tab, int kchunks,
+                                                               Mats<M, R> mt, NzMasks nzm, RowExps ex, Geo g) {
+    constexpr int A = M + R - 1;
+    using T = typename Elem<DT>::T;
+    __shared__ float sG[A][R];
+    __shared__ float sred[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int k = blockIdx.y * 4 + wv;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int u = 0; u < R; ++u) sG[a][u] = mt.G[a][u];
+    }
+    int tc = 0;
+    if (DT != kF32) {
+        float aw = 0.0f;
+        if (c < g.C) {
+#pragma unroll 8
+            for (int q = wv; q < kchunks; q += 4) aw = fmaxf(aw, part[(size_t)q * g.C_pad + c]);
+        }
+        sred[wv][lane] = aw;
+    }
+    __syncthreads();
+    if (DT != kF32 && c < g.C) {
+        const float mw = fmaxf(fmaxf(sred[0][lane], sred[1][lane]), fmaxf(sred[2][lane], sred[3][lane]));
+        tc = bin_exp(x_absmax != nullptr ? x_absmax[c] : 1.0f) - bin_exp(mw);
+    }
+    if (DT != kF32 && blockIdx.y == 0 && c < g.C_pad) {
+        if (wv == 0) t_tab[c] = tc;
+#pragma unroll
+        for (int e1 = 0; e1 < A; ++e1)
+            if ((e1 & 3) == wv) {
+#pragma unroll
+                for (int e2 = 0; e2 < A; ++e2)
+                    s_tab[(size_t)(e1 * A + e2) * g.C_pad + c] = c < g.C ? floor_half(ex.dB[e1] + ex.dB[e2] + tc) : 0;
+            }
+    }
+    if (c >= g.C_pad) return;
+    const bool live = k < g.K && c < g.C;
+    float gg[R][R];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+        for (int v = 0; v < R; ++v) gg[u][v] = live ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f;
+    T* U = reinterpret_cast<T*>(Uout);
+    const unsigned off = (unsigned)k * g.C_pad + c;
+    const size_t plane = in_vgpr((size_t)g.K_pad * g.C_pad);
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+        // row i of P1 = G g
+        float p1[R];
+#pragma unroll
+        for (int v = 0; v < R; ++v) p1[v] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (nz(nzm.g, i * R + u)) {
+                const float b = sG[i][u];
+#pragma unroll
+                for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(b, gg[u][v], p1[v]);
+            }
+        const int si = tc + ex.dB[i];
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int v = 0; v < R; ++v)
+                if (nz(nzm.g, j * R + v)) acc = __builtin_fmaf(sG[j][v], p1[v], acc);
+            if (DT != kF32) acc = ldexpf(acc, c < g.C ? floor_half(si + ex.dB[j]) : 0);
+            T* Ue = U + (size_t)(i * A + j) * plane;
+            Ue[off] = Elem<DT>::from_f32(acc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-channel max |x|
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void channel_absmax_kernel(const float* __restrict__ x, int N, int C,
+                                                             int HW, float* __restrict__ out) {
+    __shared__ float red[256];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    float mx = 0.0f;
+    for (int n = 0; n < N; ++n) {
+        const float* src = x + ((size_t)n * C + c) * HW;
+        for (int q = tid; q < HW; q += 256) mx = fmaxf(mx, fabsf(src[q]));
+    }
+    red[tid] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) out[c] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int M, int R>
+static int filter_impl(const Plan& p, const float* w, const float* x_absmax, void* U, hipStream_t s) {
+    const wg_layout& L = p.L;
+    const Geo g = make_geo(L);
+    const Mats<M, R> mt = pack_mats<M, R>(p);
+    const NzMasks nzm = pack_masks(p);
+    RowExps ex{};
+    for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
+    char* Ub = static_cast<char*>(U);
+    int32_t* s_tab = reinterpret_cast<int32_t*>(Ub + L.scale_offset);
+    int32_t* t_tab = reinterpret_cast<int32_t*>(Ub + L.chan_offset);
+    float* part = reinterpret_cast<float*>(Ub + L.chan_offset + round_up((size_t)L.C_pad * 4, 256));
+    const int kchunks = (L.K + kKChunk - 1) / kKChunk;
+    if (L.dtype != WG_F32) {
+        hipLaunchKernelGGL((filter_absmax_kernel<R * R>), dim3((unsigned)((L.C_pad + 63) / 64), (unsigned)kchunks),
+                           dim3(256), 0, s, w, part, L.K, L.C, L.C_pad);
+        const int st = last_launch("filter_absmax_kernel");
+        if (st != WG_OK) return st;
+    }
+    const dim3 grid((unsigned)((L.C_pad + 63) / 64), (unsigned)(L.K_pad / 4));
+    switch (L.dtype) {
+        case WG_F32:
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, w, U, part, x_absmax,
+                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
+            break;
+        case WG_F16:
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16>), grid, dim3(256), 0, s, w, U, part, x_absmax,
+                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
+            break;
+        default:
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16>), grid, dim3(256), 0, s, w, U, part, x_absmax,
+                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
+            break;
+    }
+    return last_launch("filter_transform_kernel");
+}
+
+int launch_filter_transform(const Plan& p, const float* w, const float* x_absmax, void* U, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+#define WG_CASE_filter(MM, RR) case MM * 16 + RR: return filter_impl<MM, RR>(p, w, x_absmax, U, s);
+    WG_DISPATCH(filter)
+#undef WG_CASE_filter
+}
+
+int launch_channel_absmax(const float* x, int N, int C, int HW, float* out, void* stream) {
+    hipLaunchKernelGGL(channel_absmax_kernel, dim3(C), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       x, N, C, HW, out);
+    return last_launch("channel_absmax_kernel");
+}
+
+int hip_check(int hip_err, const char* what) {
+    if (hip_err == (int)hipSuccess) return WG_OK;
+    return fail(WG_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)hip_err));
+}
+
+}  // namespace wg

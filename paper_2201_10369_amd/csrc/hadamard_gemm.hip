@@ -14,9 +14,10 @@
 // in a 2 x 2 arrangement, each wave a (BM/2) x (BN/2) sub-tile made of 32 x 32
 // MFMA blocks.  The contraction runs in steps of BK elements (128 bytes of
 // each operand row) through double-buffered LDS, with the next step's global
-// loads in flight while the current one is multiplied.  Block ids are mapped
-// so that consecutive work items (same e, neighbouring tiles) run on the same
-// XCD and share its L2.
+// loads in flight while the current one is multiplied; a block may take
+// several consecutive tiles, and the pipeline then runs on across the tile
+// boundaries.  Block ids are mapped so that consecutive work items (same e,
+// neighbouring tiles) run on the same XCD and share its L2.
 //
 // Element types: float32 (v_mfma_f32_32x32x2_f32), float16 and bfloat16 with
 // float32 accumulation (v_mfma_f32_32x32x16_{f16,bf16}).
@@ -34,6 +35,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXcds = 8;
+// Word 3 of a raw buffer resource on gfx9-family chips (dword data format,
+// no swizzle); out-of-range stores are dropped by the hardware.
+constexpr int kBufferWord3 = 0x00020000;
 
 // Bytes per operand row per contraction step, and LDS row pitch (16 bytes of
 // padding keep the 16-byte LDS reads of 8 consecutive rows on distinct banks).
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
                                                             const char* __restrict__ V,
                                                             float* __restrict__ Mout, int K_pad,
                                                             int P_pad, int C_pad, int nKb, int nPb,
-                                                            int total, int per_xcd) {
+                                                            int total, int tpb, int per_xcd) {
     constexpr int WM = BM / 2, WN = BN / 2;          // wave sub-tile
     constexpr int FM = WM / 32, FN = WN / 32;         // 32 x 32 blocks per wave
     constexpr int ELEM = MfmaOp<DT>::kElem;
@@ -112,26 +116,31 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
 
     __shared__ __attribute__((aligned(16))) char smem[2 * (BM + BN) * kPitchBytes];
 
-    // XCD-aware work mapping
+    // XCD-aware work mapping: block w takes tiles w*tpb .. w*tpb + tpb - 1
     const int b = blockIdx.x;
     const int w = (b % kXcds) * per_xcd + b / kXcds;
-    if (w >= total) return;
-    const int kb = w % nKb;
-    const int t2 = w / nKb;
-    const int pb = t2 % nPb;
-    const int e = t2 / nPb;
+    const int t0 = w * tpb;
+    if (t0 >= total) return;
+    const int nt = min(tpb, total - t0);
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;   // wave index is uniform
     const int wm = wave >> 1, wn = wave & 1;
     const int half = lane >> 5, l32 = lane & 31;
 
     const size_t row_bytes = (size_t)C_pad * ELEM;
-    const char* Ag = U + ((size_t)e * K_pad + (size_t)kb * BM) * row_bytes;
-    const char* Bg = V + ((size_t)e * P_pad + (size_t)pb * BN) * row_bytes;
+    // tile t -> (e, pb, kb) with kb fastest
+    auto a_tile = [&](int t) {
+        const int kb = t % nKb, e = t / (nKb * nPb);
+        return U + ((size_t)e * K_pad + (size_t)kb * BM) * row_bytes;
+    };
+    auto b_tile = [&](int t) {
+        const int pb = (t / nKb) % nPb, e = t / (nKb * nPb);
+        return V + ((size_t)e * P_pad + (size_t)pb * BN) * row_bytes;
+    };
 
     u32x4 ra[A_PER_T], rb[B_PER_T];
-    auto gload = [&](int step) {
+    auto gload = [&](const char* Ag, const char* Bg, int step) {
         const size_t koff = (size_t)step * kStepBytes;
 #pragma unroll
         for (int i = 0; i < A_PER_T; ++i) {
@@ -163,50 +172,74 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
         }
     };
 
-    f32x16 acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int lane_off = ((4 * half) * P_pad + wn * WN + l32) * 4;   // bytes, inside a tile
 
+    // one pipeline over all (tile, step) pairs of the block: the next pair's
+    // global loads are in flight while the current pair is multiplied, also
+    // across tile boundaries, where the finished tile is written out
     const int nsteps = (int)(row_bytes / kStepBytes);
-    gload(0);
+    const int niter = nt * nsteps;
+    const char* nA = a_tile(t0);
+    const char* nB = b_tile(t0);
+    gload(nA, nB, 0);
     sstore(0);
     __syncthreads();
-    for (int st = 0; st < nsteps; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nsteps) gload(st + 1);
-        const char* As = smem + buf * (BM + BN) * kPitchBytes;
-        const char* Bs = As + BM * kPitchBytes;
+    int it = 0;
+    for (int t = 0; t < nt; ++t) {
+        f32x16 acc[FM][FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-            const char* arow = As + (wm * WM + i * 32 + l32) * kPitchBytes;
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const char* brow = Bs + (wn * WN + j * 32 + l32) * kPitchBytes;
-                MfmaOp<DT>::step(arow, brow, half, acc[i][j]);
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+        for (int st = 0; st < nsteps; ++st, ++it) {
+            const int buf = it & 1;
+            const bool more = it + 1 < niter;
+            if (more) {
+                if (st + 1 == nsteps) {
+                    nA = a_tile(t0 + t + 1);
+                    nB = b_tile(t0 + t + 1);
+                }
+                gload(nA, nB, st + 1 == nsteps ? 0 : st + 1);
             }
+            const char* As = smem + buf * (BM + BN) * kPitchBytes;
+            const char* Bs = As + BM * kPitchBytes;
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const char* arow = As + (wm * WM + i * 32 + l32) * kPitchBytes;
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const char* brow = Bs + (wn * WN + j * 32 + l32) * kPitchBytes;
+                    MfmaOp<DT>::step(arow, brow, half, acc[i][j]);
+                }
+            }
+            if (more) sstore(buf ^ 1);
+            __syncthreads();
         }
-        if (st + 1 < nsteps) sstore(buf ^ 1);
-        __syncthreads();
+        // 32 x 32 accumulator layout: lane holds column (lane % 32) and, in
+        // register r, row 8*(r/4) + 4*(lane/32) + r%4.  Stores go through a
+        // buffer resource on the tile's base: the lane part of the offset is
+        // one VGPR, the row part a scalar, so no 64-bit address is formed
+        // per store.
+        const int ct = t0 + t;
+        const int kb = ct % nKb, pb = (ct / nKb) % nPb, e = ct / (nKb * nPb);
+        float* Mg = Mout + ((size_t)e * K_pad + (size_t)kb * BM) * P_pad + (size_t)pb * BN;
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(Mg, 0, BM * P_pad * 4, kBufferWord3);
+        int rstride = P_pad * 4;
+        asm volatile("" : "+s"(rstride));            // keep the row offsets out of the loop
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int srow = wm * WM + i * 32 + 8 * (r >> 2) + (r & 3);
+                    const float v = acc[i][j][r];    // a named copy: element lvalues are not bit-castable
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc, lane_off + j * 128,
+                                                          srow * rstride, 0);
+                }
     }
-
-    // 32 x 32 accumulator layout: lane holds column (lane % 32) and, in
-    // register r, row 8*(r/4) + 4*(lane/32) + r%4.
-    float* Mg = Mout + ((size_t)e * K_pad + (size_t)kb * BM) * P_pad + (size_t)pb * BN;
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int col = wn * WN + j * 32 + l32;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = wm * WM + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                Mg[(size_t)row * P_pad + col] = acc[i][j][r];
-            }
-        }
 }
 
 template <int BM, int BN, int DT>
@@ -215,11 +248,15 @@ static int gemm_launch(const Plan& p, const void* U, void* ws, hipStream_t s) {
     const int nKb = L.K_pad / BM, nPb = L.P_pad / BN;
     const long total = (long)L.alpha * L.alpha * nKb * nPb;
     if (total > (1L << 30)) return fail(WG_EUNSUPPORTED, "hadamard gemm: too many tiles");
-    const int per_xcd = (int)((total + kXcds - 1) / kXcds);
+    // the epilogue addresses one tile with 32-bit byte offsets
+    if ((long)BM * L.P_pad * 4 >= (1L << 31)) return fail(WG_EUNSUPPORTED, "hadamard gemm: tile rows too long");
+    const int tpb = p.gemm_tpb > 0 ? p.gemm_tpb : 1;
+    const long blocks = (total + tpb - 1) / tpb;
+    const int per_xcd = (int)((blocks + kXcds - 1) / kXcds);
     const char* V = static_cast<const char*>(ws) + L.v_offset;
     float* Mb = reinterpret_cast<float*>(static_cast<char*>(ws) + L.m_offset);
     hipLaunchKernelGGL((hadamard_gemm_kernel<BM, BN, DT>), dim3((unsigned)(per_xcd * kXcds)), dim3(256), 0, s,
-                       static_cast<const char*>(U), V, Mb, L.K_pad, L.P_pad, L.C_pad, nKb, nPb, (int)total,
+                       static_cast<const char*>(U), V, Mb, L.K_pad, L.P_pad, L.C_pad, nKb, nPb, (int)total, tpb,
                        per_xcd);
     return hip_check((int)hipGetLastError(), "hadamard_gemm_kernel");
 }
@@ -240,6 +277,42 @@ int launch_hadamard_gemm(const Plan& p, const void* U, void* ws, void* stream) {
         case WG_F16: return gemm_dtype<kF16>(p, U, ws, s);
         default: return gemm_dtype<kBF16>(p, U, ws, s);
     }
+}
+
+int autotune_hadamard_gemm(Plan& p, const void* U, void* ws, int reps, int* chosen, void* stream) {
+    static const int kCand[] = {1, 2, 3, 4, 6, 8};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    int st = hip_check((int)hipEventCreate(&e0), "hipEventCreate");
+    if (st != WG_OK) return st;
+    st = hip_check((int)hipEventCreate(&e1), "hipEventCreate");
+    if (st != WG_OK) {
+        (void)hipEventDestroy(e0);
+        return st;
+    }
+    const int keep = p.gemm_tpb;
+    int best = keep;
+    float best_ms = -1.0f;
+    for (int t : kCand) {
+        p.gemm_tpb = t;
+        st = launch_hadamard_gemm(p, U, ws, stream);                 // warm-up
+        if (st == WG_OK) st = hip_check((int)hipEventRecord(e0, s), "hipEventRecord");
+        for (int i = 0; i < reps && st == WG_OK; ++i) st = launch_hadamard_gemm(p, U, ws, stream);
+        if (st == WG_OK) st = hip_check((int)hipEventRecord(e1, s), "hipEventRecord");
+        if (st == WG_OK) st = hip_check((int)hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.0f;
+        if (st == WG_OK) st = hip_check((int)hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (st != WG_OK) break;
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p.gemm_tpb = st == WG_OK ? best : keep;
+    if (st == WG_OK && chosen) *chosen = best;
+    return st;
 }
 
 }  // namespace wg

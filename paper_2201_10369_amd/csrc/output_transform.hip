@@ -1,0 +1,141 @@
+// Output transform Y = A^T M A of the Winograd layer on gfx950
+// (arXiv:2201.10369, Section 4, eq. conv_2d), applied to every output tile.
+//
+// Each two-sided product P X P^T is evaluated as (P X) first and then
+// (P X) P^T, every inner product accumulated in ascending index order with one
+// fused multiply-add per term (acc <- fma(p, x, acc) from acc = 0).  The
+// float32 error of this evaluation is what gets scored against the float64
+// direct convolution (arXiv:2201.10369, Section 6).
+//
+// Layout: M[e][k][p], p (tile index) contiguous; y is N x K x Hout x Wout.
+#include <hip/hip_runtime.h>
+
+#include "wg_layer_common.h"
+
+#pragma clang fp contract(off)
+
+namespace wg {
+
+// ---------------------------------------------------------------------------
+// Output transform Y = A^T M A.  A block covers one output channel k and
+// `nb` consecutive tile rows ("bands", band = n*Th + th).  Each thread
+// transforms one tile (reading it one row of M at a time, consecutive
+// threads at consecutive tiles of each plane) and leaves its in-range
+// outputs in LDS laid out exactly like the image rows (pitch Wout); the rows
+// of consecutive bands of one image are contiguous in y, so the block then
+// copies each image's run with consecutive threads.  Zero entries of A^T are
+// not skipped (fma(0, x, acc) == acc for finite x).
+// ---------------------------------------------------------------------------
+template <int M, int R>
+__global__ __launch_bounds__(256) void output_transform_kernel(const float* __restrict__ Mbuf,
+                                                               float* __restrict__ y, Mats<M, R> mt,
+                                                               NzMasks nzm, Geo g, int nb,
+                                                               unsigned plane_stride) {
+    constexpr int A = M + R - 1;
+    extern __shared__ float lds[];
+    __shared__ float sAT[M][A];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int b = 0; b < A; ++b) sAT[a][b] = mt.AT[a][b];
+    }
+    __syncthreads();
+    const int k = blockIdx.y;
+    const int band0 = blockIdx.x * nb;
+    const int nbands = g.N * g.Th;
+    const int nbl = min(nb, nbands - band0);
+    const int items = nbl * g.Tw;
+    for (int it = tid; it < items; it += 256) {
+        const int bl = it / g.Tw, tw = it - bl * g.Tw;
+        // offset inside one plane of M; the alpha^2 planes are plane_stride apart
+        const unsigned off = (unsigned)k * g.P_pad + (unsigned)(band0 + bl) * g.Tw + tw;
+        // Z = A^T M, streaming the rows of M (plane a*A + b holds M[a][b])
+        const size_t pstride = in_vgpr((size_t)plane_stride);
+        const float* mp = Mbuf + off;
+        float z[M][A];
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int b = 0; b < A; ++b) z[i][b] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            float row[A];
+#pragma unroll
+            for (int b = 0; b < A; ++b) {
+                row[b] = *mp;
+                mp += pstride;
+            }
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const float av = sAT[i][a];
+#pragma unroll
+                for (int b = 0; b < A; ++b) z[i][b] = __builtin_fmaf(av, row[b], z[i][b]);
+            }
+        }
+        const int th = (band0 + bl) % g.Th;
+        const int rows = min(M, g.Hout - th * M);
+        const int cols = min(M, g.Wout - tw * M);
+        float* dst = lds + (bl * M) * g.Wout + tw * M;
+        // Y = Z A one column j at a time: Y[i][j] = sum_l Z[i][l] A^T[j][l]
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            float arow[A];
+#pragma unroll
+            for (int l = 0; l < A; ++l) arow[l] = sAT[j][l];
+            float col[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) col[i] = 0.0f;
+#pragma unroll
+            for (int l = 0; l < A; ++l)
+#pragma unroll
+                for (int i = 0; i < M; ++i) col[i] = __builtin_fmaf(arow[l], z[i][l], col[i]);
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+                if (i < rows && j < cols) dst[i * g.Wout + j] = col[i];
+        }
+    }
+    __syncthreads();
+    // copy runs: the bands of one image are consecutive rows of plane (n, k)
+    int bl = 0;
+    while (bl < nbl) {
+        const int band = band0 + bl;
+        const int n = band / g.Th, th = band - n * g.Th;
+        const int last = min(nbl, bl + (g.Th - th));          // bands of image n in this block
+        const int row_first = th * M;
+        const int row_end = min(g.Hout, (th + (last - bl)) * M);
+        const int len = (row_end - row_first) * g.Wout;
+        const float* src = lds + bl * M * g.Wout;
+        float* dst = y + (((size_t)n * g.K + k) * g.Hout + row_first) * g.Wout;
+        for (int q = tid; q < len; q += 256) dst[q] = src[q];
+        bl = last;
+    }
+}
+
+template <int M, int R>
+static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
+    const wg_layout& L = p.L;
+    const Geo g = make_geo(L);
+    const Mats<M, R> mt = pack_mats<M, R>(p);
+    const NzMasks nzm = pack_masks(p);
+    int nb = 256 / L.Tw;
+    if (nb < 1) nb = 1;
+    while (nb > 1 && (size_t)nb * M * L.Wout * sizeof(float) > 65536) --nb;
+    const size_t lds_bytes = (size_t)nb * M * L.Wout * sizeof(float);
+    if (lds_bytes > 65536) return fail(WG_EUNSUPPORTED, "output transform: output rows too wide");
+    const int nbands = L.N * L.Th;
+    const dim3 grid((unsigned)((nbands + nb - 1) / nb), (unsigned)L.K);
+    const float* Mbuf = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.m_offset);
+    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(256), lds_bytes, s, Mbuf, y, mt, nzm, g, nb, (unsigned)((size_t)L.K_pad * L.P_pad));
+    return last_launch("output_transform_kernel");
+}
+
+int launch_output_transform(const Plan& p, const void* ws, float* y, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+#define WG_CASE_output(MM, RR) case MM * 16 + RR: return output_impl<MM, RR>(p, ws, y, s);
+    WG_DISPATCH(output)
+#undef WG_CASE_output
+}
+
+}  // namespace wg

@@ -185,6 +185,7 @@ int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, in
     plan->gemm_bm = big ? 128 : 64;
     plan->gemm_bn = big ? 128 : 64;
     plan->gemm_bk = dtype == WG_F32 ? 32 : 64;
+    plan->gemm_tpb = 1;
 
     wg_layout& L = plan->L;
     std::memset(&L, 0, sizeof(L));
@@ -253,6 +254,19 @@ int wg_plan_matrices(const wg_plan* plan, float* AT, float* G, float* BT) {
     return WG_OK;
 }
 
+int wg_plan_set_gemm_tiles(wg_plan* plan, int tiles_per_block) {
+    if (!plan) return fail(WG_EINVAL, "wg_plan_set_gemm_tiles: null plan");
+    if (tiles_per_block < 1 || tiles_per_block > 16)
+        return fail(WG_EINVAL, "wg_plan_set_gemm_tiles: tiles_per_block must be in 1..16");
+    reinterpret_cast<Plan*>(plan)->gemm_tpb = tiles_per_block;
+    return WG_OK;
+}
+
+int wg_plan_gemm_tiles(const wg_plan* plan) {
+    if (!plan) return fail(WG_EINVAL, "wg_plan_gemm_tiles: null plan");
+    return reinterpret_cast<const Plan*>(plan)->gemm_tpb;
+}
+
 int wg_transform_filters(const wg_plan* plan, const float* w, const float* x_absmax, void* U,
                          wg_stream_t stream) {
     if (!plan || !w || !U) return fail(WG_EINVAL, "wg_transform_filters: null pointer");
@@ -283,6 +297,16 @@ int wg_hadamard_gemm(const wg_plan* plan, const void* U, void* ws, size_t ws_byt
     int st = check_ws(p, ws, ws_bytes, "wg_hadamard_gemm");
     if (st != WG_OK) return st;
     return launch_hadamard_gemm(p, U, ws, stream);
+}
+
+int wg_plan_autotune_gemm(wg_plan* plan, const void* U, void* ws, size_t ws_bytes, int reps, int* chosen,
+                          wg_stream_t stream) {
+    if (!plan || !U) return fail(WG_EINVAL, "wg_plan_autotune_gemm: null pointer");
+    if (reps < 1 || reps > 1000) return fail(WG_EINVAL, "wg_plan_autotune_gemm: reps must be in 1..1000");
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    int st = check_ws(p, ws, ws_bytes, "wg_plan_autotune_gemm");
+    if (st != WG_OK) return st;
+    return autotune_hadamard_gemm(p, U, ws, reps, chosen, stream);
 }
 
 int wg_output_transform(const wg_plan* plan, const void* ws, size_t ws_bytes, float* y,

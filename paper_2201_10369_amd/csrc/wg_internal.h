@@ -28,6 +28,7 @@ struct Plan {
     int dB[kMaxAlpha];                 // eB - eG
     // GEMM tiling chosen at plan creation
     int gemm_bm, gemm_bn, gemm_bk;
+    int gemm_tpb;                 // GEMM tiles per block (consecutive, pipelined)
 };
 
 // Exact construction (exact_construct.cpp): entries rounded to nearest float64.
@@ -44,6 +45,9 @@ int launch_filter_transform(const Plan& p, const float* w, const float* x_absmax
 int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws,
                            void* stream);
 int launch_hadamard_gemm(const Plan& p, const void* U, void* ws, void* stream);
+// Times each candidate tiles-per-block value on the caller's operands and
+// keeps the fastest in the plan (synchronous on `stream`).
+int autotune_hadamard_gemm(Plan& p, const void* U, void* ws, int reps, int* chosen, void* stream);
 int launch_output_transform(const Plan& p, const void* ws, float* y, void* stream);
 int launch_channel_absmax(const float* x, int N, int C, int HW, float* out, void* stream);
 int launch_direct_f64(const float* x, const float* w, double* y, int N, int C, int K, int H,

@@ -1,0 +1,95 @@
+// Shared pieces of the layer transform kernels (filter, input, output):
+// geometry passed to kernels, per-row exponent offsets for the 16-bit
+// scaling, host-side packing of the transform matrices into kernel arguments
+// and the launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+#include <set>
+#include <string>
+#include <utility>
+
+#include "wg_device.h"
+#include "wg_internal.h"
+
+namespace wg {
+
+constexpr int kXcdCount = 8;     // XCDs of the chip, each with its own L2
+
+struct Geo {
+    int N, C, K, H, W, pad, Hout, Wout, Th, Tw, P, P_pad, K_pad, C_pad;
+};
+
+inline Geo make_geo(const wg_layout& L) {
+    return Geo{L.N, L.C, L.K, L.H, L.W, L.pad, L.Hout, L.Wout, L.Th, L.Tw, L.P, L.P_pad, L.K_pad, L.C_pad};
+}
+
+struct RowExps {
+    int dB[kMaxAlpha];     // E(|B^T row i|_1) - E(|G row i|_1)
+};
+
+__device__ __forceinline__ int bin_exp(float v) {
+    int e = 0;
+    if (v != 0.0f) frexpf(v, &e);
+    return e;
+}
+
+// floor(d / 2): arithmetic right shift of a two's-complement int
+__device__ __forceinline__ int floor_half(int d) { return d >> 1; }
+
+// ---------------------------------------------------------------------------
+// Host-side packing and launch helpers
+// ---------------------------------------------------------------------------
+inline NzMasks pack_masks(const Plan& p) {
+    NzMasks z{};
+    const int A = p.L.alpha, m = p.L.m, r = p.L.r;
+    for (int q = 0; q < m * A; ++q)
+        if (p.AT[q] != 0.0f) z.at[q >> 6] |= 1ull << (q & 63);
+    for (int q = 0; q < A * r; ++q)
+        if (p.G[q] != 0.0f) z.g[q >> 6] |= 1ull << (q & 63);
+    for (int q = 0; q < A * A; ++q)
+        if (p.BT[q] != 0.0f) z.bt[q >> 6] |= 1ull << (q & 63);
+    return z;
+}
+
+template <int M, int R>
+inline Mats<M, R> pack_mats(const Plan& p) {
+    constexpr int A = M + R - 1;
+    Mats<M, R> mt;
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < A; ++j) mt.AT[i][j] = p.AT[i * A + j];
+    for (int i = 0; i < A; ++i)
+        for (int j = 0; j < R; ++j) mt.G[i][j] = p.G[i * R + j];
+    for (int i = 0; i < A; ++i)
+        for (int j = 0; j < A; ++j) mt.BT[i][j] = p.BT[i * A + j];
+    return mt;
+}
+
+inline int last_launch(const char* what) {
+    return hip_check((int)hipGetLastError(), what);
+}
+
+// Raise a kernel's dynamic LDS limit above 64 KB (gfx950 has 160 KB per CU);
+// done once per kernel and size.
+template <typename F>
+inline void allow_lds(F kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::set<std::pair<const void*, size_t>> done;
+    if (bytes <= 65536) return;
+    const void* key = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.insert({key, bytes}).second)
+        (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// switch over the compiled (m, r) pairs; FN names a WG_CASE_FN(MM, RR) macro
+#define WG_DISPATCH(FN, ...)                                              \
+    switch (p.L.m * 16 + p.L.r) {                                         \
+        WG_FOR_EACH_SIZE(WG_CASE_##FN)                                    \
+        default: return fail(WG_EUNSUPPORTED, "tile size not compiled");   \
+    }
+
+}  // namespace wg

@@ -60,6 +60,9 @@ _SIGS = {
     "wg_plan_sizes": (c_int, [c_void_p, P_size_t, P_size_t, P_int, P_int]),
     "wg_plan_layout": (c_int, [c_void_p, ctypes.POINTER(Layout)]),
     "wg_plan_matrices": (c_int, [c_void_p, P_float, P_float, P_float]),
+    "wg_plan_set_gemm_tiles": (c_int, [c_void_p, c_int]),
+    "wg_plan_gemm_tiles": (c_int, [c_void_p]),
+    "wg_plan_autotune_gemm": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P_int, c_void_p]),
     "wg_transform_filters": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "wg_conv2d_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "wg_input_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -223,6 +226,15 @@ class Plan:
         return AT, G, BT
 
     # -- device buffers -----------------------------------------------------
+    @property
+    def gemm_tiles(self):
+        """Output tiles per thread block of the Hadamard GEMM (a tuning knob)."""
+        return _check(lib().wg_plan_gemm_tiles(self._h))
+
+    @gemm_tiles.setter
+    def gemm_tiles(self, value):
+        _check(lib().wg_plan_set_gemm_tiles(self._h, int(value)))
+
     def empty_filters(self, device="cuda"):
         torch = _torch()
         return torch.empty(self.filter_bytes, dtype=torch.uint8, device=device)
@@ -263,6 +275,15 @@ class Plan:
     def hadamard_gemm(self, U, ws, stream=None):
         _check(lib().wg_hadamard_gemm(self._h, _tptr(U, None, "U"), _tptr(ws, None, "ws"),
                                       ws.numel() * ws.element_size(), _stream(stream)))
+
+    def autotune_gemm(self, U, ws, reps=10, stream=None):
+        """Pick the GEMM's tiles per block by timing the candidates on these
+        operands (synchronous; overwrites M in ws).  Returns the choice."""
+        chosen = c_int(0)
+        _check(lib().wg_plan_autotune_gemm(self._h, _tptr(U, None, "U"), _tptr(ws, None, "ws"),
+                                           ws.numel() * ws.element_size(), int(reps), ctypes.byref(chosen),
+                                           _stream(stream)))
+        return chosen.value
 
     def output_transform(self, ws, y, stream=None):
         torch = _torch()

@@ -156,3 +156,14 @@ def test_plan_layout_contract():
 def test_score_workspace_is_positive():
     assert wg.lib().wg_score_workspace_bytes(1) >= 16
     assert wg.lib().wg_score_workspace_bytes(10 ** 9) <= 1024 * 16
+
+
+def test_gemm_tiles_knob_validation():
+    plan = wg.Plan(6, 3, [0, 1, -1, 2, -2, 0.5, -0.5], 2, 8, 8, 12, 12)
+    assert plan.gemm_tiles == 1
+    plan.gemm_tiles = 4
+    assert plan.gemm_tiles == 4
+    for bad in (0, 17, -3):
+        with pytest.raises(wg.WGError):
+            plan.gemm_tiles = bad
+    assert plan.gemm_tiles == 4

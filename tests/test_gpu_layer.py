@@ -149,6 +149,28 @@ def test_gemm_and_output_transform(case, dtype):
     assert np.array_equal(_host(y), Yo)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("case", CASES[:3])
+def test_gemm_tiles_per_block_do_not_change_results(case, dtype):
+    """Blocks that take several consecutive GEMM tiles (pipelined across tile
+    boundaries, with a ragged last block) write the same M bit for bit."""
+    m, r, fam, N, C, K, H, W, padding = case
+    plan, x, w, xd, wd, U, ax = _setup(m, r, _pts(fam), N, C, K, H, W, padding, dtype)
+    ws = plan.empty_workspace()
+    plan.input_transform(xd, U, ws)
+    outs = []
+    for t in (1, 2, 3, 7):
+        plan.gemm_tiles = t
+        assert plan.gemm_tiles == t
+        plan.view_M(ws).fill_(1e30 * t)               # a different sentinel per run
+        plan.hadamard_gemm(U, ws)
+        # columns p >= P come from unwritten V' rows and may hold NaN in
+        # every run alike
+        outs.append(torch.nan_to_num(plan.view_M(ws), nan=0.0))
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("case", CASES)
 def test_forward_matches_oracle(case, dtype):
