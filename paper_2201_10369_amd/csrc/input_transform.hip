@@ -72,17 +72,26 @@ __device__ __forceinline__ void stage_band(const float* __restrict__ x, float* l
     }
 }
 
-template <int M, int R, int DT>
+// S: B^T has the zero structure of sets with 0 and infinity (rows arrive in
+// the order of RowPerm: point 0 first, infinity last), so column 0 is used
+// only by the first row and column alpha-1 only by the last.
+template <int A, bool S>
+struct BtTerms {
+    __device__ static constexpr int lo(int q) { return (S && q > 0) ? 1 : 0; }
+    __device__ static constexpr int hi(int q) { return (S && q < A - 1) ? A - 2 : A - 1; }
+};
+
+template <int M, int R, int DT, bool S>
 __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float* __restrict__ x,
                                                                      void* __restrict__ Vout,
                                                                      const int32_t* __restrict__ t_tab,
-                                                                     Mats<M, R> mt, NzMasks nzm, RowExps ex,
+                                                                     Mats<M, R> mt, RowPerm rp, RowExps ex,
                                                                      Geo g, int twb, int n_twb, int row_w,
                                                                      int ch_stride, int n_blocks) {
     constexpr int A = M + R - 1;
     using T = typename Elem<DT>::T;
+    using Terms = BtTerms<A, S>;
     extern __shared__ float lds[];
-    __shared__ float sBT[A][A];
     __shared__ int sdB[A];
     __shared__ int stc[kInCh];
     const int tid = threadIdx.x;
@@ -103,11 +112,7 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
     const int row0 = th * M - g.pad, col0 = tw0 * M - g.pad;
     if (tid == 0) {
 #pragma unroll
-        for (int a = 0; a < A; ++a) {
-#pragma unroll
-            for (int b = 0; b < A; ++b) sBT[a][b] = mt.BT[a][b];
-            sdB[a] = ex.dB[a];
-        }
+        for (int a = 0; a < A; ++a) sdB[a] = ex.dB[a];
     }
     if (DT != kF32 && tid < kInCh) stc[tid] = c0 + tid < g.C ? t_tab[c0 + tid] : 0;
 
@@ -120,50 +125,86 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
         stage_band<A, false>(x, lds, g, n, c0, nch, row0, col0, wl, row_w, ch_stride);
     __syncthreads();
 
-    // pass 1: T1 = B^T d, column by column, in place
-    for (int q = tid; q < kInCh * wl; q += kInThreads) {
-        const int ch = q / wl, col = q - ch * wl;
-        float* colp = lds + ch * ch_stride + col;
-        float d[A];
+    // pass 1: T1 = B^T d, column by column, in place (task indices advance
+    // by constant steps instead of being divided out each time)
+    {
+        const int dch = kInThreads / wl, dcol = kInThreads - dch * wl;
+        int ch = tid / wl, col = tid - ch * wl;
+        for (int q = tid; q < kInCh * wl; q += kInThreads) {
+            float* colp = lds + ch * ch_stride + col;
+            float d[A];
 #pragma unroll
-        for (int l = 0; l < A; ++l) d[l] = colp[l * row_w];
-        float t1[A];
+            for (int l = 0; l < A; ++l) d[l] = colp[l * row_w];
+            float t1[A];
 #pragma unroll
-        for (int i = 0; i < A; ++i) {
-            float acc = 0.0f;
+            for (int k = 0; k < A; ++k) {
+                float acc = 0.0f;
 #pragma unroll
-            for (int l = 0; l < A; ++l) acc = __builtin_fmaf(sBT[i][l], d[l], acc);
-            t1[i] = acc;
+                for (int l = Terms::lo(k); l <= Terms::hi(k); ++l) acc = __builtin_fmaf(mt.BT[k][l], d[l], acc);
+                t1[k] = acc;
+            }
+#pragma unroll
+            for (int k = 0; k < A; ++k) colp[rp.row[k] * row_w] = t1[k];
+            col += dcol;
+            ch += dch;
+            if (col >= wl) {
+                col -= wl;
+                ++ch;
+            }
         }
-#pragma unroll
-        for (int i = 0; i < A; ++i) colp[i * row_w] = t1[i];
     }
     __syncthreads();
 
-    // pass 2: V = T1 B, row by row; scaling, rounding, stores
+    // pass 2: V = T1 B, row by row for pairs of adjacent channels; scaling,
+    // rounding, and one store per pair.  The 16-bit exponent
+    // -floor((dB[i] + dB[j] + t[c]) / 2) is taken as
+    // (1 - dB[i] - t[c] - dB[j]) >> 1 (padded channels hold zeros).
     T* V = reinterpret_cast<T*>(Vout);
-    const size_t plane = in_vgpr((size_t)g.P_pad * g.C_pad);
-    for (int q = tid; q < kInCh * ntw * A; q += kInThreads) {
-        const int ch = q % kInCh, rest = q / kInCh;
+    const size_t plane = (size_t)g.P_pad * g.C_pad;
+    constexpr int kPairs = kInCh / 2;
+    for (int q = tid; q < kPairs * ntw * A; q += kInThreads) {
+        const int pc = q % kPairs, rest = q / kPairs;
         const int t = rest / A, i = rest - t * A;
+        const int ch = 2 * pc;
         const int gc = c0 + ch;
         const float* rowp = lds + ch * ch_stride + i * row_w + t * M;
-        float r[A];
+        float r0[A], r1[A];
 #pragma unroll
-        for (int l = 0; l < A; ++l) r[l] = rowp[l];
-        const int sv = (DT != kF32 && gc < g.C) ? sdB[i] + stc[ch] : 0;
+        for (int l = 0; l < A; ++l) {
+            r0[l] = rowp[l];
+            r1[l] = rowp[ch_stride + l];
+        }
+        int nb0 = 0, nb1 = 0;
+        if (DT != kF32) {
+            nb0 = 1 - sdB[i] - stc[ch];
+            nb1 = 1 - sdB[i] - stc[ch + 1];
+        }
         const unsigned p = ((unsigned)n * g.Th + th) * g.Tw + tw0 + t;
-        T* Vp = V + (size_t)(i * A) * plane + ((size_t)p * g.C_pad + gc);
+        T* Vi = V + (size_t)(i * A) * plane + ((size_t)p * g.C_pad + gc);
 #pragma unroll
-        for (int j = 0; j < A; ++j) {
-            float acc = 0.0f;
+        for (int k = 0; k < A; ++k) {
+            float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
-            for (int l = 0; l < A; ++l) acc = __builtin_fmaf(sBT[j][l], r[l], acc);
-            if (DT != kF32) acc = ldexpf(acc, gc < g.C ? -floor_half(sv + ex.dB[j]) : 0);
-            *Vp = Elem<DT>::from_f32(acc);
-            Vp += plane;
+            for (int l = Terms::lo(k); l <= Terms::hi(k); ++l) {
+                a0 = __builtin_fmaf(mt.BT[k][l], r0[l], a0);
+                a1 = __builtin_fmaf(mt.BT[k][l], r1[l], a1);
+            }
+            if (DT != kF32) {
+                a0 = ldexpf(a0, (nb0 - rp.dB[k]) >> 1);
+                a1 = ldexpf(a1, (nb1 - rp.dB[k]) >> 1);
+            }
+            Elem<DT>::store2(Vi + rp.plane_off[k], a0, a1);
         }
     }
+}
+
+template <int M, int R, int DT, bool S>
+static void input_launch(dim3 grid, size_t lds_bytes, hipStream_t s, const float* x, void* V,
+                         const int32_t* t_tab, const Mats<M, R>& mt, const RowPerm& rp, const RowExps& ex,
+                         const Geo& g, int twb, int n_twb, int row_w, int ch_stride, int nb) {
+    allow_lds(input_transform_kernel<M, R, DT, S>, lds_bytes);
+    hipLaunchKernelGGL((input_transform_kernel<M, R, DT, S>), grid, dim3(kInThreads), lds_bytes, s, x, V, t_tab, mt,
+                       rp, ex, g, twb, n_twb, row_w, ch_stride, nb);
 }
 
 template <int M, int R>
@@ -171,8 +212,12 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     constexpr int A = M + R - 1;
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
-    const Mats<M, R> mt = pack_mats<M, R>(p);
-    const NzMasks nzm = pack_masks(p);
+    const bool structured = zero_shape(p).bt;
+    const RowPerm rp = bt_row_perm(p, structured, (size_t)L.P_pad * L.C_pad);
+    // B^T rows in RowPerm order
+    Mats<M, R> mt = pack_mats<M, R>(p);
+    for (int k = 0; k < A; ++k)
+        for (int l = 0; l < A; ++l) mt.BT[k][l] = p.BT[rp.row[k] * A + l];
     RowExps ex{};
     for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
     // as many tiles of a tile row per block as fit in 40 KB of staged rows,
@@ -195,24 +240,20 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const long n_blocks = (long)L.N * L.Th * n_twb * (L.C_pad / kInCh);
     if (n_blocks > (1L << 30)) return fail(WG_EUNSUPPORTED, "input transform: grid too large");
     const dim3 grid((unsigned)((n_blocks + kXcdCount - 1) / kXcdCount * kXcdCount));
-    const dim3 block(kInThreads);
     const int32_t* t_tab = reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.chan_offset);
     void* V = static_cast<char*>(ws) + L.v_offset;
     const int nb = (int)n_blocks;
+#define WG_IN(DT)                                                                                              \
+    (structured ? input_launch<M, R, DT, true>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb, row_w, \
+                                               ch_stride, nb)                                                  \
+                : input_launch<M, R, DT, false>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb,       \
+                                                row_w, ch_stride, nb))
     switch (L.dtype) {
-        case WG_F32:
-            allow_lds(input_transform_kernel<M, R, kF32>, lds_bytes);
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kF32>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride, nb);
-            break;
-        case WG_F16:
-            allow_lds(input_transform_kernel<M, R, kF16>, lds_bytes);
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride, nb);
-            break;
-        default:
-            allow_lds(input_transform_kernel<M, R, kBF16>, lds_bytes);
-            hipLaunchKernelGGL((input_transform_kernel<M, R, kBF16>), grid, block, lds_bytes, s, x, V, t_tab, mt, nzm, ex, g, twb, n_twb, row_w, ch_stride, nb);
-            break;
+        case WG_F32: WG_IN(kF32); break;
+        case WG_F16: WG_IN(kF16); break;
+        default: WG_IN(kBF16); break;
     }
+#undef WG_IN
     return last_launch("input_transform_kernel");
 }
 

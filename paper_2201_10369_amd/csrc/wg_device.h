@@ -45,12 +45,11 @@ __device__ __forceinline__ int in_vgpr(int v) {
     return v;
 }
 
-// Round-to-nearest-even float32 -> bfloat16 bits (NaN stays a quiet NaN).
+// Round-to-nearest-even float32 -> bfloat16 bits (hardware conversion,
+// v_cvt_pk_bf16_f32 on gfx950; NaN stays NaN).
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const __bf16 h = (__bf16)f;
+    return __builtin_bit_cast(uint16_t, h);
 }
 
 // Round-to-nearest-even float32 -> float16 bits (hardware conversion).
@@ -64,20 +63,38 @@ enum : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
 template <int DT>
 struct Elem;
+typedef float wg_f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 wg_f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 wg_bf16x2 __attribute__((ext_vector_type(2)));
+
+// from_f32: one element; store2: two adjacent elements (a at the lower
+// address) in one store, rounded to nearest even by the packed conversions
+// (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32 on gfx950).
 template <>
 struct Elem<kF32> {
     using T = float;
     __device__ static __forceinline__ float from_f32(float v) { return v; }
+    __device__ static __forceinline__ void store2(float* p, float a, float b) {
+        *reinterpret_cast<wg_f32x2*>(p) = wg_f32x2{a, b};
+    }
 };
 template <>
 struct Elem<kF16> {
     using T = uint16_t;
     __device__ static __forceinline__ uint16_t from_f32(float v) { return f32_to_f16_bits(v); }
+    __device__ static __forceinline__ void store2(uint16_t* p, float a, float b) {
+        const wg_f16x2 h = __builtin_convertvector(wg_f32x2{a, b}, wg_f16x2);
+        *reinterpret_cast<uint32_t*>(p) = __builtin_bit_cast(uint32_t, h);
+    }
 };
 template <>
 struct Elem<kBF16> {
     using T = uint16_t;
     __device__ static __forceinline__ uint16_t from_f32(float v) { return f32_to_bf16_bits(v); }
+    __device__ static __forceinline__ void store2(uint16_t* p, float a, float b) {
+        const wg_bf16x2 h = __builtin_convertvector(wg_f32x2{a, b}, wg_bf16x2);
+        *reinterpret_cast<uint32_t*>(p) = __builtin_bit_cast(uint32_t, h);
+    }
 };
 
 }  // namespace wg

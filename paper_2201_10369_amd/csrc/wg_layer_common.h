@@ -85,6 +85,69 @@ inline void allow_lds(F kernel, size_t bytes) {
         (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// ---------------------------------------------------------------------------
+// Zero structure of B^T shared by every point set that contains 0 and ends
+// with infinity (the modified construction of Section 4.2, and all the
+// families of Section 5): column 0 is nonzero only in the row of point 0
+// (every other row's polynomial has the factor x), column alpha-1 only in the
+// infinity row (the finite rows have degree alpha-2).  Kernels compiled for
+// this structure leave those terms out; the host checks that the entries are
+// exactly zero before choosing them, so the results are the same as with all
+// terms (fma(0, x, acc) == acc for finite x).
+// ---------------------------------------------------------------------------
+struct ZeroShape {
+    int z0;            // index of the point 0, or -1
+    bool bt;           // the B^T pattern holds
+};
+
+inline ZeroShape zero_shape(const Plan& p) {
+    const int A = p.L.alpha;
+    ZeroShape z{-1, false};
+    int found = 0;
+    for (int i = 0; i < A - 1; ++i)
+        if (p.BT[i * A] != 0.0f) {
+            z.z0 = i;
+            ++found;
+        }
+    if (found != 1 || p.BT[(A - 1) * A] != 0.0f) {
+        z.z0 = -1;
+        return z;
+    }
+    z.bt = true;
+    for (int i = 0; i < A - 1; ++i)
+        if (p.BT[i * A + (A - 1)] != 0.0f) z.bt = false;
+    return z;
+}
+
+// B^T rows in processing order (with the structure: the row of point 0
+// first, the infinity row last, the others ascending; else the identity),
+// with each row's exponent offset and the element offset of its V' plane.
+struct RowPerm {
+    int row[kMaxAlpha];
+    int dB[kMaxAlpha];
+    unsigned long long plane_off[kMaxAlpha];
+};
+
+inline RowPerm bt_row_perm(const Plan& p, bool structured, size_t plane_elems) {
+    const int A = p.L.alpha;
+    RowPerm rp{};
+    int q = 0;
+    if (structured) {
+        const int z0 = zero_shape(p).z0;
+        rp.row[q++] = z0;
+        for (int i = 0; i < A - 1; ++i)
+            if (i != z0) rp.row[q++] = i;
+        rp.row[q++] = A - 1;
+    } else {
+        for (int i = 0; i < A; ++i) rp.row[q++] = i;
+    }
+    for (int k = 0; k < A; ++k) {
+        rp.dB[k] = p.dB[rp.row[k]];
+        rp.plane_off[k] = (unsigned long long)rp.row[k] * plane_elems;
+    }
+    return rp;
+}
+
 // switch over the compiled (m, r) pairs; FN names a WG_CASE_FN(MM, RR) macro
 #define WG_DISPATCH(FN, ...)                                              \
     switch (p.L.m * 16 + p.L.r) {                                         \

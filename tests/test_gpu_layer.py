@@ -78,11 +78,15 @@ CASES = [
     (4, 3, (6, 1.622, 1.0), 1, 33, 17, 9, 14, "valid"),
     (3, 5, (7, 1.3, 2.5), 1, 24, 20, 12, 13, "same"),
     (6, 5, (10, 1.272, 2.099), 1, 8, 9, 15, 11, "valid"),
+    # points without 0: the kernels for general zero patterns
+    (4, 3, ("pts", (-2.0, -1.0, -0.5, 0.5, 1.5)), 1, 20, 12, 11, 10, "same"),
 ]
 
 
 def _pts(fam):
     wg = _wg()
+    if fam[0] == "pts":
+        return np.array(fam[1])
     alpha, c1, c2 = fam
     if alpha == 4 and c1 == 1.0:
         return np.array([0.0, 1.0, -1.0])          # the classic F(2,3) points
@@ -119,7 +123,7 @@ def test_transforms_bitexact(case, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("case", CASES[:4])
+@pytest.mark.parametrize("case", CASES[:4] + CASES[-1:])
 def test_gemm_and_output_transform(case, dtype):
     """The MFMA channel-sum GEMM is within the summation-order bound of the
     oracle's ascending sum; the output transform, fed the oracle's own M, is
