@@ -29,19 +29,11 @@ namespace wg {
 template <int M, int R>
 __global__ __launch_bounds__(256) void output_transform_kernel(const float* __restrict__ Mbuf,
                                                                float* __restrict__ y, Mats<M, R> mt,
-                                                               NzMasks nzm, Geo g, int nb,
-                                                               unsigned plane_stride) {
+                                                               Geo g, int nb, unsigned plane_stride,
+                                                               unsigned plane_bytes) {
     constexpr int A = M + R - 1;
     extern __shared__ float lds[];
-    __shared__ float sAT[M][A];
     const int tid = threadIdx.x;
-    if (tid == 0) {
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-#pragma unroll
-            for (int b = 0; b < A; ++b) sAT[a][b] = mt.AT[a][b];
-    }
-    __syncthreads();
     const int k = blockIdx.y;
     const int band0 = blockIdx.x * nb;
     const int nbands = g.N * g.Th;
@@ -49,11 +41,10 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
     const int items = nbl * g.Tw;
     for (int it = tid; it < items; it += 256) {
         const int bl = it / g.Tw, tw = it - bl * g.Tw;
-        // offset inside one plane of M; the alpha^2 planes are plane_stride apart
-        const unsigned off = (unsigned)k * g.P_pad + (unsigned)(band0 + bl) * g.Tw + tw;
-        // Z = A^T M, streaming the rows of M (plane a*A + b holds M[a][b])
-        const size_t pstride = in_vgpr((size_t)plane_stride);
-        const float* mp = Mbuf + off;
+        // Z = A^T M, streaming the rows of M: row a of the tile is planes
+        // a*A .. a*A+A-1, read through a buffer resource on plane a*A with
+        // the plane step as scalar offset and the tile's offset in a VGPR
+        const unsigned voff = ((unsigned)k * g.P_pad + (unsigned)(band0 + bl) * g.Tw + tw) * 4u;
         float z[M][A];
 #pragma unroll
         for (int i = 0; i < M; ++i)
@@ -61,15 +52,15 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
             for (int b = 0; b < A; ++b) z[i][b] = 0.0f;
 #pragma unroll
         for (int a = 0; a < A; ++a) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(Mbuf) + (size_t)(a * A) * plane_stride, 0, (int)(A * plane_bytes), kBufferWord3);
             float row[A];
 #pragma unroll
-            for (int b = 0; b < A; ++b) {
-                row[b] = *mp;
-                mp += pstride;
-            }
+            for (int b = 0; b < A; ++b)
+                row[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)(b * plane_bytes), 0));
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                const float av = sAT[i][a];
+                const float av = mt.AT[i][a];
 #pragma unroll
                 for (int b = 0; b < A; ++b) z[i][b] = __builtin_fmaf(av, row[b], z[i][b]);
             }
@@ -83,7 +74,7 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
         for (int j = 0; j < M; ++j) {
             float arow[A];
 #pragma unroll
-            for (int l = 0; l < A; ++l) arow[l] = sAT[j][l];
+            for (int l = 0; l < A; ++l) arow[l] = mt.AT[j][l];
             float col[M];
 #pragma unroll
             for (int i = 0; i < M; ++i) col[i] = 0.0f;
@@ -118,16 +109,20 @@ static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const Mats<M, R> mt = pack_mats<M, R>(p);
-    const NzMasks nzm = pack_masks(p);
     int nb = 256 / L.Tw;
     if (nb < 1) nb = 1;
     while (nb > 1 && (size_t)nb * M * L.Wout * sizeof(float) > 65536) --nb;
     const size_t lds_bytes = (size_t)nb * M * L.Wout * sizeof(float);
     if (lds_bytes > 65536) return fail(WG_EUNSUPPORTED, "output transform: output rows too wide");
+    // one row of alpha planes is addressed with 32-bit byte offsets
+    const size_t plane_elems = (size_t)L.K_pad * L.P_pad;
+    if ((size_t)L.alpha * plane_elems * sizeof(float) >= (1ull << 31))
+        return fail(WG_EUNSUPPORTED, "output transform: planes of M too large");
     const int nbands = L.N * L.Th;
     const dim3 grid((unsigned)((nbands + nb - 1) / nb), (unsigned)L.K);
     const float* Mbuf = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.m_offset);
-    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(256), lds_bytes, s, Mbuf, y, mt, nzm, g, nb, (unsigned)((size_t)L.K_pad * L.P_pad));
+    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(256), lds_bytes, s, Mbuf, y, mt, g, nb,
+                       (unsigned)plane_elems, (unsigned)(plane_elems * sizeof(float)));
     return last_launch("output_transform_kernel");
 }
 
