@@ -18,59 +18,33 @@ namespace wg {
 
 // ---------------------------------------------------------------------------
 // Input transform V = B^T d B.  A block covers one image n, one tile row th,
-// `twb` consecutive tiles of that row and kInCh input channels.  It stages the
-// alpha input rows of those channels in LDS (threads own fixed positions of
-// the band and walk the channels, so consecutive threads read contiguous row
-// segments; zeros outside the image), then transforms in two passes over LDS:
-//   pass 1: every staged column b of every channel, T1[:, b] = B^T d[:, b],
-//           written back in place (columns shared by neighbouring tiles are
-//           transformed once);
-//   pass 2: every (channel, tile, row i), V[i][j] = sum_l T1[i][l] B^T[j][l],
-//           scaled and rounded to the GEMM type and stored; consecutive lanes
-//           hold consecutive channels, so every V' store is a contiguous run.
-// Zero entries of B^T are not skipped: fma(0, x, acc) == acc for finite x,
-// and a per-term branch costs more than the multiply-add.  Block indices are
-// mapped so
-// that each XCD runs a contiguous range of bands, keeping the channel blocks
-// of one tile row (which write the halves of the same V' lines) and
-// neighbouring tile rows (which share R-1 input rows) in one L2.
+// `twb` consecutive tiles of that row and kInCh input channels, handled as
+// channel pairs throughout:
+//   load + pass 1: a thread takes one column of the alpha-row band for two
+//           adjacent channels (coalesced: lanes along columns), transforms
+//           it at once, T1[:, b] = B^T d[:, b] (columns shared by
+//           neighbouring tiles are transformed once), and writes it to LDS;
+//   pass 2: a thread takes one row of T1 of one tile for a channel pair,
+//           V[i][j] = sum_l T1[i][l] B^T[j][l], scales and rounds both
+//           channels and stores them with one store (consecutive lanes hold
+//           consecutive pairs, so every V' store is a contiguous run).
+// Input reads go through a buffer resource on image n: columns outside the
+// image and channels past C get an out-of-range offset and read as zero;
+// rows outside the image are block-uniform and skipped.
+// With the B^T structure of sets with 0 and infinity (S), rows are taken in
+// RowPerm order and the structurally zero terms are left out.  Block indices
+// are mapped so that each XCD runs a contiguous range of bands, keeping the
+// channel blocks of one tile row (which write the halves of the same V'
+// lines) and neighbouring tile rows (which share R-1 input rows) in one L2.
+//
+// LDS: T1 of the band, lds[pc * pair_stride + col * CS + k * 2 + (c & 1)]
+// for pair pc, column col, T1 row slot k (RowPerm order); CS = 2 (alpha | 1)
+// words (an odd number of word pairs: lanes along columns hit distinct
+// banks), pair_stride = 8 mod 64 words (lanes along pairs likewise).
 // ---------------------------------------------------------------------------
 constexpr int kInCh = 32;
+constexpr int kInPairs = kInCh / 2;
 constexpr int kInThreads = 256;
-
-template <int A, bool kFull>
-__device__ __forceinline__ void stage_band(const float* __restrict__ x, float* lds, const Geo& g, int n, int c0,
-                                           int nch, int row0, int col0, int wl, int row_w, int ch_stride) {
-    constexpr int kBatch = 16;
-    const size_t hw = in_vgpr((size_t)g.H * g.W);
-    const int cstride = in_vgpr(ch_stride);
-    const int last = in_vgpr(max(nch - 1, 0));
-    for (int ac = threadIdx.x; ac < A * wl; ac += kInThreads) {
-        const int a = ac / wl, col = ac - a * wl;
-        const int gi = row0 + a, gj = col0 + col;
-        const bool inside = gi >= 0 && gi < g.H && gj >= 0 && gj < g.W && nch > 0;
-        // loads are unconditional (from a valid address) and masked after,
-        // so a whole batch is in flight at once
-        const float* src = inside ? x + (((size_t)n * g.C + c0) * g.H + gi) * g.W + gj : x;
-        float* dst = lds + a * row_w + col;
-#pragma unroll
-        for (int cb = 0; cb < kInCh; cb += kBatch) {
-            float v[kBatch];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                v[u] = *src;                        // channel min(cb + u, last)
-                if (kFull || cb + u < last) src += hw;
-            }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) v[u] = (inside && (kFull || cb + u <= last)) ? v[u] : 0.0f;
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                *dst = v[u];
-                dst += cstride;
-            }
-        }
-    }
-}
 
 // S: B^T has the zero structure of sets with 0 and infinity (rows arrive in
 // the order of RowPerm: point 0 first, infinity last), so column 0 is used
@@ -86,13 +60,15 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
                                                                      void* __restrict__ Vout,
                                                                      const int32_t* __restrict__ t_tab,
                                                                      Mats<M, R> mt, RowPerm rp, RowExps ex,
-                                                                     Geo g, int twb, int n_twb, int row_w,
-                                                                     int ch_stride, int n_blocks) {
+                                                                     Geo g, int twb, int n_twb, int pair_stride,
+                                                                     int n_blocks) {
     constexpr int A = M + R - 1;
+    constexpr int CS = 2 * (A | 1);
     using T = typename Elem<DT>::T;
     using Terms = BtTerms<A, S>;
     extern __shared__ float lds[];
-    __shared__ int sdB[A];
+    __shared__ int sdB[A];                        // dB of T1 row slot k (RowPerm order)
+    __shared__ int srow[A];                       // T1 row index of slot k
     __shared__ int stc[kInCh];
     const int tid = threadIdx.x;
     const int per_xcd = (int)(gridDim.x / kXcdCount);
@@ -112,44 +88,60 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
     const int row0 = th * M - g.pad, col0 = tw0 * M - g.pad;
     if (tid == 0) {
 #pragma unroll
-        for (int a = 0; a < A; ++a) sdB[a] = ex.dB[a];
+        for (int k = 0; k < A; ++k) {
+            srow[k] = rp.row[k];
+            sdB[k] = rp.dB[k];
+        }
     }
     if (DT != kF32 && tid < kInCh) stc[tid] = c0 + tid < g.C ? t_tab[c0 + tid] : 0;
 
-    // stage the band (channel tail handled apart so that the full case
-    // carries no per-channel conditions)
-    const int nch = min(kInCh, g.C - c0);          // channels present (may be <= 0)
-    if (nch == kInCh)
-        stage_band<A, true>(x, lds, g, n, c0, nch, row0, col0, wl, row_w, ch_stride);
-    else
-        stage_band<A, false>(x, lds, g, n, c0, nch, row0, col0, wl, row_w, ch_stride);
-    __syncthreads();
-
-    // pass 1: T1 = B^T d, column by column, in place (task indices advance
-    // by constant steps instead of being divided out each time)
+    // load + pass 1
     {
-        const int dch = kInThreads / wl, dcol = kInThreads - dch * wl;
-        int ch = tid / wl, col = tid - ch * wl;
-        for (int q = tid; q < kInCh * wl; q += kInThreads) {
-            float* colp = lds + ch * ch_stride + col;
-            float d[A];
+        const size_t img = (size_t)g.C * g.H * g.W;
+        const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(x) + (size_t)n * img, 0, (int)(img * sizeof(float)), kBufferWord3);
+        const int hw4 = g.H * g.W * 4;
+        const int dpc = kInThreads / wl, dcol = kInThreads - dpc * wl;
+        int pc = tid / wl, col = tid - pc * wl;
+        for (int q = tid; q < kInPairs * wl; q += kInThreads) {
+            // per-lane byte offsets of (channel, row 0, column) for both
+            // channels, or an out-of-range marker (reads as zero) for columns
+            // outside the image and channels past C; the row goes in the
+            // scalar offset
+            const int gj = col0 + col;
+            const int cch = c0 + 2 * pc;
+            const bool cok = gj >= 0 && gj < g.W;
+            const unsigned base = (unsigned)(cch * hw4 + gj * 4);
+            const unsigned voff0 = (cok && cch < g.C) ? base : 0x80000000u;
+            const unsigned voff1 = (cok && cch + 1 < g.C) ? base + (unsigned)hw4 : 0x80000000u;
+            float d0[A], d1[A];
 #pragma unroll
-            for (int l = 0; l < A; ++l) d[l] = colp[l * row_w];
-            float t1[A];
+            for (int a = 0; a < A; ++a) {
+                const int gi = row0 + a;                      // uniform over the block
+                if (gi >= 0 && gi < g.H) {
+                    d0[a] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, (int)voff0, gi * g.W * 4, 0));
+                    d1[a] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, (int)voff1, gi * g.W * 4, 0));
+                } else {
+                    d0[a] = 0.0f;
+                    d1[a] = 0.0f;
+                }
+            }
+            float* dst = lds + pc * pair_stride + col * CS;
 #pragma unroll
             for (int k = 0; k < A; ++k) {
-                float acc = 0.0f;
+                float t0 = 0.0f, t1 = 0.0f;
 #pragma unroll
-                for (int l = Terms::lo(k); l <= Terms::hi(k); ++l) acc = __builtin_fmaf(mt.BT[k][l], d[l], acc);
-                t1[k] = acc;
+                for (int l = Terms::lo(k); l <= Terms::hi(k); ++l) {
+                    t0 = __builtin_fmaf(mt.BT[k][l], d0[l], t0);
+                    t1 = __builtin_fmaf(mt.BT[k][l], d1[l], t1);
+                }
+                *reinterpret_cast<wg_f32x2*>(dst + 2 * k) = wg_f32x2{t0, t1};
             }
-#pragma unroll
-            for (int k = 0; k < A; ++k) colp[rp.row[k] * row_w] = t1[k];
             col += dcol;
-            ch += dch;
+            pc += dpc;
             if (col >= wl) {
                 col -= wl;
-                ++ch;
+                ++pc;
             }
         }
     }
@@ -161,39 +153,39 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
     // (1 - dB[i] - t[c] - dB[j]) >> 1 (padded channels hold zeros).
     T* V = reinterpret_cast<T*>(Vout);
     const size_t plane = (size_t)g.P_pad * g.C_pad;
-    constexpr int kPairs = kInCh / 2;
-    for (int q = tid; q < kPairs * ntw * A; q += kInThreads) {
-        const int pc = q % kPairs, rest = q / kPairs;
-        const int t = rest / A, i = rest - t * A;
-        const int ch = 2 * pc;
-        const int gc = c0 + ch;
-        const float* rowp = lds + ch * ch_stride + i * row_w + t * M;
+    for (int q = tid; q < kInPairs * ntw * A; q += kInThreads) {
+        const int pc = q % kInPairs, rest = q / kInPairs;
+        const int t = rest / A, k = rest - t * A;
+        const int i = srow[k];
+        const int gc = c0 + 2 * pc;
+        const float* rowp = lds + pc * pair_stride + (t * M) * CS + 2 * k;
         float r0[A], r1[A];
 #pragma unroll
         for (int l = 0; l < A; ++l) {
-            r0[l] = rowp[l];
-            r1[l] = rowp[ch_stride + l];
+            const wg_f32x2 v = *reinterpret_cast<const wg_f32x2*>(rowp + l * CS);
+            r0[l] = v.x;
+            r1[l] = v.y;
         }
         int nb0 = 0, nb1 = 0;
         if (DT != kF32) {
-            nb0 = 1 - sdB[i] - stc[ch];
-            nb1 = 1 - sdB[i] - stc[ch + 1];
+            nb0 = 1 - sdB[k] - stc[2 * pc];
+            nb1 = 1 - sdB[k] - stc[2 * pc + 1];
         }
         const unsigned p = ((unsigned)n * g.Th + th) * g.Tw + tw0 + t;
         T* Vi = V + (size_t)(i * A) * plane + ((size_t)p * g.C_pad + gc);
 #pragma unroll
-        for (int k = 0; k < A; ++k) {
+        for (int kk = 0; kk < A; ++kk) {
             float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
-            for (int l = Terms::lo(k); l <= Terms::hi(k); ++l) {
-                a0 = __builtin_fmaf(mt.BT[k][l], r0[l], a0);
-                a1 = __builtin_fmaf(mt.BT[k][l], r1[l], a1);
+            for (int l = Terms::lo(kk); l <= Terms::hi(kk); ++l) {
+                a0 = __builtin_fmaf(mt.BT[kk][l], r0[l], a0);
+                a1 = __builtin_fmaf(mt.BT[kk][l], r1[l], a1);
             }
             if (DT != kF32) {
-                a0 = ldexpf(a0, (nb0 - rp.dB[k]) >> 1);
-                a1 = ldexpf(a1, (nb1 - rp.dB[k]) >> 1);
+                a0 = ldexpf(a0, (nb0 - rp.dB[kk]) >> 1);
+                a1 = ldexpf(a1, (nb1 - rp.dB[kk]) >> 1);
             }
-            Elem<DT>::store2(Vi + rp.plane_off[k], a0, a1);
+            Elem<DT>::store2(Vi + rp.plane_off[kk], a0, a1);
         }
     }
 }
@@ -201,15 +193,16 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
 template <int M, int R, int DT, bool S>
 static void input_launch(dim3 grid, size_t lds_bytes, hipStream_t s, const float* x, void* V,
                          const int32_t* t_tab, const Mats<M, R>& mt, const RowPerm& rp, const RowExps& ex,
-                         const Geo& g, int twb, int n_twb, int row_w, int ch_stride, int nb) {
+                         const Geo& g, int twb, int n_twb, int pair_stride, int nb) {
     allow_lds(input_transform_kernel<M, R, DT, S>, lds_bytes);
     hipLaunchKernelGGL((input_transform_kernel<M, R, DT, S>), grid, dim3(kInThreads), lds_bytes, s, x, V, t_tab, mt,
-                       rp, ex, g, twb, n_twb, row_w, ch_stride, nb);
+                       rp, ex, g, twb, n_twb, pair_stride, nb);
 }
 
 template <int M, int R>
 static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s) {
     constexpr int A = M + R - 1;
+    constexpr int CS = 2 * (A | 1);
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const bool structured = zero_shape(p).bt;
@@ -220,18 +213,19 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
         for (int l = 0; l < A; ++l) mt.BT[k][l] = p.BT[rp.row[k] * A + l];
     RowExps ex{};
     for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
-    // as many tiles of a tile row per block as fit in 40 KB of staged rows,
-    // split evenly; the channel stride is 33 mod 64 words, so neither the
-    // column pass (lanes along columns) nor the row pass (lanes along
-    // channels) has LDS bank conflicts
-    int nsplit = 1, twb = 0, row_w = 0, ch_stride = 0;
+    // one image's input is addressed with 32-bit byte offsets (channels up to
+    // C_pad, and an out-of-range marker at 2^31)
+    if ((size_t)L.C_pad * L.H * L.W * sizeof(float) >= (1ull << 31))
+        return fail(WG_EUNSUPPORTED, "input transform: one image of the input exceeds 2 GB");
+    // as many tiles of a tile row per block as fit in 40 KB of LDS, split evenly
+    int nsplit = 1, twb = 0, pair_stride = 0;
     size_t lds_bytes = 0;
     for (;; ++nsplit) {
         twb = (L.Tw + nsplit - 1) / nsplit;
-        row_w = twb * M + R - 1;
-        ch_stride = A * row_w;
-        ch_stride += (33 - ch_stride % 64 + 64) % 64;
-        lds_bytes = (size_t)kInCh * ch_stride * sizeof(float);
+        const int wl = twb * M + R - 1;
+        pair_stride = wl * CS;
+        pair_stride += (8 - pair_stride % 64 + 64) % 64;
+        lds_bytes = (size_t)kInPairs * pair_stride * sizeof(float);
         if (lds_bytes <= 40 * 1024 || twb == 1) break;
     }
     if (lds_bytes > 128 * 1024) return fail(WG_EUNSUPPORTED, "input transform: tile too large for LDS");
@@ -243,11 +237,11 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const int32_t* t_tab = reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.chan_offset);
     void* V = static_cast<char*>(ws) + L.v_offset;
     const int nb = (int)n_blocks;
-#define WG_IN(DT)                                                                                              \
-    (structured ? input_launch<M, R, DT, true>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb, row_w, \
-                                               ch_stride, nb)                                                  \
-                : input_launch<M, R, DT, false>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb,       \
-                                                row_w, ch_stride, nb))
+#define WG_IN(DT)                                                                                                 \
+    (structured ? input_launch<M, R, DT, true>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb,         \
+                                               pair_stride, nb)                                                   \
+                : input_launch<M, R, DT, false>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb,        \
+                                                pair_stride, nb))
     switch (L.dtype) {
         case WG_F32: WG_IN(kF32); break;
         case WG_F16: WG_IN(kF16); break;
