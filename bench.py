@@ -178,12 +178,15 @@ def traffic_for(kernel_key):
     k = rec.get("kernels", {}).get(kernel_key)
     if k is None:
         return None
-    src = os.path.join(ROOT, "paper_2201_10369_amd", "csrc", k["source"])
-    if not os.path.exists(src):
-        return None
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != k["source_sha256"]:
+    h = hashlib.sha256()
+    for name in k["sources"]:
+        src = os.path.join(ROOT, "paper_2201_10369_amd", "csrc", name)
+        if not os.path.exists(src):
             return None
+        with open(src, "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != k["sources_sha256"]:
+        return None
     return k["fetch_bytes"] + k["write_bytes"]
 
 

@@ -15,9 +15,9 @@
 // MFMA blocks.  The contraction runs in steps of BK elements (128 bytes of
 // each operand row) through double-buffered LDS, with the next step's global
 // loads in flight while the current one is multiplied; a block may take
-// several consecutive tiles, and the pipeline then runs on across the tile
-// boundaries.  Block ids are mapped so that consecutive work items (same e,
-// neighbouring tiles) run on the same XCD and share its L2.
+// several tiles, and the pipeline then runs on across the tile boundaries.
+// Block ids are mapped so that the blocks running together on one XCD work on
+// neighbouring tiles (same e) and share its L2.
 //
 // Element types: float32 (v_mfma_f32_32x32x2_f32), float16 and bfloat16 with
 // float32 accumulation (v_mfma_f32_32x32x16_{f16,bf16}).
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
                                                             const char* __restrict__ V,
                                                             float* __restrict__ Mout, int K_pad,
                                                             int P_pad, int C_pad, int nKb, int nPb,
-                                                            int total, int tpb, int per_xcd) {
+                                                            int total, int tiles_per_xcd, int blocks_per_xcd) {
     constexpr int WM = BM / 2, WN = BN / 2;          // wave sub-tile
     constexpr int FM = WM / 32, FN = WN / 32;         // 32 x 32 blocks per wave
     constexpr int ELEM = MfmaOp<DT>::kElem;
@@ -116,12 +116,18 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
 
     __shared__ __attribute__((aligned(16))) char smem[2 * (BM + BN) * kPitchBytes];
 
-    // XCD-aware work mapping: block w takes tiles w*tpb .. w*tpb + tpb - 1
+    // XCD-aware work mapping: XCD x (blocks b = x mod 8) owns the contiguous
+    // tile range [x * tiles_per_xcd, (x+1) * tiles_per_xcd); its block in
+    // slot s takes tiles s, s + blocks_per_xcd, s + 2 blocks_per_xcd, ... of
+    // that range, so the blocks running together on one XCD always work on
+    // neighbouring tiles (same e, shared operand rows in its L2)
     const int b = blockIdx.x;
-    const int w = (b % kXcds) * per_xcd + b / kXcds;
-    const int t0 = w * tpb;
-    if (t0 >= total) return;
-    const int nt = min(tpb, total - t0);
+    const int xcd = b % kXcds, slot = b / kXcds;
+    const int lo = xcd * tiles_per_xcd, hi = min(total, lo + tiles_per_xcd);
+    const int t0 = lo + slot;
+    if (t0 >= hi) return;
+    const int nt = (hi - t0 + blocks_per_xcd - 1) / blocks_per_xcd;
+    const int tstride = blocks_per_xcd;
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;   // wave index is uniform
@@ -198,8 +204,8 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
             const bool more = it + 1 < niter;
             if (more) {
                 if (st + 1 == nsteps) {
-                    nA = a_tile(t0 + t + 1);
-                    nB = b_tile(t0 + t + 1);
+                    nA = a_tile(t0 + (t + 1) * tstride);
+                    nB = b_tile(t0 + (t + 1) * tstride);
                 }
                 gload(nA, nB, st + 1 == nsteps ? 0 : st + 1);
             }
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
         // buffer resource on the tile's base: the lane part of the offset is
         // one VGPR, the row part a scalar, so no 64-bit address is formed
         // per store.
-        const int ct = t0 + t;
+        const int ct = t0 + t * tstride;
         const int kb = ct % nKb, pb = (ct / nKb) % nPb, e = ct / (nKb * nPb);
         float* Mg = Mout + ((size_t)e * K_pad + (size_t)kb * BM) * P_pad + (size_t)pb * BN;
         const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(Mg, 0, BM * P_pad * 4, kBufferWord3);
@@ -251,13 +257,13 @@ static int gemm_launch(const Plan& p, const void* U, void* ws, hipStream_t s) {
     // the epilogue addresses one tile with 32-bit byte offsets
     if ((long)BM * L.P_pad * 4 >= (1L << 31)) return fail(WG_EUNSUPPORTED, "hadamard gemm: tile rows too long");
     const int tpb = p.gemm_tpb > 0 ? p.gemm_tpb : 1;
-    const long blocks = (total + tpb - 1) / tpb;
-    const int per_xcd = (int)((blocks + kXcds - 1) / kXcds);
+    const int tiles_per_xcd = (int)((total + kXcds - 1) / kXcds);
+    const int blocks_per_xcd = (tiles_per_xcd + tpb - 1) / tpb;
     const char* V = static_cast<const char*>(ws) + L.v_offset;
     float* Mb = reinterpret_cast<float*>(static_cast<char*>(ws) + L.m_offset);
-    hipLaunchKernelGGL((hadamard_gemm_kernel<BM, BN, DT>), dim3((unsigned)(per_xcd * kXcds)), dim3(256), 0, s,
-                       static_cast<const char*>(U), V, Mb, L.K_pad, L.P_pad, L.C_pad, nKb, nPb, (int)total, tpb,
-                       per_xcd);
+    hipLaunchKernelGGL((hadamard_gemm_kernel<BM, BN, DT>), dim3((unsigned)(blocks_per_xcd * kXcds)), dim3(256), 0, s,
+                       static_cast<const char*>(U), V, Mb, L.K_pad, L.P_pad, L.C_pad, nKb, nPb, (int)total,
+                       tiles_per_xcd, blocks_per_xcd);
     return hip_check((int)hipGetLastError(), "hadamard_gemm_kernel");
 }
 
