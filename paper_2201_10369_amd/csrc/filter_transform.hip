@@ -53,10 +53,11 @@ __global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Filter transform U = G g G^T.  A block covers 64 channels (the lanes of a
-// wave) and four filters (one per wave); each thread transforms one filter
-// channel g = w[k][c] into all alpha x alpha entries, so every store of
-// U'[e][k][.] is a contiguous run of 64 channels.
+// Filter transform U = G g G^T.  A block covers 128 channels (64 lanes, two
+// adjacent channels each) and four filters (one per wave); each thread
+// transforms its two filter channels g = w[k][c], w[k][c+1] into all
+// alpha x alpha entries and stores each entry pair with one store, so every
+// store of U'[e][k][.] is a contiguous run of 128 channels.
 //
 // For the 16-bit stage the block first finishes the per-channel exponent
 // part t[c] = E(x_absmax[c]) - E(max_k |w[k][c]|) from the partial maxima of
@@ -72,77 +73,90 @@ __global__ __launch_bounds__(256) void filter_transform_kernel(const float* __re
                                                                const float* __restrict__ x_absmax,
                                                                int32_t* __restrict__ s_tab,
                                                                int32_t* __restrict__ t_tab, int kchunks,
-                                                               Mats<M, R> mt, NzMasks nzm, RowExps ex, Geo g) {
+                                                               Mats<M, R> mt, RowExps ex, Geo g) {
     constexpr int A = M + R - 1;
     using T = typename Elem<DT>::T;
-    __shared__ float sG[A][R];
-    __shared__ float sred[4][64];
+    __shared__ int stc[2][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + lane;
+    const int c = blockIdx.x * 128 + 2 * lane;            // channels c, c + 1
     const int k = blockIdx.y * 4 + wv;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int a = 0; a < A; ++a)
-#pragma unroll
-            for (int u = 0; u < R; ++u) sG[a][u] = mt.G[a][u];
-    }
-    int tc = 0;
-    if (DT != kF32) {
-        float aw = 0.0f;
-        if (c < g.C) {
-#pragma unroll 8
-            for (int q = wv; q < kchunks; q += 4) aw = fmaxf(aw, part[(size_t)q * g.C_pad + c]);
-        }
-        sred[wv][lane] = aw;
-    }
-    __syncthreads();
-    if (DT != kF32 && c < g.C) {
-        const float mw = fmaxf(fmaxf(sred[0][lane], sred[1][lane]), fmaxf(sred[2][lane], sred[3][lane]));
-        tc = bin_exp(x_absmax != nullptr ? x_absmax[c] : 1.0f) - bin_exp(mw);
-    }
-    if (DT != kF32 && blockIdx.y == 0 && c < g.C_pad) {
-        if (wv == 0) t_tab[c] = tc;
-#pragma unroll
-        for (int e1 = 0; e1 < A; ++e1)
-            if ((e1 & 3) == wv) {
-#pragma unroll
-                for (int e2 = 0; e2 < A; ++e2)
-                    s_tab[(size_t)(e1 * A + e2) * g.C_pad + c] = c < g.C ? floor_half(ex.dB[e1] + ex.dB[e2] + tc) : 0;
-            }
-    }
-    if (c >= g.C_pad) return;
-    const bool live = k < g.K && c < g.C;
-    float gg[R][R];
+    // the filter taps first, so their loads overlap the exponent reduction
+    float g0[R][R], g1[R][R];
+    const bool live0 = k < g.K && c < g.C, live1 = k < g.K && c + 1 < g.C;
 #pragma unroll
     for (int u = 0; u < R; ++u)
 #pragma unroll
-        for (int v = 0; v < R; ++v) gg[u][v] = live ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f;
+        for (int v = 0; v < R; ++v) {
+            g0[u][v] = live0 ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f;
+            g1[u][v] = live1 ? w[(((size_t)k * g.C + c + 1) * R + u) * R + v] : 0.0f;
+        }
+    int tc0 = 0, tc1 = 0;
+    if (DT != kF32) {
+        // t[c] from the partial maxima of every filter chunk: wave wv takes
+        // the channels wv*32 .. wv*32+31 of the block's 128, two chunks'
+        // worth of lanes at a time
+        __shared__ float sred[2][128];
+        const int cl = (threadIdx.x & 127), half = threadIdx.x >> 7;
+        const int cc = blockIdx.x * 128 + cl;
+        float aw = 0.0f;
+        if (cc < g.C) {
+#pragma unroll 8
+            for (int q = half; q < kchunks; q += 2) aw = fmaxf(aw, part[(size_t)q * g.C_pad + cc]);
+        }
+        sred[half][cl] = aw;
+        __syncthreads();
+        // both halves derive t for channel cl; they split the table rows
+        const float mw = fmaxf(sred[0][cl], sred[1][cl]);
+        const int tc = cc < g.C ? bin_exp(x_absmax != nullptr ? x_absmax[cc] : 1.0f) - bin_exp(mw) : 0;
+        if (half == 0) stc[cl & 1][cl >> 1] = tc;
+        if (blockIdx.y == 0 && cc < g.C_pad) {
+            if (half == 0) t_tab[cc] = tc;
+#pragma unroll
+            for (int e1 = 0; e1 < A; ++e1)
+                if ((e1 & 1) == half) {
+#pragma unroll
+                    for (int e2 = 0; e2 < A; ++e2)
+                        s_tab[(size_t)(e1 * A + e2) * g.C_pad + cc] = floor_half(ex.dB[e1] + ex.dB[e2] + tc);
+                }
+        }
+        __syncthreads();
+        tc0 = stc[0][lane];
+        tc1 = stc[1][lane];
+    }
+    if (c >= g.C_pad) return;
     T* U = reinterpret_cast<T*>(Uout);
-    const unsigned off = (unsigned)k * g.C_pad + c;
     const size_t plane = in_vgpr((size_t)g.K_pad * g.C_pad);
+    T* Up = U + ((size_t)k * g.C_pad + c);          // plane e = i*A + j, advanced by one plane per entry
 #pragma unroll
     for (int i = 0; i < A; ++i) {
-        // row i of P1 = G g
-        float p1[R];
+        // row i of P1 = G g for both channels
+        float p0[R], p1[R];
 #pragma unroll
-        for (int v = 0; v < R; ++v) p1[v] = 0.0f;
+        for (int v = 0; v < R; ++v) p0[v] = p1[v] = 0.0f;
 #pragma unroll
-        for (int u = 0; u < R; ++u)
-            if (nz(nzm.g, i * R + u)) {
-                const float b = sG[i][u];
+        for (int u = 0; u < R; ++u) {
+            const float b = mt.G[i][u];
 #pragma unroll
-                for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(b, gg[u][v], p1[v]);
+            for (int v = 0; v < R; ++v) {
+                p0[v] = __builtin_fmaf(b, g0[u][v], p0[v]);
+                p1[v] = __builtin_fmaf(b, g1[u][v], p1[v]);
             }
-        const int si = tc + ex.dB[i];
+        }
+        const int si0 = tc0 + ex.dB[i], si1 = tc1 + ex.dB[i];
 #pragma unroll
         for (int j = 0; j < A; ++j) {
-            float acc = 0.0f;
+            float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
-            for (int v = 0; v < R; ++v)
-                if (nz(nzm.g, j * R + v)) acc = __builtin_fmaf(sG[j][v], p1[v], acc);
-            if (DT != kF32) acc = ldexpf(acc, c < g.C ? floor_half(si + ex.dB[j]) : 0);
-            T* Ue = U + (size_t)(i * A + j) * plane;
-            Ue[off] = Elem<DT>::from_f32(acc);
+            for (int v = 0; v < R; ++v) {
+                a0 = __builtin_fmaf(mt.G[j][v], p0[v], a0);
+                a1 = __builtin_fmaf(mt.G[j][v], p1[v], a1);
+            }
+            if (DT != kF32) {                       // padded channels hold zeros
+                a0 = ldexpf(a0, floor_half(si0 + ex.dB[j]));
+                a1 = ldexpf(a1, floor_half(si1 + ex.dB[j]));
+            }
+            Elem<DT>::store2(Up, a0, a1);
+            Up += plane;
         }
     }
 }
@@ -176,7 +190,6 @@ static int filter_impl(const Plan& p, const float* w, const float* x_absmax, voi
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const Mats<M, R> mt = pack_mats<M, R>(p);
-    const NzMasks nzm = pack_masks(p);
     RowExps ex{};
     for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
     char* Ub = static_cast<char*>(U);
@@ -190,19 +203,19 @@ static int filter_impl(const Plan& p, const float* w, const float* x_absmax, voi
         const int st = last_launch("filter_absmax_kernel");
         if (st != WG_OK) return st;
     }
-    const dim3 grid((unsigned)((L.C_pad + 63) / 64), (unsigned)(L.K_pad / 4));
+    const dim3 grid((unsigned)((L.C_pad + 127) / 128), (unsigned)(L.K_pad / 4));
     switch (L.dtype) {
         case WG_F32:
             hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, w, U, part, x_absmax,
-                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
+                               s_tab, t_tab, kchunks, mt, ex, g);
             break;
         case WG_F16:
             hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16>), grid, dim3(256), 0, s, w, U, part, x_absmax,
-                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
+                               s_tab, t_tab, kchunks, mt, ex, g);
             break;
         default:
             hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16>), grid, dim3(256), 0, s, w, U, part, x_absmax,
-                               s_tab, t_tab, kchunks, mt, nzm, ex, g);
+                               s_tab, t_tab, kchunks, mt, ex, g);
             break;
     }
     return last_launch("filter_transform_kernel");

@@ -26,6 +26,8 @@ namespace wg {
 // copies each image's run with consecutive threads.  Zero entries of A^T are
 // not skipped (fma(0, x, acc) == acc for finite x).
 // ---------------------------------------------------------------------------
+constexpr int kOutThreads = 128;
+
 template <int M, int R>
 __global__ __launch_bounds__(256) void output_transform_kernel(const float* __restrict__ Mbuf,
                                                                float* __restrict__ y, Mats<M, R> mt,
@@ -39,7 +41,8 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
     const int nbands = g.N * g.Th;
     const int nbl = min(nb, nbands - band0);
     const int items = nbl * g.Tw;
-    for (int it = tid; it < items; it += 256) {
+    const int nthr = blockDim.x;
+    for (int it = tid; it < items; it += nthr) {
         const int bl = it / g.Tw, tw = it - bl * g.Tw;
         // Z = A^T M, streaming the rows of M: row a of the tile is planes
         // a*A .. a*A+A-1, read through a buffer resource on plane a*A with
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
         const int len = (row_end - row_first) * g.Wout;
         const float* src = lds + bl * M * g.Wout;
         float* dst = y + (((size_t)n * g.K + k) * g.Hout + row_first) * g.Wout;
-        for (int q = tid; q < len; q += 256) dst[q] = src[q];
+        for (int q = tid; q < len; q += nthr) dst[q] = src[q];
         bl = last;
     }
 }
@@ -109,7 +112,8 @@ static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const Mats<M, R> mt = pack_mats<M, R>(p);
-    int nb = 256 / L.Tw;
+    const int nthr = kOutThreads;
+    int nb = nthr / L.Tw;
     if (nb < 1) nb = 1;
     while (nb > 1 && (size_t)nb * M * L.Wout * sizeof(float) > 65536) --nb;
     const size_t lds_bytes = (size_t)nb * M * L.Wout * sizeof(float);
@@ -121,7 +125,7 @@ static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
     const int nbands = L.N * L.Th;
     const dim3 grid((unsigned)((nbands + nb - 1) / nb), (unsigned)L.K);
     const float* Mbuf = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.m_offset);
-    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(256), lds_bytes, s, Mbuf, y, mt, g, nb,
+    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(nthr), lds_bytes, s, Mbuf, y, mt, g, nb,
                        (unsigned)plane_elems, (unsigned)(plane_elems * sizeof(float)));
     return last_launch("output_transform_kernel");
 }
