@@ -113,6 +113,8 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
     constexpr int B_CHUNKS = BN * kStepBytes / 16;
     constexpr int A_PER_T = A_CHUNKS / 256, B_PER_T = B_CHUNKS / 256;
     static_assert(A_CHUNKS % 256 == 0 && B_CHUNKS % 256 == 0, "tile too small");
+    constexpr int kStagePitch = BN + 4;               // floats per staged row of M
+    static_assert((BM / 2) * kStagePitch * 4 <= (BM + BN) * kPitchBytes, "epilogue stage exceeds one buffer");
 
     __shared__ __attribute__((aligned(16))) char smem[2 * (BM + BN) * kPitchBytes];
 
@@ -178,7 +180,6 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
         }
     };
 
-    const int lane_off = ((4 * half) * P_pad + wn * WN + l32) * 4;   // bytes, inside a tile
 
     // one pipeline over all (tile, step) pairs of the block: the next pair's
     // global loads are in flight while the current pair is multiplied, also
@@ -223,28 +224,42 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
             if (more) sstore(buf ^ 1);
             __syncthreads();
         }
-        // 32 x 32 accumulator layout: lane holds column (lane % 32) and, in
-        // register r, row 8*(r/4) + 4*(lane/32) + r%4.  Stores go through a
-        // buffer resource on the tile's base: the lane part of the offset is
-        // one VGPR, the row part a scalar, so no 64-bit address is formed
-        // per store.
+        // Epilogue through LDS: the buffer the last step consumed is free (the
+        // other one may already hold the next tile's first step), and holds
+        // half a tile.  In round h the waves of row group wm == h write their
+        // accumulators there (32 x 32 layout: lane holds column lane % 32
+        // and, in register r, row 8*(r/4) + 4*(lane/32) + r%4); then every
+        // thread writes 16 bytes of a full tile row, so each store
+        // instruction covers two whole 512-byte rows of M.  Stores go through
+        // a buffer resource on the tile (lane offset in a VGPR, no 64-bit
+        // address per store).
         const int ct = t0 + t * tstride;
         const int kb = ct % nKb, pb = (ct / nKb) % nPb, e = ct / (nKb * nPb);
         float* Mg = Mout + ((size_t)e * K_pad + (size_t)kb * BM) * P_pad + (size_t)pb * BN;
         const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(Mg, 0, BM * P_pad * 4, kBufferWord3);
-        int rstride = P_pad * 4;
-        asm volatile("" : "+s"(rstride));            // keep the row offsets out of the loop
+        float* stage = reinterpret_cast<float*>(smem + ((it & 1) ^ 1) * (BM + BN) * kPitchBytes);
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int h = 0; h < 2; ++h) {
+            if (wm == h) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int srow = wm * WM + i * 32 + 8 * (r >> 2) + (r & 3);
-                    const float v = acc[i][j][r];    // a named copy: element lvalues are not bit-castable
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc, lane_off + j * 128,
-                                                          srow * rstride, 0);
-                }
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row = i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            stage[row * kStagePitch + wn * WN + j * 32 + l32] = acc[i][j][r];
+                        }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = tid; q < WM * (BN / 4); q += 256) {
+                const int row = q / (BN / 4), c4 = q - row * (BN / 4);
+                const u32x4 v = *reinterpret_cast<const u32x4*>(stage + row * kStagePitch + 4 * c4);
+                __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, ((h * WM + row) * P_pad + 4 * c4) * 4, 0, 0);
+            }
+            __syncthreads();
+        }
     }
 }
 
