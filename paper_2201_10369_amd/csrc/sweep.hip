@@ -199,10 +199,11 @@ __global__ void sweep_prefix_kernel(const double* __restrict__ ref_abs, int n_po
 // candidate is staged in LDS as columns of B^T, columns and rows of G and
 // columns and rows of A^T (each padded to a multiple of 4 floats, read as
 // broadcast 16-byte loads).  Every term is a fused multiply-add in ascending
-// index order from zero; zero matrix entries are not skipped, which changes
-// nothing because fma(0, x, acc) == acc for the finite values involved
-// (flagged candidates, the only ones that could hold non-finite entries, are
-// never evaluated).
+// index order from zero; the exact zeros that every family set has are left
+// out at compile time (FamilyZeros), other zero entries are not tested for,
+// which changes nothing because fma(0, x, acc) == acc for the finite values
+// involved (flagged candidates, the only ones that could hold non-finite
+// entries, are never evaluated).
 // ---------------------------------------------------------------------------
 template <int M, int R>
 struct EvalLds {
@@ -230,6 +231,28 @@ struct EvalLds {
     }
 };
 
+// Exact zeros that every family set has (it contains 0, at index z0, and
+// ends with infinity): column 0 of B^T only in row z0 (every other row's
+// polynomial has the factor x) and column alpha-1 only in the infinity row;
+// row z0 of G only in column 0 (0^k) and the infinity row only in column
+// r-1; column z0 of A^T only in row 0 and the infinity column only in row
+// m-1.  Terms with these entries are left out (fma(0, x, acc) == acc for the
+// finite values involved, so nothing changes).
+template <int M, int R>
+struct FamilyZeros {
+    static constexpr int A = M + R - 1;
+    static constexpr int Z0 = A == 4 ? 1 : (A == 5 ? 0 : 2);     // position of 0 in the family order
+    __device__ static constexpr bool bt(int i, int l) {          // B^T[i][l] may be nonzero
+        return !((l == 0 && i != Z0) || (l == A - 1 && i != A - 1));
+    }
+    __device__ static constexpr bool g(int j, int v) {           // G[j][v]
+        return !((j == Z0 && v != 0) || (j == A - 1 && v != R - 1));
+    }
+    __device__ static constexpr bool at(int k, int i) {          // A^T[k][i]
+        return !((i == Z0 && k != 0) || (i == A - 1 && k != M - 1));
+    }
+};
+
 template <int N>
 __device__ __forceinline__ void lds_vec(const float* p, float (&v)[N]) {
     static_assert(N % 4 == 0, "padded length");
@@ -246,6 +269,7 @@ template <int M, int R>
 __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
                                                 const double* __restrict__ yref, int s, int np, const float* lds) {
     using L = EvalLds<M, R>;
+    using Z = FamilyZeros<M, R>;
     constexpr int A = L::A, AP = L::AP, MP = L::MP, RP = L::RP;
     float gg[R][R];
 #pragma unroll
@@ -266,8 +290,10 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
         lds_vec(lds + L::kBc + l * AP, bc);
 #pragma unroll
         for (int i = 0; i < A; ++i)
+            if (Z::bt(i, l)) {
 #pragma unroll
-            for (int b = 0; b < A; ++b) t1[i][b] = __builtin_fmaf(bc[i], drow[b], t1[i][b]);
+                for (int b = 0; b < A; ++b) t1[i][b] = __builtin_fmaf(bc[i], drow[b], t1[i][b]);
+            }
     }
     // V = T1 B, one column of B^T at a time
     float vv[A][A];
@@ -282,7 +308,8 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
 #pragma unroll
         for (int i = 0; i < A; ++i)
 #pragma unroll
-            for (int j = 0; j < A; ++j) vv[i][j] = __builtin_fmaf(t1[i][l], bc[j], vv[i][j]);
+            for (int j = 0; j < A; ++j)
+                if (Z::bt(j, l)) vv[i][j] = __builtin_fmaf(t1[i][l], bc[j], vv[i][j]);
     }
     // row i of U = G g G^T, Hadamard with row i of V, accumulate Z = A^T Mh
     float z[M][A];
@@ -298,8 +325,10 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
         for (int v = 0; v < R; ++v) p1[v] = 0.0f;
 #pragma unroll
         for (int u = 0; u < R; ++u)
+            if (Z::g(i, u)) {
 #pragma unroll
-            for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(gr[u], gg[u][v], p1[v]);
+                for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(gr[u], gg[u][v], p1[v]);
+            }
 #pragma unroll
         for (int j = 0; j < A; ++j) urow[j] = 0.0f;
 #pragma unroll
@@ -307,14 +336,16 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
             float gc[AP];
             lds_vec(lds + L::kGc + v * AP, gc);
 #pragma unroll
-            for (int j = 0; j < A; ++j) urow[j] = __builtin_fmaf(gc[j], p1[v], urow[j]);
+            for (int j = 0; j < A; ++j)
+                if (Z::g(j, v)) urow[j] = __builtin_fmaf(gc[j], p1[v], urow[j]);
         }
         lds_vec(lds + L::kAc + i * MP, ac);
 #pragma unroll
         for (int j = 0; j < A; ++j) {
             const float mh = urow[j] * vv[i][j];
 #pragma unroll
-            for (int k = 0; k < M; ++k) z[k][j] = __builtin_fmaf(ac[k], mh, z[k][j]);
+            for (int k = 0; k < M; ++k)
+                if (Z::at(k, i)) z[k][j] = __builtin_fmaf(ac[k], mh, z[k][j]);
         }
     }
     // Y = Z A, one row of A^T at a time
@@ -327,7 +358,8 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
         for (int k = 0; k < M; ++k) {
             float y = 0.0f;
 #pragma unroll
-            for (int j = 0; j < A; ++j) y = __builtin_fmaf(z[k][j], ar[j], y);
+            for (int j = 0; j < A; ++j)
+                if (Z::at(q, j)) y = __builtin_fmaf(z[k][j], ar[j], y);
             err += fabs((double)y - yref[(size_t)(k * M + q) * np + s]);
         }
     }
@@ -341,6 +373,7 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
                                                 const double* __restrict__ yref, const int (&s)[T],
                                                 const bool (&ok)[T], int np, const float* lds) {
     using L = EvalLds<M, R>;
+    using Z = FamilyZeros<M, R>;
     constexpr int A = L::A, AP = L::AP, MP = L::MP;
     float gv[T][R], dv[T][A], u[T][A], v[T][A];
 #pragma unroll
@@ -359,7 +392,8 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int i = 0; i < A; ++i) u[t][i] = __builtin_fmaf(gc[i], gv[t][k], u[t][i]);
+            for (int i = 0; i < A; ++i)
+                if (Z::g(i, k)) u[t][i] = __builtin_fmaf(gc[i], gv[t][k], u[t][i]);
     }
 #pragma unroll
     for (int l = 0; l < A; ++l) {                       // V = B^T d, column l of B^T
@@ -368,7 +402,8 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int i = 0; i < A; ++i) v[t][i] = __builtin_fmaf(bc[i], dv[t][l], v[t][i]);
+            for (int i = 0; i < A; ++i)
+                if (Z::bt(i, l)) v[t][i] = __builtin_fmaf(bc[i], dv[t][l], v[t][i]);
     }
     float y[T][M];
 #pragma unroll
@@ -383,7 +418,8 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
         for (int t = 0; t < T; ++t) {
             const float mh = u[t][i] * v[t][i];
 #pragma unroll
-            for (int j = 0; j < M; ++j) y[t][j] = __builtin_fmaf(ac[j], mh, y[t][j]);
+            for (int j = 0; j < M; ++j)
+                if (Z::at(j, i)) y[t][j] = __builtin_fmaf(ac[j], mh, y[t][j]);
         }
     }
     double err = 0.0;
