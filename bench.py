@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--c", type=float, default=2.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-tiles", type=int, default=640)
+    ap.add_argument("--cpu-tiles", type=int, default=1200)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate search")
     return ap.parse_args()
 

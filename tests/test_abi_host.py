@@ -167,3 +167,16 @@ def test_gemm_tiles_knob_validation():
         with pytest.raises(wg.WGError):
             plan.gemm_tiles = bad
     assert plan.gemm_tiles == 4
+
+
+def test_gemm_autotune_argument_checks():
+    """Argument errors are reported before any device work."""
+    L = wg.lib()
+    plan = wg.Plan(6, 3, [0, 1, -1, 2, -2, 0.5, -0.5], 2, 8, 8, 12, 12)
+    chosen = ctypes.c_int(0)
+    fake = ctypes.c_void_p(256)
+    assert L.wg_plan_autotune_gemm(None, fake, fake, 1 << 30, 4, ctypes.byref(chosen), None) == -1
+    assert L.wg_plan_autotune_gemm(plan.handle, None, fake, 1 << 30, 4, ctypes.byref(chosen), None) == -1
+    assert L.wg_plan_autotune_gemm(plan.handle, fake, fake, 1 << 30, 0, ctypes.byref(chosen), None) == -1
+    assert L.wg_plan_autotune_gemm(plan.handle, fake, fake, 16, 4, ctypes.byref(chosen), None) == -4
+    assert chosen.value == 0 and plan.gemm_tiles == 1

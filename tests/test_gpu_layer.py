@@ -175,6 +175,22 @@ def test_gemm_tiles_per_block_do_not_change_results(case, dtype):
         assert torch.equal(o, outs[0])
 
 
+def test_gemm_autotuner_picks_a_candidate_and_keeps_results():
+    """The GEMM autotuner times its candidates on the caller's operands, keeps
+    one of them, and the GEMM then writes the same M as with the default."""
+    m, r, fam, N, C, K, H, W, padding = CASES[2]
+    plan, x, w, xd, wd, U, ax = _setup(m, r, _pts(fam), N, C, K, H, W, padding, "f16")
+    ws = plan.empty_workspace()
+    plan.input_transform(xd, U, ws)
+    plan.hadamard_gemm(U, ws)
+    ref = torch.nan_to_num(plan.view_M(ws), nan=0.0).clone()
+    chosen = plan.autotune_gemm(U, ws, reps=2)
+    assert chosen in (1, 2, 3, 4, 6, 8) and plan.gemm_tiles == chosen
+    plan.view_M(ws).fill_(-7.0)
+    plan.hadamard_gemm(U, ws)
+    assert torch.equal(torch.nan_to_num(plan.view_M(ws), nan=0.0), ref)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("case", CASES)
 def test_forward_matches_oracle(case, dtype):
