@@ -209,6 +209,9 @@ int wg_conv2d_forward(const wg_plan* plan, const float* x, const void* U, float*
 /* The three stages of wg_conv2d_forward, separately (same buffers):
  *   input:  V'[e][p][c] = scaled/rounded (B^T d B)[e] of tile p, channel c
  *   gemm:   M[e][k][p] = sum_c U'[e][k][c] V'[e][p][c]  (float32 accumulation)
+ *           for k < K, p < P; the padding of M (k >= K, and p >= P from the
+ *           first multiple of 4 at or above P) is left unwritten, and the
+ *           padding rows of U' and V' are not read
  *   output: y tile p, channel k = (A^T M[.][k][p] A), outputs past the edge
  *           discarded. */
 int wg_input_transform(const wg_plan* plan, const float* x, const void* U,

@@ -103,7 +103,7 @@ struct MfmaOp<kBF16> {
 template <int BM, int BN, int DT>
 __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restrict__ U,
                                                             const char* __restrict__ V,
-                                                            float* __restrict__ Mout, int K_pad,
+                                                            float* __restrict__ Mout, int K, int K_pad, int P,
                                                             int P_pad, int C_pad, int nKb, int nPb,
                                                             int total, int tiles_per_xcd, int blocks_per_xcd) {
     constexpr int WM = BM / 2, WN = BN / 2;          // wave sub-tile
@@ -138,29 +138,36 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
 
     const size_t row_bytes = (size_t)C_pad * ELEM;
     // tile t -> (e, pb, kb) with kb fastest
+    // operand tiles are read through buffer resources that end at the last
+    // real row (k < K for U', p < P for V'): padding rows read as zero without
+    // touching memory
+    u32x4 ra[A_PER_T], rb[B_PER_T];
+    auto tile_rsrc = [&](const char* base, int rows_left, int rows) {
+        const int n = rows_left < rows ? (rows_left > 0 ? rows_left : 0) : rows;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, (int)(n * row_bytes), kBufferWord3);
+    };
     auto a_tile = [&](int t) {
         const int kb = t % nKb, e = t / (nKb * nPb);
-        return U + ((size_t)e * K_pad + (size_t)kb * BM) * row_bytes;
+        return tile_rsrc(U + ((size_t)e * K_pad + (size_t)kb * BM) * row_bytes, K - kb * BM, BM);
     };
     auto b_tile = [&](int t) {
         const int pb = (t / nKb) % nPb, e = t / (nKb * nPb);
-        return V + ((size_t)e * P_pad + (size_t)pb * BN) * row_bytes;
+        return tile_rsrc(V + ((size_t)e * P_pad + (size_t)pb * BN) * row_bytes, P - pb * BN, BN);
     };
 
-    u32x4 ra[A_PER_T], rb[B_PER_T];
-    auto gload = [&](const char* Ag, const char* Bg, int step) {
-        const size_t koff = (size_t)step * kStepBytes;
+    auto gload = [&](const __amdgpu_buffer_rsrc_t& Ar, const __amdgpu_buffer_rsrc_t& Br, int step) {
+        const int koff = step * kStepBytes;
 #pragma unroll
         for (int i = 0; i < A_PER_T; ++i) {
             const int q = tid + i * 256;
             const int row = q >> 3, ch = q & 7;
-            ra[i] = *reinterpret_cast<const u32x4*>(Ag + row * row_bytes + koff + ch * 16);
+            ra[i] = __builtin_amdgcn_raw_buffer_load_b128(Ar, (int)(row * row_bytes) + koff + ch * 16, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < B_PER_T; ++i) {
             const int q = tid + i * 256;
             const int row = q >> 3, ch = q & 7;
-            rb[i] = *reinterpret_cast<const u32x4*>(Bg + row * row_bytes + koff + ch * 16);
+            rb[i] = __builtin_amdgcn_raw_buffer_load_b128(Br, (int)(row * row_bytes) + koff + ch * 16, 0, 0);
         }
     };
     auto sstore = [&](int buf) {
@@ -186,8 +193,8 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
     // across tile boundaries, where the finished tile is written out
     const int nsteps = (int)(row_bytes / kStepBytes);
     const int niter = nt * nsteps;
-    const char* nA = a_tile(t0);
-    const char* nB = b_tile(t0);
+    __amdgpu_buffer_rsrc_t nA = a_tile(t0);
+    __amdgpu_buffer_rsrc_t nB = b_tile(t0);
     gload(nA, nB, 0);
     sstore(0);
     __syncthreads();
@@ -236,7 +243,11 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
         const int ct = t0 + t * tstride;
         const int kb = ct % nKb, pb = (ct / nKb) % nPb, e = ct / (nKb * nPb);
         float* Mg = Mout + ((size_t)e * K_pad + (size_t)kb * BM) * P_pad + (size_t)pb * BN;
-        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(Mg, 0, BM * P_pad * 4, kBufferWord3);
+        // rows k >= K fall outside the resource (dropped); 16-byte column
+        // groups starting at p >= P are not written
+        const int krows = min(BM, K - kb * BM);
+        const int pcols = P - pb * BN;
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(Mg, 0, krows * P_pad * 4, kBufferWord3);
         float* stage = reinterpret_cast<float*>(smem + ((it & 1) ^ 1) * (BM + BN) * kPitchBytes);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -256,7 +267,8 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
             for (int q = tid; q < WM * (BN / 4); q += 256) {
                 const int row = q / (BN / 4), c4 = q - row * (BN / 4);
                 const u32x4 v = *reinterpret_cast<const u32x4*>(stage + row * kStagePitch + 4 * c4);
-                __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, ((h * WM + row) * P_pad + 4 * c4) * 4, 0, 0);
+                if (4 * c4 < pcols)
+                    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, ((h * WM + row) * P_pad + 4 * c4) * 4, 0, 0);
             }
             __syncthreads();
         }
@@ -270,14 +282,15 @@ static int gemm_launch(const Plan& p, const void* U, void* ws, hipStream_t s) {
     const long total = (long)L.alpha * L.alpha * nKb * nPb;
     if (total > (1L << 30)) return fail(WG_EUNSUPPORTED, "hadamard gemm: too many tiles");
     // the epilogue addresses one tile with 32-bit byte offsets
-    if ((long)BM * L.P_pad * 4 >= (1L << 31)) return fail(WG_EUNSUPPORTED, "hadamard gemm: tile rows too long");
+    if ((long)BM * L.P_pad * 4 >= (1L << 31) || (long)BN * L.C_pad * 4 >= (1L << 31))
+        return fail(WG_EUNSUPPORTED, "hadamard gemm: tile rows too long");
     const int tpb = p.gemm_tpb > 0 ? p.gemm_tpb : 1;
     const int tiles_per_xcd = (int)((total + kXcds - 1) / kXcds);
     const int blocks_per_xcd = (tiles_per_xcd + tpb - 1) / tpb;
     const char* V = static_cast<const char*>(ws) + L.v_offset;
     float* Mb = reinterpret_cast<float*>(static_cast<char*>(ws) + L.m_offset);
     hipLaunchKernelGGL((hadamard_gemm_kernel<BM, BN, DT>), dim3((unsigned)(blocks_per_xcd * kXcds)), dim3(256), 0, s,
-                       static_cast<const char*>(U), V, Mb, L.K_pad, L.P_pad, L.C_pad, nKb, nPb, (int)total,
+                       static_cast<const char*>(U), V, Mb, L.K, L.K_pad, L.P, L.P_pad, L.C_pad, nKb, nPb, (int)total,
                        tiles_per_xcd, blocks_per_xcd);
     return hip_check((int)hipGetLastError(), "hadamard_gemm_kernel");
 }

@@ -162,17 +162,22 @@ def test_gemm_tiles_per_block_do_not_change_results(case, dtype):
     plan, x, w, xd, wd, U, ax = _setup(m, r, _pts(fam), N, C, K, H, W, padding, dtype)
     ws = plan.empty_workspace()
     plan.input_transform(xd, U, ws)
+    L = plan.layout
     outs = []
     for t in (1, 2, 3, 7):
         plan.gemm_tiles = t
         assert plan.gemm_tiles == t
         plan.view_M(ws).fill_(1e30 * t)               # a different sentinel per run
         plan.hadamard_gemm(U, ws)
-        # columns p >= P come from unwritten V' rows and may hold NaN in
-        # every run alike
-        outs.append(torch.nan_to_num(plan.view_M(ws), nan=0.0))
+        Mv = plan.view_M(ws)
+        outs.append(Mv[:, :K, :L["P"]].clone())       # the real (k, p) entries
+        # padding rows k >= K and the 4-column groups that start at p >= P
+        # are not written
+        p4 = -(-L["P"] // 4) * 4
+        assert bool((Mv[:, K:, :] == 1e30 * t).all()) and bool((Mv[:, :, p4:] == 1e30 * t).all())
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+    assert torch.isfinite(outs[0]).all()
 
 
 def test_gemm_autotuner_picks_a_candidate_and_keeps_results():
@@ -181,14 +186,15 @@ def test_gemm_autotuner_picks_a_candidate_and_keeps_results():
     m, r, fam, N, C, K, H, W, padding = CASES[2]
     plan, x, w, xd, wd, U, ax = _setup(m, r, _pts(fam), N, C, K, H, W, padding, "f16")
     ws = plan.empty_workspace()
+    P = plan.layout["P"]
     plan.input_transform(xd, U, ws)
     plan.hadamard_gemm(U, ws)
-    ref = torch.nan_to_num(plan.view_M(ws), nan=0.0).clone()
+    ref = plan.view_M(ws)[:, :K, :P].clone()
     chosen = plan.autotune_gemm(U, ws, reps=2)
     assert chosen in (1, 2, 3, 4, 6, 8) and plan.gemm_tiles == chosen
     plan.view_M(ws).fill_(-7.0)
     plan.hadamard_gemm(U, ws)
-    assert torch.equal(torch.nan_to_num(plan.view_M(ws), nan=0.0), ref)
+    assert torch.equal(plan.view_M(ws)[:, :K, :P], ref)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
