@@ -12,12 +12,16 @@
 //
 // Tiling: a 256-thread block computes a BM x BN tile of M[e] with four waves
 // in a 2 x 2 arrangement, each wave a (BM/2) x (BN/2) sub-tile made of 32 x 32
-// MFMA blocks.  The contraction runs in steps of BK elements (128 bytes of
-// each operand row) through double-buffered LDS, with the next step's global
-// loads in flight while the current one is multiplied; a block may take
-// several tiles, and the pipeline then runs on across the tile boundaries.
-// Block ids are mapped so that the blocks running together on one XCD work on
-// neighbouring tiles (same e) and share its L2.
+// MFMA blocks.  The contraction runs in steps of 64 bytes of each operand row
+// through a ring of kStages LDS stages filled by direct global-to-LDS buffer
+// loads (no staging registers): the loads of kStages-1 steps are in flight
+// while one is multiplied.  Within a stage an operand row is 64 bytes; its
+// four 16-byte chunks are stored XOR-swizzled by bits 2-3 of the row index,
+// so the 32 rows an MFMA operand read touches spread over all banks.  The
+// operand buffer resources end at the last real row, so padding rows are not
+// fetched (they read as zero).  The finished tile goes out through LDS as
+// whole 512-byte rows of M.  Block ids are mapped so that the blocks running
+// together on one XCD work on neighbouring tiles (same e) and share its L2.
 //
 // Element types: float32 (v_mfma_f32_32x32x2_f32), float16 and bfloat16 with
 // float32 accumulation (v_mfma_f32_32x32x16_{f16,bf16}).
@@ -29,20 +33,22 @@
 namespace wg {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int kXcds = 8;
 // Word 3 of a raw buffer resource on gfx9-family chips (dword data format,
-// no swizzle); out-of-range stores are dropped by the hardware.
+// no swizzle); out-of-range loads read zero and out-of-range stores are
+// dropped by the hardware.
 constexpr int kBufferWord3 = 0x00020000;
 
-// Bytes per operand row per contraction step, and LDS row pitch (16 bytes of
-// padding keep the 16-byte LDS reads of 8 consecutive rows on distinct banks).
-constexpr int kStepBytes = 128;
-constexpr int kPitchBytes = kStepBytes + 16;
+constexpr int kStepBytes = 64;        // bytes of each operand row per pipeline step
+constexpr int kStages = 4;            // LDS ring depth
+
+// byte offset of 16-byte chunk c of row r inside a stage region
+__device__ __forceinline__ int chunk_at(int r, int c) { return r * kStepBytes + ((c ^ ((r >> 2) & 3)) << 4); }
 
 template <int DT>
 struct MfmaOp;
@@ -50,35 +56,34 @@ struct MfmaOp;
 template <>
 struct MfmaOp<kF32> {
     static constexpr int kElem = 4;
-    // per 128-byte step (32 floats): each half-wave holds 16 consecutive k of
-    // one row; instruction q multiplies element q of both operands.
-    __device__ static __forceinline__ void step(const char* a_row, const char* b_row, int half,
+    // per 64-byte step (16 floats): half-wave h holds k = 8h .. 8h+7 of its
+    // row (chunks 2h, 2h+1); instruction q multiplies element q of both.
+    __device__ static __forceinline__ void step(const char* A, const char* B, int ra, int rb, int half,
                                                 f32x16& acc) {
-        const f32x4* pa = reinterpret_cast<const f32x4*>(a_row + half * 64);
-        const f32x4* pb = reinterpret_cast<const f32x4*>(b_row + half * 64);
+        const u32x4 a0 = *reinterpret_cast<const u32x4*>(A + chunk_at(ra, 2 * half));
+        const u32x4 a1 = *reinterpret_cast<const u32x4*>(A + chunk_at(ra, 2 * half + 1));
+        const u32x4 b0 = *reinterpret_cast<const u32x4*>(B + chunk_at(rb, 2 * half));
+        const u32x4 b1 = *reinterpret_cast<const u32x4*>(B + chunk_at(rb, 2 * half + 1));
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const f32x4 a = pa[v];
-            const f32x4 b = pb[v];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], acc, 0, 0, 0);
-        }
+        for (int q = 0; q < 4; ++q)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a0[q]), __uint_as_float(b0[q]), acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a1[q]), __uint_as_float(b1[q]), acc, 0, 0, 0);
     }
 };
 
 template <>
 struct MfmaOp<kF16> {
     static constexpr int kElem = 2;
-    // per 128-byte step (64 halves): 4 instructions of k = 16, each half-wave
-    // holding 8 consecutive k of its row.
-    __device__ static __forceinline__ void step(const char* a_row, const char* b_row, int half,
+    // per 64-byte step (32 halves): two instructions of k = 16, half-wave h
+    // holding 8 consecutive k (chunk 2s + h of slice s).
+    __device__ static __forceinline__ void step(const char* A, const char* B, int ra, int rb, int half,
                                                 f32x16& acc) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const u32x4 a = *reinterpret_cast<const u32x4*>(a_row + s * 32 + half * 16);
-            const u32x4 b = *reinterpret_cast<const u32x4*>(b_row + s * 32 + half * 16);
+        for (int s = 0; s < 2; ++s) {
+            const u32x4 a = *reinterpret_cast<const u32x4*>(A + chunk_at(ra, 2 * s + half));
+            const u32x4 b = *reinterpret_cast<const u32x4*>(B + chunk_at(rb, 2 * s + half));
             acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
                                                          __builtin_bit_cast(f16x8, b), acc, 0, 0, 0);
         }
@@ -88,17 +93,37 @@ struct MfmaOp<kF16> {
 template <>
 struct MfmaOp<kBF16> {
     static constexpr int kElem = 2;
-    __device__ static __forceinline__ void step(const char* a_row, const char* b_row, int half,
+    __device__ static __forceinline__ void step(const char* A, const char* B, int ra, int rb, int half,
                                                 f32x16& acc) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const u32x4 a = *reinterpret_cast<const u32x4*>(a_row + s * 32 + half * 16);
-            const u32x4 b = *reinterpret_cast<const u32x4*>(b_row + s * 32 + half * 16);
+        for (int s = 0; s < 2; ++s) {
+            const u32x4 a = *reinterpret_cast<const u32x4*>(A + chunk_at(ra, 2 * s + half));
+            const u32x4 b = *reinterpret_cast<const u32x4*>(B + chunk_at(rb, 2 * s + half));
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                           __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
         }
     }
 };
+
+// s_waitcnt vmcnt(n) for the few counts the ring needs (expcnt and lgkmcnt
+// left at their maxima)
+__device__ __forceinline__ void wait_vmcnt(int n) {
+    switch (n) {
+        case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+        case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+        case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+        case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
+        case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
+        default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    }
+}
+
+// barrier without a memory fence (the waits are explicit), and no compiler
+// motion of memory accesses across it
+__device__ __forceinline__ void block_barrier() {
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 template <int BM, int BN, int DT>
 __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restrict__ U,
@@ -109,14 +134,15 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
     constexpr int WM = BM / 2, WN = BN / 2;          // wave sub-tile
     constexpr int FM = WM / 32, FN = WN / 32;         // 32 x 32 blocks per wave
     constexpr int ELEM = MfmaOp<DT>::kElem;
-    constexpr int A_CHUNKS = BM * kStepBytes / 16;    // 16-byte chunks per A tile
-    constexpr int B_CHUNKS = BN * kStepBytes / 16;
-    constexpr int A_PER_T = A_CHUNKS / 256, B_PER_T = B_CHUNKS / 256;
-    static_assert(A_CHUNKS % 256 == 0 && B_CHUNKS % 256 == 0, "tile too small");
+    constexpr int ROWS = BM + BN;                     // operand rows per stage (A then B)
+    constexpr int STAGE_BYTES = ROWS * kStepBytes;
+    constexpr int LOADS = ROWS / 64;                  // 16-row DMA loads per wave per step
+    static_assert(ROWS % 64 == 0 && BM % 16 == 0, "tile shape");
     constexpr int kStagePitch = BN + 4;               // floats per staged row of M
-    static_assert((BM / 2) * kStagePitch * 4 <= (BM + BN) * kPitchBytes, "epilogue stage exceeds one buffer");
+    static_assert((BM / 2) * kStagePitch * 4 <= kStages * STAGE_BYTES, "epilogue stage exceeds the ring");
+    static_assert(kStages - 2 <= 2 && LOADS <= 4, "vmcnt table");
 
-    __shared__ __attribute__((aligned(16))) char smem[2 * (BM + BN) * kPitchBytes];
+    __shared__ __attribute__((aligned(16))) char smem[kStages * STAGE_BYTES];
 
     // XCD-aware work mapping: XCD x (blocks b = x mod 8) owns the contiguous
     // tile range [x * tiles_per_xcd, (x+1) * tiles_per_xcd); its block in
@@ -135,71 +161,43 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;   // wave index is uniform
     const int wm = wave >> 1, wn = wave & 1;
     const int half = lane >> 5, l32 = lane & 31;
+    const int row_bytes = C_pad * ELEM;
+    const int nsteps = row_bytes / kStepBytes;
 
-    const size_t row_bytes = (size_t)C_pad * ELEM;
-    // tile t -> (e, pb, kb) with kb fastest
-    // operand tiles are read through buffer resources that end at the last
-    // real row (k < K for U', p < P for V'): padding rows read as zero without
-    // touching memory
-    u32x4 ra[A_PER_T], rb[B_PER_T];
-    auto tile_rsrc = [&](const char* base, int rows_left, int rows) {
-        const int n = rows_left < rows ? (rows_left > 0 ? rows_left : 0) : rows;
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, (int)(n * row_bytes), kBufferWord3);
-    };
-    auto a_tile = [&](int t) {
-        const int kb = t % nKb, e = t / (nKb * nPb);
-        return tile_rsrc(U + ((size_t)e * K_pad + (size_t)kb * BM) * row_bytes, K - kb * BM, BM);
-    };
-    auto b_tile = [&](int t) {
-        const int pb = (t / nKb) % nPb, e = t / (nKb * nPb);
-        return tile_rsrc(V + ((size_t)e * P_pad + (size_t)pb * BN) * row_bytes, P - pb * BN, BN);
-    };
-
-    auto gload = [&](const __amdgpu_buffer_rsrc_t& Ar, const __amdgpu_buffer_rsrc_t& Br, int step) {
-        const int koff = step * kStepBytes;
-#pragma unroll
-        for (int i = 0; i < A_PER_T; ++i) {
-            const int q = tid + i * 256;
-            const int row = q >> 3, ch = q & 7;
-            ra[i] = __builtin_amdgcn_raw_buffer_load_b128(Ar, (int)(row * row_bytes) + koff + ch * 16, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < B_PER_T; ++i) {
-            const int q = tid + i * 256;
-            const int row = q >> 3, ch = q & 7;
-            rb[i] = __builtin_amdgcn_raw_buffer_load_b128(Br, (int)(row * row_bytes) + koff + ch * 16, 0, 0);
-        }
-    };
-    auto sstore = [&](int buf) {
-        char* As = smem + buf * (BM + BN) * kPitchBytes;
-        char* Bs = As + BM * kPitchBytes;
-#pragma unroll
-        for (int i = 0; i < A_PER_T; ++i) {
-            const int q = tid + i * 256;
-            const int row = q >> 3, ch = q & 7;
-            *reinterpret_cast<u32x4*>(As + row * kPitchBytes + ch * 16) = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < B_PER_T; ++i) {
-            const int q = tid + i * 256;
-            const int row = q >> 3, ch = q & 7;
-            *reinterpret_cast<u32x4*>(Bs + row * kPitchBytes + ch * 16) = rb[i];
-        }
-    };
-
-
-    // one pipeline over all (tile, step) pairs of the block: the next pair's
-    // global loads are in flight while the current pair is multiplied, also
-    // across tile boundaries, where the finished tile is written out
-    const int nsteps = (int)(row_bytes / kStepBytes);
-    const int niter = nt * nsteps;
-    __amdgpu_buffer_rsrc_t nA = a_tile(t0);
-    __amdgpu_buffer_rsrc_t nB = b_tile(t0);
-    gload(nA, nB, 0);
-    sstore(0);
-    __syncthreads();
-    int it = 0;
     for (int t = 0; t < nt; ++t) {
+        const int ct = t0 + t * tstride;
+        const int kb = ct % nKb, pb = (ct / nKb) % nPb, e = ct / (nKb * nPb);
+        // operand resources end at the last real row (k < K, p < P)
+        const int arows = min(BM, K - kb * BM), brows = min(BN, P - pb * BN);
+        const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char*>(U) + ((size_t)e * K_pad + (size_t)kb * BM) * row_bytes, 0, arows * row_bytes,
+            kBufferWord3);
+        const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char*>(V) + ((size_t)e * P_pad + (size_t)pb * BN) * row_bytes, 0, brows * row_bytes,
+            kBufferWord3);
+        // DMA of step st into its stage: wave w moves combined rows
+        // (w*LOADS + j)*16 .. +16; lane L takes row +L/4, stored chunk L%4,
+        // which holds global chunk (L%4) ^ swizzle(row)
+        auto issue = [&](int st) {
+            char* stage = smem + (st % kStages) * STAGE_BYTES;
+#pragma unroll
+            for (int j = 0; j < LOADS; ++j) {
+                const int R0 = (wave * LOADS + j) * 16;                   // uniform
+                const bool isA = R0 < BM;
+                const int lr = (isA ? R0 : R0 - BM) + (lane >> 2);
+                const int c = (lane & 3) ^ ((lr >> 2) & 3);
+                const int voff = lr * row_bytes + st * kStepBytes + c * 16;
+                lds_void* dst = (lds_void*)(stage + R0 * kStepBytes);
+                if (isA)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsA, dst, 16, voff, 0, 0, 0);
+                else
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsB, dst, 16, voff, 0, 0, 0);
+            }
+        };
+#pragma unroll
+        for (int s = 0; s < kStages - 1; ++s)
+            if (s < nsteps) issue(s);
+
         f32x16 acc[FM][FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -207,48 +205,31 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-        for (int st = 0; st < nsteps; ++st, ++it) {
-            const int buf = it & 1;
-            const bool more = it + 1 < niter;
-            if (more) {
-                if (st + 1 == nsteps) {
-                    nA = a_tile(t0 + (t + 1) * tstride);
-                    nB = b_tile(t0 + (t + 1) * tstride);
-                }
-                gload(nA, nB, st + 1 == nsteps ? 0 : st + 1);
-            }
-            const char* As = smem + buf * (BM + BN) * kPitchBytes;
-            const char* Bs = As + BM * kPitchBytes;
+        for (int st = 0; st < nsteps; ++st) {
+            // step st has landed once at most the later steps' loads remain
+            wait_vmcnt(min(kStages - 2, nsteps - 1 - st) * LOADS);
+            block_barrier();                         // ... in every wave; stage st-1 is free
+            if (st + kStages - 1 < nsteps) issue(st + kStages - 1);
+            const char* As = smem + (st % kStages) * STAGE_BYTES;
+            const char* Bs = As + BM * kStepBytes;
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                const char* arow = As + (wm * WM + i * 32 + l32) * kPitchBytes;
+            for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    const char* brow = Bs + (wn * WN + j * 32 + l32) * kPitchBytes;
-                    MfmaOp<DT>::step(arow, brow, half, acc[i][j]);
-                }
-            }
-            if (more) sstore(buf ^ 1);
-            __syncthreads();
+                for (int j = 0; j < FN; ++j)
+                    MfmaOp<DT>::step(As, Bs, wm * WM + i * 32 + l32, wn * WN + j * 32 + l32, half, acc[i][j]);
         }
-        // Epilogue through LDS: the buffer the last step consumed is free (the
-        // other one may already hold the next tile's first step), and holds
-        // half a tile.  In round h the waves of row group wm == h write their
-        // accumulators there (32 x 32 layout: lane holds column lane % 32
-        // and, in register r, row 8*(r/4) + 4*(lane/32) + r%4); then every
-        // thread writes 16 bytes of a full tile row, so each store
-        // instruction covers two whole 512-byte rows of M.  Stores go through
-        // a buffer resource on the tile (lane offset in a VGPR, no 64-bit
-        // address per store).
-        const int ct = t0 + t * tstride;
-        const int kb = ct % nKb, pb = (ct / nKb) % nPb, e = ct / (nKb * nPb);
+        __syncthreads();                             // every wave done with the ring
+
+        // Epilogue through LDS, in two halves: the waves of row group wm == h
+        // write their accumulators (32 x 32 layout: lane holds column
+        // lane % 32 and, in register r, row 8*(r/4) + 4*(lane/32) + r%4),
+        // then every thread writes 16 bytes of a full tile row.  Rows k >= K
+        // fall outside the store resource (dropped); 16-byte column groups
+        // starting at p >= P are not written.
         float* Mg = Mout + ((size_t)e * K_pad + (size_t)kb * BM) * P_pad + (size_t)pb * BN;
-        // rows k >= K fall outside the resource (dropped); 16-byte column
-        // groups starting at p >= P are not written
-        const int krows = min(BM, K - kb * BM);
         const int pcols = P - pb * BN;
-        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(Mg, 0, krows * P_pad * 4, kBufferWord3);
-        float* stage = reinterpret_cast<float*>(smem + ((it & 1) ^ 1) * (BM + BN) * kPitchBytes);
+        const __amdgpu_buffer_rsrc_t rsM = __builtin_amdgcn_make_buffer_rsrc(Mg, 0, arows * P_pad * 4, kBufferWord3);
+        float* stage = reinterpret_cast<float*>(smem);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (wm == h) {
@@ -268,7 +249,7 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
                 const int row = q / (BN / 4), c4 = q - row * (BN / 4);
                 const u32x4 v = *reinterpret_cast<const u32x4*>(stage + row * kStagePitch + 4 * c4);
                 if (4 * c4 < pcols)
-                    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, ((h * WM + row) * P_pad + 4 * c4) * 4, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b128(v, rsM, ((h * WM + row) * P_pad + 4 * c4) * 4, 0, 0);
             }
             __syncthreads();
         }
@@ -281,8 +262,9 @@ static int gemm_launch(const Plan& p, const void* U, void* ws, hipStream_t s) {
     const int nKb = L.K_pad / BM, nPb = L.P_pad / BN;
     const long total = (long)L.alpha * L.alpha * nKb * nPb;
     if (total > (1L << 30)) return fail(WG_EUNSUPPORTED, "hadamard gemm: too many tiles");
-    // the epilogue addresses one tile with 32-bit byte offsets
-    if ((long)BM * L.P_pad * 4 >= (1L << 31) || (long)BN * L.C_pad * 4 >= (1L << 31))
+    // one tile of each operand and of M is addressed with 32-bit byte offsets
+    if ((long)BM * L.P_pad * 4 >= (1L << 31) || (long)BN * L.C_pad * 4 >= (1L << 31) ||
+        (long)BM * L.C_pad * 4 >= (1L << 31))
         return fail(WG_EUNSUPPORTED, "hadamard gemm: tile rows too long");
     const int tpb = p.gemm_tpb > 0 ? p.gemm_tpb : 1;
     const int tiles_per_xcd = (int)((total + kXcds - 1) / kXcds);
