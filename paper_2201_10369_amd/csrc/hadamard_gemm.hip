@@ -45,7 +45,7 @@ constexpr int kXcds = 8;
 constexpr int kBufferWord3 = 0x00020000;
 
 constexpr int kStepBytes = 64;        // bytes of each operand row per pipeline step
-constexpr int kStages = 4;            // LDS ring depth
+constexpr int kStages = 3;            // LDS ring depth (48 KB: three blocks per CU)
 
 // byte offset of 16-byte chunk c of row r inside a stage region
 __device__ __forceinline__ int chunk_at(int r, int c) { return r * kStepBytes + ((c ^ ((r >> 2) & 3)) << 4); }
