@@ -36,8 +36,15 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
     constexpr int A = M + R - 1;
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
-    const int k = blockIdx.y;
-    const int band0 = blockIdx.x * nb;
+    // XCD-aware mapping: each XCD runs a contiguous range of (band group, k)
+    // work items, so the partial 128-byte lines of M that neighbouring band
+    // groups share are fetched into one L2
+    const int per_xcd = (int)(gridDim.x / kXcdCount);
+    const int w = (int)(blockIdx.x % kXcdCount) * per_xcd + (int)(blockIdx.x / kXcdCount);
+    const int nbg = (g.N * g.Th + nb - 1) / nb;
+    if (w >= nbg * g.K) return;
+    const int k = w / nbg;
+    const int band0 = (w - k * nbg) * nb;
     const int nbands = g.N * g.Th;
     const int nbl = min(nb, nbands - band0);
     const int items = nbl * g.Tw;
@@ -123,7 +130,9 @@ static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
     if ((size_t)L.alpha * plane_elems * sizeof(float) >= (1ull << 31))
         return fail(WG_EUNSUPPORTED, "output transform: planes of M too large");
     const int nbands = L.N * L.Th;
-    const dim3 grid((unsigned)((nbands + nb - 1) / nb), (unsigned)L.K);
+    const long items = (long)((nbands + nb - 1) / nb) * L.K;
+    if (items > (1L << 30)) return fail(WG_EUNSUPPORTED, "output transform: grid too large");
+    const dim3 grid((unsigned)((items + kXcdCount - 1) / kXcdCount * kXcdCount));
     const float* Mbuf = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.m_offset);
     hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(nthr), lds_bytes, s, Mbuf, y, mt, g, nb,
                        (unsigned)plane_elems, (unsigned)(plane_elems * sizeof(float)));
