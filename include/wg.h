@@ -181,6 +181,11 @@ int wg_plan_autotune_gemm(wg_plan* plan, const void* U, void* ws, size_t ws_byte
  * to the layer of eq. conv; Section 4.1 notes that the filter and input
  * transforms are amortised and that the channel sum of the Hadamard products
  * is a matrix product.
+ *
+ * Size limits of the launches (WG_EUNSUPPORTED when exceeded; the kernels
+ * address these ranges with 32-bit byte offsets): one image of x padded to
+ * C_pad channels below 2 GB; one row of alpha planes of M below 2 GB; 128
+ * rows of a plane of M, U' or V' below 2 GB.
  * ---------------------------------------------------------------------- */
 
 /* Filter transform U = G g G^T for every (k, c) (offline, once per weights).
