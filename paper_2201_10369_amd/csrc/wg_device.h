@@ -19,19 +19,6 @@ struct Mats {
     float BT[A][A];
 };
 
-// Bit masks of the nonzero entries of the matrices (bit i*cols + j of the
-// row-major matrix), so kernels can skip zero terms with scalar branches.
-struct NzMasks {
-    uint64_t at[2];   // m x alpha   (m * alpha <= 128)
-    uint64_t g[1];    // alpha x r   (alpha * r <= 64)
-    uint64_t bt[3];   // alpha x alpha (alpha^2 <= 192)
-};
-
-template <int N_>
-__device__ __forceinline__ bool nz(const uint64_t (&mask)[N_], int q) {
-    return (mask[q >> 6] >> (q & 63)) & 1u;
-}
-
 // Returns v unchanged but held in a vector register the compiler cannot see
 // through.  Used for the stride between the planes of a transformed tensor:
 // otherwise every plane's base address is a separate uniform value, they are

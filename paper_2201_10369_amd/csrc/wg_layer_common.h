@@ -47,18 +47,6 @@ __device__ __forceinline__ int floor_half(int d) { return d >> 1; }
 // ---------------------------------------------------------------------------
 // Host-side packing and launch helpers
 // ---------------------------------------------------------------------------
-inline NzMasks pack_masks(const Plan& p) {
-    NzMasks z{};
-    const int A = p.L.alpha, m = p.L.m, r = p.L.r;
-    for (int q = 0; q < m * A; ++q)
-        if (p.AT[q] != 0.0f) z.at[q >> 6] |= 1ull << (q & 63);
-    for (int q = 0; q < A * r; ++q)
-        if (p.G[q] != 0.0f) z.g[q >> 6] |= 1ull << (q & 63);
-    for (int q = 0; q < A * A; ++q)
-        if (p.BT[q] != 0.0f) z.bt[q >> 6] |= 1ull << (q & 63);
-    return z;
-}
-
 template <int M, int R>
 inline Mats<M, R> pack_mats(const Plan& p) {
     constexpr int A = M + R - 1;
