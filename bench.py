@@ -99,6 +99,15 @@ def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup):
     return plan, U, y, elapsed / steps * 1e3, stage_ms
 
 
+# float32 operations the evaluation kernel performs per (candidate, sample)
+# tile of the F(6,3) family sweep (multiply-adds counted twice, the exact
+# zeros of the family left out): 2D 1552 fma + 64 mul, 1D 108 fma + 8 mul
+SWEEP_FLOP_PER_TILE = {1: 2 * 108 + 8, 2: 2 * 1552 + 64}
+# vector fp32 peak without packed instructions (the build does not use
+# them): 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+FP32_VECTOR_TFLOPS = 78.6
+
+
 def bench_sweep(wg, torch, reps=5):
     """4096 candidate c values log-spaced over [0.05, 20] (family {0, inf, +-1,
     +-c, +-1/c}), each scored on its own uneven count of 500-2000 pool samples,
@@ -125,9 +134,13 @@ def bench_sweep(wg, torch, reps=5):
         o = out.cpu().numpy()
         mean = o[:, 0] / np.maximum(o[:, 2], 1)
         best = int(np.nanargmin(np.where(o[:, 3] > 0, np.inf, mean)))
+        tflops = tiles * SWEEP_FLOP_PER_TILE[dims] / (ms * 1e-3) / 1e12
         res[f"{dims}d"] = {"ms": round(ms, 4), "candidates_per_s": round(n / (ms * 1e-3)),
                            "tiles_per_s": round(tiles / (ms * 1e-3)), "tuning": S.tuning(),
-                           "best_c": float(c1[best]), "best_mean_abs": float(mean[best])}
+                           "best_c": float(c1[best]), "best_mean_abs": float(mean[best]),
+                           "roofline": {"bound": "alu", "achieved": round(tflops, 2),
+                                        "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": round(tflops / FP32_VECTOR_TFLOPS, 4)}}
     return res
 
 
