@@ -54,17 +54,17 @@ __global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restr
 
 // ---------------------------------------------------------------------------
 // Filter transform U = G g G^T.  A block covers 128 channels (64 lanes, two
-// adjacent channels each) and four filters (one per wave); each thread
-// transforms its two filter channels g = w[k][c], w[k][c+1] into all
-// alpha x alpha entries and stores each entry pair with one store, so every
-// store of U'[e][k][.] is a contiguous run of 128 channels.
+// adjacent channels each) of one filter k; wave wv takes the rows i of U
+// with i mod 4 = wv.  Each thread transforms its two filter channels
+// g = w[k][c], w[k][c+1] into those rows and stores each entry pair with one
+// store, so every store of U'[e][k][.] is a contiguous run of 128 channels.
 //
 // For the 16-bit stage the block first finishes the per-channel exponent
 // part t[c] = E(x_absmax[c]) - E(max_k |w[k][c]|) from the partial maxima of
 // all filter chunks (every block of a channel group repeats this small
 // reduction, so no second launch is needed), scales entry (i, j) by 2^s with
 // s = floor((dB[i] + dB[j] + t[c]) / 2) before rounding, and the blocks of
-// the first filter group also write t and the table s[e][c].
+// filter 0 also write t and the table s[e][c].
 // ---------------------------------------------------------------------------
 template <int M, int R, int DT>
 __global__ __launch_bounds__(256) void filter_transform_kernel(const float* __restrict__ w,
@@ -77,9 +77,9 @@ __global__ __launch_bounds__(256) void filter_transform_kernel(const float* __re
     constexpr int A = M + R - 1;
     using T = typename Elem<DT>::T;
     __shared__ int stc[2][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c = blockIdx.x * 128 + 2 * lane;            // channels c, c + 1
-    const int k = blockIdx.y * 4 + wv;
+    const int k = blockIdx.y;
     // the filter taps first, so their loads overlap the exponent reduction
     float g0[R][R], g1[R][R];
     const bool live0 = k < g.K && c < g.C, live1 = k < g.K && c + 1 < g.C;
@@ -92,9 +92,9 @@ __global__ __launch_bounds__(256) void filter_transform_kernel(const float* __re
         }
     int tc0 = 0, tc1 = 0;
     if (DT != kF32) {
-        // t[c] from the partial maxima of every filter chunk: wave wv takes
-        // the channels wv*32 .. wv*32+31 of the block's 128, two chunks'
-        // worth of lanes at a time
+        // t[c] from the partial maxima of every filter chunk: the two halves
+        // of the block (one thread per channel of the block's 128) take the
+        // even and the odd chunks
         __shared__ float sred[2][128];
         const int cl = (threadIdx.x & 127), half = threadIdx.x >> 7;
         const int cc = blockIdx.x * 128 + cl;
@@ -126,9 +126,11 @@ __global__ __launch_bounds__(256) void filter_transform_kernel(const float* __re
     if (c >= g.C_pad) return;
     T* U = reinterpret_cast<T*>(Uout);
     const size_t plane = in_vgpr((size_t)g.K_pad * g.C_pad);
-    T* Up = U + ((size_t)k * g.C_pad + c);          // plane e = i*A + j, advanced by one plane per entry
+    T* const U0 = U + ((size_t)k * g.C_pad + c);
 #pragma unroll
     for (int i = 0; i < A; ++i) {
+        if ((i & 3) != wv) continue;                  // uniform over the wave
+        T* Up = U0 + (size_t)(i * A) * plane;          // plane e = i*A + j, one plane per entry
         // row i of P1 = G g for both channels
         float p0[R], p1[R];
 #pragma unroll
@@ -203,7 +205,7 @@ static int filter_impl(const Plan& p, const float* w, const float* x_absmax, voi
         const int st = last_launch("filter_absmax_kernel");
         if (st != WG_OK) return st;
     }
-    const dim3 grid((unsigned)((L.C_pad + 127) / 128), (unsigned)(L.K_pad / 4));
+    const dim3 grid((unsigned)((L.C_pad + 127) / 128), (unsigned)L.K_pad);
     switch (L.dtype) {
         case WG_F32:
             hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, w, U, part, x_absmax,

@@ -9,7 +9,8 @@
 // Section 6.1 sweeps c over a range, Section 6.3 scores many combinations).
 //
 // Launch structure (one hipGraph, replayed):
-//   construct : one thread per candidate, float64 construction -> float32
+//   construct : one thread per (candidate, matrix row), float64
+//               construction -> float32
 //   evaluate  : persistent blocks stride over work items (candidate, chunk
 //               of `chunk` samples); per item a fixed-tree block reduction
 //               writes one float64 partial sum
@@ -81,63 +82,109 @@ __device__ void product_poly_snapped(const double* roots, int n, double* coef) {
         if (fabs(coef[i]) <= tol * bnd[i]) coef[i] = 0.0;
 }
 
+// One thread per (candidate, row): thread i < alpha-1 builds what point i
+// owns (column i of A^T, row i of G, row i of B^T), thread alpha-1 the
+// infinity row and column; a block holds kConsCands candidates in slots of
+// kConsRows lanes.  Every entry gets the same float64 operations in the same
+// order as a single-thread construction would apply.  A candidate is flagged
+// (and its matrices left zero) when a parameter is zero or not finite or two
+// points coincide (|N_i| < 1e-300); it is also flagged when an entry comes
+// out non-finite.
+constexpr int kConsRows = 16;
+constexpr int kConsCands = 256 / kConsRows;
+
 template <int M, int R>
-__global__ __launch_bounds__(64) void sweep_construct_kernel(const double* __restrict__ c1,
-                                                             const double* __restrict__ c2, int n_cand,
-                                                             float* __restrict__ mats,
-                                                             int* __restrict__ flags) {
+__global__ __launch_bounds__(256) void sweep_construct_kernel(const double* __restrict__ c1,
+                                                              const double* __restrict__ c2, int n_cand,
+                                                              float* __restrict__ mats,
+                                                              int* __restrict__ flags) {
     constexpr int A = M + R - 1;
     constexpr int NF = A - 1;
-    const int cand = blockIdx.x * 64 + threadIdx.x;
-    if (cand >= n_cand) return;
-    float* out = mats + (size_t)cand * kMatStride;
+    static_assert(A <= kConsRows, "rows per candidate slot");
+    __shared__ int bad[2][kConsCands];
+    const int slot = threadIdx.x / kConsRows, i = threadIdx.x % kConsRows;
+    const int cand = blockIdx.x * kConsCands + slot;
+    const bool live = cand < n_cand && i < A;
+    if (i == 0) bad[0][slot] = bad[1][slot] = 0;
+    __syncthreads();
+    double pts[NF];
+    double x1 = 1.0, x2 = 1.0;
+    if (live) {
+        x1 = c1[cand];
+        x2 = c2 != nullptr ? c2[cand] : 1.0;
+    }
+    int flag = 0;
+    if (live && (!isfinite(x1) || x1 == 0.0 || (A > 6 && (!isfinite(x2) || x2 == 0.0)))) flag = 1;
+    if (live && !flag) family_points_dev(A, x1, x2, pts);
+    // point i and the others in order, picked with constant indices (no
+    // dynamically indexed private arrays)
+    double a = 0.0, others[NF];
+    if (live && !flag) {
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+            if (j == i) a = pts[j];
+#pragma unroll
+        for (int j = 0; j + 1 < NF; ++j) others[j] = j < i ? pts[j] : pts[j + 1];
+    }
+    double norm = 1.0;
+    if (live && !flag && i < NF) {
+#pragma unroll
+        for (int j = 0; j + 1 < NF; ++j) norm *= (a - others[j]);
+        if (!(fabs(norm) >= 1e-300) || !isfinite(norm)) flag = 1;
+    }
+    if (flag) bad[0][slot] = 1;
+    __syncthreads();
+    flag = bad[0][slot];
+    float* out = mats + (size_t)(live ? cand : 0) * kMatStride;
     float* AT = out;
     float* G = out + M * A;
     float* BT = out + M * A + A * R;
-    const double x1 = c1[cand], x2 = c2 != nullptr ? c2[cand] : 1.0;
-    int flag = 0;
-    if (!isfinite(x1) || x1 == 0.0 || (A > 6 && (!isfinite(x2) || x2 == 0.0))) flag = 1;
-    double pts[NF];
-    if (!flag) family_points_dev(A, x1, x2, pts);
-    double norm[NF];
-    if (!flag) {
-        for (int i = 0; i < NF && !flag; ++i) {
-            double prod = 1.0;
-            for (int j = 0; j < NF; ++j)
-                if (j != i) prod *= (pts[i] - pts[j]);
-            if (!(fabs(prod) >= 1e-300) || !isfinite(prod)) flag = 1;
-            norm[i] = prod;
-        }
-    }
-    for (int q = 0; q < M * A + A * R + A * A; ++q) out[q] = 0.0f;
-    if (!flag) {
-        double others[NF], coef[A + 1];
-        for (int i = 0; i < NF; ++i) {
-            const double a = pts[i];
+    float at[M], gr[R], bt[A];
+    for (int j = 0; j < M; ++j) at[j] = 0.0f;
+    for (int k = 0; k < R; ++k) gr[k] = 0.0f;
+    for (int l = 0; l < A; ++l) bt[l] = 0.0f;
+    if (live && !flag) {
+        double coef[A + 1];
+        if (i < NF) {
             double pw = 1.0;
             for (int j = 0; j < M; ++j) {
-                AT[j * A + i] = (float)pw;
+                at[j] = (float)pw;
                 pw *= a;
             }
             pw = 1.0;
             for (int k = 0; k < R; ++k) {
-                G[i * R + k] = (float)(pw / norm[i]);
+                gr[k] = (float)(pw / norm);
                 pw *= a;
             }
-            int no = 0;
-            for (int j = 0; j < NF; ++j)
-                if (j != i) others[no++] = pts[j];
-            product_poly_snapped<A>(others, no, coef);
-            for (int l = 0; l <= no; ++l) BT[i * A + l] = (float)coef[l];
+            product_poly_snapped<A>(others, NF - 1, coef);
+#pragma unroll
+            for (int l = 0; l < NF; ++l) bt[l] = (float)coef[l];
+        } else {
+            at[M - 1] = 1.0f;
+            gr[R - 1] = 1.0f;
+            product_poly_snapped<A>(pts, NF, coef);
+#pragma unroll
+            for (int l = 0; l <= NF; ++l) bt[l] = (float)coef[l];
         }
-        AT[(M - 1) * A + (A - 1)] = 1.0f;
-        G[(A - 1) * R + (R - 1)] = 1.0f;
-        product_poly_snapped<A>(pts, NF, coef);
-        for (int l = 0; l <= NF; ++l) BT[(A - 1) * A + l] = (float)coef[l];
-        for (int q = 0; q < M * A + A * R + A * A; ++q)
-            if (!isfinite(out[q])) flag = 1;
     }
-    flags[cand] = flag;
+    if (live) {
+        int nonfinite = 0;
+        for (int j = 0; j < M; ++j) {
+            AT[j * A + i] = at[j];
+            nonfinite |= !isfinite(at[j]);
+        }
+        for (int k = 0; k < R; ++k) {
+            G[i * R + k] = gr[k];
+            nonfinite |= !isfinite(gr[k]);
+        }
+        for (int l = 0; l < A; ++l) {
+            BT[i * A + l] = bt[l];
+            nonfinite |= !isfinite(bt[l]);
+        }
+        if (nonfinite) bad[1][slot] = 1;
+    }
+    __syncthreads();
+    if (live && i == 0) flags[cand] = flag | bad[1][slot];
 }
 
 // ---------------------------------------------------------------------------
@@ -528,7 +575,8 @@ struct SweepOps {
     }
     static void run(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st) {
         const int ipc = (S.n_pool + t.chunk - 1) / t.chunk;
-        hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + 63) / 64), dim3(64), 0, st, a.c1,
+        hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + kConsCands - 1) / kConsCands),
+                           dim3(256), 0, st, a.c1,
                            a.c2, a.n_cand, S.mats, S.flags);
         const long items = (long)a.n_cand * ipc;
         long grid = (long)S.n_cu * t.blocks_per_cu;
