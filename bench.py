@@ -179,6 +179,36 @@ def bench_surrogate(torch):
             "within_1pct": bool(err <= 1.01 * np.min(plain))}
 
 
+def bench_two_param(torch):
+    """(c, d) grid-and-refine search for the two-parameter families of
+    n = 9 and 10 points (F(7,3), F(8,3); Tables tab:sota_1d, tab:sota_2d),
+    against the comparison sets P9, P10, the paper's proposed (c, d) and the
+    Chebyshev nodes, all scored by the same sweep on 2000 pool samples."""
+    from paper_2201_10369_amd import pointsets as ps, search
+    from paper_2201_10369_amd import surrogate as sg
+    res = {}
+    for m in (7, 8):
+        alpha = m + 2
+        for dims in (1, 2):
+            S = sg.sweep_for(m, 3, dims=dims, max_cand=4096)
+            search.two_param_search(S, grid=8, rounds=0)          # first launches of the kernels
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = search.two_param_search(S)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pn = float(search.score_points(S, [ps.comparison_set(alpha, dims)], S.n_pool)[0])
+            c, d = ps.PROPOSED_CD[(alpha, dims)]
+            paper = float(search.score_family(S, [c], [d], S.n_pool)[0])
+            cheb = float(search.score_points(S, [ps.chebyshev(alpha)], S.n_pool)[0])
+            res[f"n{alpha}_{dims}d"] = {
+                "c": round(r["c"], 4), "d": round(r["d"], 4), "mean_abs": r["mean_abs"],
+                "comparison_set": pn, "paper_cd": paper, "chebyshev": cheb,
+                "improvement_pct": round(100.0 * (pn - r["mean_abs"]) / pn, 2),
+                "evaluations": r["evaluations"], "ms": round(1e3 * (t1 - t0), 2)}
+    return res
+
+
 def traffic_for(kernel_key):
     """HBM bytes per launch of a kernel from the committed counter summary, or
     None when the kernel's source changed since the counters were taken."""
@@ -279,6 +309,7 @@ def main():
                       "gemm_tiles_per_block": f["plan"].gemm_tiles} for d, f in forms.items()},
     }
     out["sweep"] = bench_sweep(wg, torch)
+    out["two_param"] = bench_two_param(torch)
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(torch)
     if not args.no_cpu:

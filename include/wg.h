@@ -296,6 +296,22 @@ int wg_sweep_destroy(wg_sweep* sweep);      /* NULL is accepted */
 int wg_sweep_run(wg_sweep* sweep, const double* c1, const double* c2, const int* counts,
                  int n_cand, double* out, wg_stream_t stream);
 
+/* As wg_sweep_run, for explicit point sets instead of a family: the
+ * comparison sets of Tables tab:sota_1d and tab:sota_2d, subsets of a base
+ * set (Section 5.1, eq. subset_points), or any other ordered list.
+ * pts: device float64 [n_cand][alpha - 1], each row the ordered finite
+ * points of one candidate (infinity is appended last, the modified form of
+ * Section 4.2).  The matrices are built as for a family (Sections 4.1, 4.2)
+ * and every term of every product is evaluated (no zero pattern is
+ * assumed), so a list equal to a family's points scores exactly as that
+ * family.  A candidate is flagged when a point is not finite, two points
+ * coincide, |N_i| < 1e-300 or an entry overflows float32.  Shares the
+ * tuning and graph cache of wg_sweep_run (a change between the two modes
+ * recaptures the graph).  Errors: WG_EINVAL (null pointer, n_cand out of
+ * range), WG_EHIP. */
+int wg_sweep_run_points(wg_sweep* sweep, const double* pts, const int* counts, int n_cand,
+                        double* out, wg_stream_t stream);
+
 /* Times the evaluation over a fixed set of launch shapes (block size,
  * samples per work item, persistent blocks per compute unit) on the given
  * arguments, keeps the fastest for later runs and synchronises `stream`.

@@ -65,3 +65,21 @@ def argmin(values, grid):
         if best is None or v < values[best] or (v == values[best] and grid[i] < grid[best]):
             best = i
     return best, (None if best is None else grid[best])
+
+
+def candidate_error_points(pts, m, r, dims, d, g, yref, n):
+    """L1 error sums of one explicit point list (finite points, infinity
+    implied last) on the pool prefix [0, n).  Float points are taken as the
+    exact rationals they denote."""
+    from fractions import Fraction
+    try:
+        exact = [p if isinstance(p, Fraction) else Fraction(float(p)) for p in pts]
+        mats = fp.mats_f32(exact, m, r)
+    except tc.SingularPoints:
+        return dict(abs_sum=math.inf, ref_sum=float(np.abs(yref[:n]).sum()),
+                    rel_l1=math.inf, mean_abs=math.inf, count=0, singular=True)
+    tile = fp.tile_1d_f32 if dims == 1 else fp.tile_2d_f32
+    y = tile(mats, d[:n], g[:n])
+    e = fp.l1_errors(y, yref[:n])
+    e["singular"] = False
+    return e

@@ -24,6 +24,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "wg_device.h"
 #include "wg_internal.h"
@@ -89,13 +90,15 @@ __device__ void product_poly_snapped(const double* roots, int n, double* coef) {
 // order as a single-thread construction would apply.  A candidate is flagged
 // (and its matrices left zero) when a parameter is zero or not finite or two
 // points coincide (|N_i| < 1e-300); it is also flagged when an entry comes
-// out non-finite.
+// out non-finite.  With explicit point lists (pts_in, n_cand x (alpha-1),
+// infinity implied last) a non-finite point flags the candidate instead.
 constexpr int kConsRows = 16;
 constexpr int kConsCands = 256 / kConsRows;
 
 template <int M, int R>
 __global__ __launch_bounds__(256) void sweep_construct_kernel(const double* __restrict__ c1,
-                                                              const double* __restrict__ c2, int n_cand,
+                                                              const double* __restrict__ c2,
+                                                              const double* __restrict__ pts_in, int n_cand,
                                                               float* __restrict__ mats,
                                                               int* __restrict__ flags) {
     constexpr int A = M + R - 1;
@@ -108,14 +111,18 @@ __global__ __launch_bounds__(256) void sweep_construct_kernel(const double* __re
     if (i == 0) bad[0][slot] = bad[1][slot] = 0;
     __syncthreads();
     double pts[NF];
-    double x1 = 1.0, x2 = 1.0;
-    if (live) {
-        x1 = c1[cand];
-        x2 = c2 != nullptr ? c2[cand] : 1.0;
-    }
     int flag = 0;
-    if (live && (!isfinite(x1) || x1 == 0.0 || (A > 6 && (!isfinite(x2) || x2 == 0.0)))) flag = 1;
-    if (live && !flag) family_points_dev(A, x1, x2, pts);
+    if (live && pts_in != nullptr) {
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            pts[j] = pts_in[(size_t)cand * NF + j];
+            if (!isfinite(pts[j])) flag = 1;
+        }
+    } else if (live) {
+        const double x1 = c1[cand], x2 = c2 != nullptr ? c2[cand] : 1.0;
+        if (!isfinite(x1) || x1 == 0.0 || (A > 6 && (!isfinite(x2) || x2 == 0.0))) flag = 1;
+        if (!flag) family_points_dev(A, x1, x2, pts);
+    }
     // point i and the others in order, picked with constant indices (no
     // dynamically indexed private arrays)
     double a = 0.0, others[NF];
@@ -300,6 +307,14 @@ struct FamilyZeros {
     }
 };
 
+// Explicit point lists: no zero pattern is assumed, every term is taken.
+template <int M, int R>
+struct AllTerms {
+    __device__ static constexpr bool bt(int, int) { return true; }
+    __device__ static constexpr bool g(int, int) { return true; }
+    __device__ static constexpr bool at(int, int) { return true; }
+};
+
 template <int N>
 __device__ __forceinline__ void lds_vec(const float* p, float (&v)[N]) {
     static_assert(N % 4 == 0, "padded length");
@@ -312,11 +327,10 @@ __device__ __forceinline__ void lds_vec(const float* p, float (&v)[N]) {
 
 // One 2D tile: Y = A^T [(G g G^T) .* (B^T d B)] A against the float64
 // reference; `lds` is the staged candidate.
-template <int M, int R>
+template <int M, int R, typename Z>
 __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
                                                 const double* __restrict__ yref, int s, int np, const float* lds) {
     using L = EvalLds<M, R>;
-    using Z = FamilyZeros<M, R>;
     constexpr int A = L::A, AP = L::AP, MP = L::MP, RP = L::RP;
     float gg[R][R];
 #pragma unroll
@@ -415,12 +429,11 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
 
 // T 1D tiles per thread (samples s[t]; invalid ones are evaluated on a
 // clamped index and not counted), sharing each matrix value read.
-template <int M, int R, int T>
+template <int M, int R, int T, typename Z>
 __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
                                                 const double* __restrict__ yref, const int (&s)[T],
                                                 const bool (&ok)[T], int np, const float* lds) {
     using L = EvalLds<M, R>;
-    using Z = FamilyZeros<M, R>;
     constexpr int A = L::A, AP = L::AP, MP = L::MP;
     float gv[T][R], dv[T][A], u[T][A], v[T][A];
 #pragma unroll
@@ -482,7 +495,8 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
 
 constexpr int kTiles1d = 4;
 
-template <int M, int R, int DIMS>
+// FAM: candidates are family sets (FamilyZeros applies), else explicit lists.
+template <int M, int R, int DIMS, bool FAM>
 __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict__ d_soa,
                                                          const float* __restrict__ g_soa,
                                                          const double* __restrict__ yref,
@@ -491,6 +505,7 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
                                                          const int* __restrict__ counts, int n_cand, int n_pool,
                                                          int ipc, int chunk, double* __restrict__ partial) {
     using L = EvalLds<M, R>;
+    using Z = typename std::conditional<FAM, FamilyZeros<M, R>, AllTerms<M, R>>::type;
     __shared__ __align__(16) float sm[L::kSize];
     __shared__ double red[256];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -523,13 +538,13 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
                     ok[t] = si < stop;
                     ss[t] = ok[t] ? si : s0;
                 }
-                err += tile_error_1d<M, R, kTiles1d>(d_soa, g_soa, yref, ss, ok, n_pool, sm + z0);
+                err += tile_error_1d<M, R, kTiles1d, Z>(d_soa, g_soa, yref, ss, ok, n_pool, sm + z0);
             }
         } else {
             for (int s = start + tid; s < stop; s += nthr) {
                 int z0 = 0;
                 asm volatile("" : "+v"(z0));
-                err += tile_error_2d<M, R>(d_soa, g_soa, yref, s, n_pool, sm + z0);
+                err += tile_error_2d<M, R, Z>(d_soa, g_soa, yref, s, n_pool, sm + z0);
             }
         }
         red[tid] = err;
@@ -576,15 +591,19 @@ struct SweepOps {
     static void run(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st) {
         const int ipc = (S.n_pool + t.chunk - 1) / t.chunk;
         hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + kConsCands - 1) / kConsCands),
-                           dim3(256), 0, st, a.c1,
-                           a.c2, a.n_cand, S.mats, S.flags);
+                           dim3(256), 0, st, a.c1, a.c2, a.pts, a.n_cand, S.mats, S.flags);
         const long items = (long)a.n_cand * ipc;
         long grid = (long)S.n_cu * t.blocks_per_cu;
         if (grid > items) grid = items;
         if (grid < 1) grid = 1;
-        hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS>), dim3((unsigned)grid), dim3(t.block), 0, st, S.d_soa,
-                           S.g_soa, S.yref, S.mats, S.flags, a.counts, a.n_cand, S.n_pool, ipc, t.chunk,
-                           S.partial);
+        if (a.pts == nullptr)
+            hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS, true>), dim3((unsigned)grid), dim3(t.block), 0, st,
+                               S.d_soa, S.g_soa, S.yref, S.mats, S.flags, a.counts, a.n_cand, S.n_pool, ipc,
+                               t.chunk, S.partial);
+        else
+            hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS, false>), dim3((unsigned)grid), dim3(t.block), 0, st,
+                               S.d_soa, S.g_soa, S.yref, S.mats, S.flags, a.counts, a.n_cand, S.n_pool, ipc,
+                               t.chunk, S.partial);
         hipLaunchKernelGGL(sweep_finalize_kernel, dim3((a.n_cand + 255) / 256), dim3(256), 0, st, S.partial,
                            S.prefix, S.flags, a.counts, a.n_cand, S.n_pool, ipc, DIMS == 1 ? M : M * M, a.out);
     }
@@ -704,10 +723,11 @@ int wg_sweep_destroy(wg_sweep* sweep) {
     return WG_OK;
 }
 
-static int check_args(const Sweep& S, const double* c1, const int* counts, int n_cand, double* out) {
-    if (!c1 || !counts || !out) return fail(WG_EINVAL, "wg_sweep_run: null pointer");
+static int check_args(const Sweep& S, const double* c1, const int* counts, int n_cand, double* out,
+                      const char* who = "wg_sweep_run") {
+    if (!c1 || !counts || !out) return fail(WG_EINVAL, std::string(who) + ": null pointer");
     if (n_cand <= 0 || n_cand > S.max_cand)
-        return fail(WG_EINVAL, "wg_sweep_run: n_cand must be 1.." + std::to_string(S.max_cand));
+        return fail(WG_EINVAL, std::string(who) + ": n_cand must be 1.." + std::to_string(S.max_cand));
     return WG_OK;
 }
 
@@ -718,7 +738,7 @@ int wg_sweep_autotune(wg_sweep* sweep, const double* c1, const double* c2, const
     int st = check_args(S, c1, counts, n_cand, out);
     if (st != WG_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const SweepArgs a{c1, c2, counts, n_cand, out};
+    const SweepArgs a{c1, c2, counts, n_cand, out, nullptr};
     hipEvent_t e0, e1;
     if ((st = hipc(hipEventCreate(&e0), "hipEventCreate")) != WG_OK) return st;
     if ((st = hipc(hipEventCreate(&e1), "hipEventCreate")) != WG_OK) { (void)hipEventDestroy(e0); return st; }
@@ -758,13 +778,10 @@ int wg_sweep_tuning(const wg_sweep* sweep, int* block, int* chunk, int* blocks_p
     return S.tuned ? 1 : 0;
 }
 
-int wg_sweep_run(wg_sweep* sweep, const double* c1, const double* c2, const int* counts, int n_cand,
-                 double* out, wg_stream_t stream) {
-    if (!sweep) return fail(WG_EINVAL, "wg_sweep_run: null sweep");
-    Sweep& S = *reinterpret_cast<Sweep*>(sweep);
-    int st = check_args(S, c1, counts, n_cand, out);
-    if (st != WG_OK) return st;
-    const SweepArgs a{c1, c2, counts, n_cand, out};
+// Replays the captured graph of this argument set, capturing it first when
+// the arguments differ from the last capture.
+static int run_graph(Sweep& S, const SweepArgs& a, wg_stream_t stream) {
+    int st = WG_OK;
     if (!S.exec || !(a == S.captured)) {
         if (S.exec) { (void)hipGraphExecDestroy(S.exec); S.exec = nullptr; }
         if (S.graph) { (void)hipGraphDestroy(S.graph); S.graph = nullptr; }
@@ -780,6 +797,24 @@ int wg_sweep_run(wg_sweep* sweep, const double* c1, const double* c2, const int*
         S.captured = a;
     }
     return hipc(hipGraphLaunch(S.exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+int wg_sweep_run(wg_sweep* sweep, const double* c1, const double* c2, const int* counts, int n_cand,
+                 double* out, wg_stream_t stream) {
+    if (!sweep) return fail(WG_EINVAL, "wg_sweep_run: null sweep");
+    Sweep& S = *reinterpret_cast<Sweep*>(sweep);
+    int st = check_args(S, c1, counts, n_cand, out);
+    if (st != WG_OK) return st;
+    return run_graph(S, SweepArgs{c1, c2, counts, n_cand, out, nullptr}, stream);
+}
+
+int wg_sweep_run_points(wg_sweep* sweep, const double* pts, const int* counts, int n_cand, double* out,
+                        wg_stream_t stream) {
+    if (!sweep) return fail(WG_EINVAL, "wg_sweep_run_points: null sweep");
+    Sweep& S = *reinterpret_cast<Sweep*>(sweep);
+    int st = check_args(S, pts, counts, n_cand, out, "wg_sweep_run_points");
+    if (st != WG_OK) return st;
+    return run_graph(S, SweepArgs{nullptr, nullptr, counts, n_cand, out, pts}, stream);
 }
 
 int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, float* BT, int* flag) {

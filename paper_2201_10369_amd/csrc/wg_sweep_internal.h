@@ -13,14 +13,18 @@ struct SweepTune {
     int blocks_per_cu;  // persistent blocks per compute unit
 };
 
+// One scoring call: either family parameters (c1, c2) or explicit point
+// lists (pts: n_cand x (alpha-1), c1 = c2 = null).
 struct SweepArgs {
     const double* c1;
     const double* c2;
     const int* counts;
     int n_cand;
     double* out;
+    const double* pts;
     bool operator==(const SweepArgs& o) const {
-        return c1 == o.c1 && c2 == o.c2 && counts == o.counts && n_cand == o.n_cand && out == o.out;
+        return c1 == o.c1 && c2 == o.c2 && counts == o.counts && n_cand == o.n_cand && out == o.out &&
+               pts == o.pts;
     }
 };
 

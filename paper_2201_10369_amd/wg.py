@@ -76,6 +76,7 @@ _SIGS = {
                                 c_void_p]),
     "wg_sweep_destroy": (c_int, [c_void_p]),
     "wg_sweep_run": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "wg_sweep_run_points": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_tuning": (c_int, [c_void_p, P_int, P_int, P_int]),
     "wg_sweep_matrices": (c_int, [c_void_p, c_int, P_float, P_float, P_float, P_int]),
@@ -405,6 +406,21 @@ class Sweep:
         _check(lib().wg_sweep_run(self._h, _tptr(c1, torch.float64, "c1"), _tptr(c2, torch.float64, "c2"),
                                   _tptr(counts, torch.int32, "counts"), n, _tptr(out, torch.float64, "out"),
                                   _stream(stream)))
+        return out
+
+    def run_points(self, pts, counts, out=None, stream=None):
+        """Scores explicit point sets: pts is a device float64 tensor
+        [n_cand, alpha - 1] of ordered finite points (infinity implied last)."""
+        torch = _torch()
+        if pts.dim() != 2 or pts.shape[1] != self.alpha - 1:
+            raise ValueError(f"pts must have shape [n_cand, {self.alpha - 1}]")
+        n = pts.shape[0]
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float64, device=pts.device)
+        self._args = (pts, counts, out)                  # held by the captured graph
+        _check(lib().wg_sweep_run_points(self._h, _tptr(pts, torch.float64, "pts"),
+                                         _tptr(counts, torch.int32, "counts"), n,
+                                         _tptr(out, torch.float64, "out"), _stream(stream)))
         return out
 
     def autotune(self, c1, c2, counts, out=None, stream=None):

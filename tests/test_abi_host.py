@@ -180,3 +180,43 @@ def test_gemm_autotune_argument_checks():
     assert L.wg_plan_autotune_gemm(plan.handle, fake, fake, 1 << 30, 0, ctypes.byref(chosen), None) == -1
     assert L.wg_plan_autotune_gemm(plan.handle, fake, fake, 16, 4, ctypes.byref(chosen), None) == -4
     assert chosen.value == 0 and plan.gemm_tiles == 1
+
+
+def test_sweep_points_argument_checks():
+    L = wg.lib()
+    assert L.wg_sweep_run_points(None, None, None, 1, None, None) == -1     # null sweep
+    assert L.wg_sweep_autotune(None, None, None, None, 1, None, None) == -1
+
+
+def test_point_sets_of_the_tables():
+    """Comparison sets of Tables tab:sota_1d / tab:sota_2d (P4 ... P10), the
+    Chebyshev nodes of Section 2 and the subsets of eq. subset_points."""
+    from paper_2201_10369_amd import pointsets as ps
+    for dims in (1, 2):
+        for alpha in range(4, 11):
+            s = ps.comparison_set(alpha, dims)
+            assert len(s) == alpha - 1 and len(set(s)) == alpha - 1 and s[:3] == [0.0, -1.0, 1.0]
+    assert ps.comparison_set(9, 1) == [0.0, -1.0, 1.0, 0.5, -0.5, 2.0, -2.0, -0.25]
+    assert ps.comparison_set(10, 2)[-2:] == [-0.25, 4.0]
+    assert ps.comparison_set(6, 1)[-1] == -3.0 and ps.comparison_set(6, 2)[-1] == -2.0
+    with pytest.raises(ValueError):
+        ps.comparison_set(11, 1)
+    for alpha in range(4, 11):
+        nodes = ps.chebyshev(alpha)
+        ref = tc.chebyshev_nodes(alpha - 1)
+        assert len(nodes) == alpha - 1
+        for a, b in zip(nodes, ref):
+            assert abs(a - b) < 1e-15                       # the oracle's nodes (middle one 6e-17 there)
+        if (alpha - 1) % 2 == 1:
+            assert nodes[(alpha - 2) // 2] == 0.0
+        assert all(abs(a + b) < 1e-15 for a, b in zip(nodes, nodes[::-1]))   # symmetric
+    # eq. subset_points for F(4,3) with base {1, -1}: the six pairs of proposed points
+    subs = ps.base_subsets(6, [1.0, -1.0])
+    assert len(subs) == 6 and ("-1/c", "-c") in subs and ("c", "1/c") in subs
+    assert ps.base_subsets(6, []) == [("-1/c", "-c", "c", "1/c")]
+    lists = ps.subset_lists([-3.0], ("-1/c", "c", "1/c"), [2.0, 4.0])
+    assert lists.tolist() == [[0.0, -3.0, -0.5, 2.0, 0.5], [0.0, -3.0, -0.25, 4.0, 0.25]]
+    with pytest.raises(ValueError):
+        ps.base_subsets(4, [1.0, -1.0, 3.0])
+    fam = ps.family_lists(10, [2.0, 1.5], [3.0, 1.25])
+    assert fam.shape == (2, 9) and np.array_equal(fam[0], wg.family_points(10, 2.0, 3.0))

@@ -163,3 +163,154 @@ def test_full_candidate_grid_sampled(dims):
         assert abs(mean[i] / mean[j] - 1) < 0.05
     best = int(np.nanargmin(mean))
     assert 0.2 < c1[best] < 5.0
+
+
+# ----------------------------------------------------------------------------
+# explicit point lists
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("m,r", [(2, 3), (4, 3), (6, 3), (7, 3), (8, 3), (4, 5), (6, 5)])
+def test_point_lists_score_exactly_as_the_family(m, r, dims):
+    """A family's points passed as explicit lists give bit-identical results
+    (same float64 construction; the terms the family kernels leave out are
+    exact zeros)."""
+    from paper_2201_10369_amd import pointsets as ps
+    alpha = m + r - 1
+    S, d, g = _make(m, r, dims, 600, 48)
+    rng = np.random.default_rng(100 + 10 * m + r + dims)
+    c1 = np.exp(rng.uniform(np.log(0.1), np.log(10.0), 48))
+    c2 = np.exp(rng.uniform(np.log(0.1), np.log(10.0), 48))
+    if alpha >= 5:
+        c1[0] = 1.0                                       # c = 1/c: both modes flag it
+    counts = rng.integers(0, 650, 48).astype(np.int32)
+    a = S.run(_dev(c1), _dev(c2), _dev(counts)).clone()
+    b = S.run_points(_dev(ps.family_lists(alpha, c1, c2)), _dev(counts)).clone()
+    assert torch.equal(a[:, 1:], b[:, 1:])
+    fin = torch.isfinite(a[:, 0])
+    assert torch.equal(fin, torch.isfinite(b[:, 0])) and (alpha == 4 or not bool(fin[0]))
+    assert torch.equal(a[fin, 0], b[fin, 0])
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("m,r", [(2, 3), (3, 3), (4, 3), (6, 3), (7, 3), (8, 3), (4, 5)])
+def test_point_lists_match_oracle(m, r, dims):
+    """Comparison sets, Chebyshev nodes, base-point subsets and random lists
+    (no zero, zero not first) on uneven pool prefixes equal the oracle's
+    scores of the same float64 points."""
+    from paper_2201_10369_amd import pointsets as ps
+    alpha = m + r - 1
+    n_pool = 500
+    S, d, g = _make(m, r, dims, n_pool, 32)
+    rng = np.random.default_rng(200 + 10 * m + r + dims)
+    lists = [ps.comparison_set(alpha, dims), ps.chebyshev(alpha)]
+    if alpha >= 5:
+        base = {5: [0.5], 6: [1.0, -1.0], 7: [1.0, -1.0], 8: [1.0, -1.0, 3.0], 9: [1.0, -1.0, 3.0],
+                10: [1.0, -1.0, 3.0, -3.0]}[alpha]
+        sub = ps.base_subsets(alpha, base)[-1]
+        lists.append(ps.subset_lists(base, sub, [1.7])[0].tolist())
+    while len(lists) < 12:
+        lists.append(list(rng.uniform(-3, 3, alpha - 1)))
+    lists[-1][0] = lists[-1][1]                           # coinciding points: flagged
+    pts = np.array(lists, np.float64)
+    counts = rng.integers(0, n_pool + 40, len(pts)).astype(np.int32)
+    counts[0] = n_pool
+    out = S.run_points(_dev(pts), _dev(counts)).cpu().numpy()
+    yref = sweep.pool_reference(d, g)
+    outs = m if dims == 1 else m * m
+    for i, p in enumerate(pts):
+        n = min(int(counts[i]), n_pool)
+        e = sweep.candidate_error_points(p, m, r, dims, d, g, yref, n)
+        assert out[i, 2] == n * outs
+        assert out[i, 3] == (1.0 if e["singular"] else 0.0), i
+        if e["singular"]:
+            assert math.isinf(out[i, 0])
+            continue
+        AT, G, BT, _ = S.matrices(i)
+        same = all(np.array_equal(a_, b_) for a_, b_ in
+                   zip((AT, G, BT), fp.mats_f32([Fr(float(v)) for v in p], m, r)))
+        assert out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-12 if same else 1e-3, abs=1e-300), (i, same)
+
+
+def test_point_lists_flag_invalid_points():
+    S, d, g = _make(4, 3, 2, 100, 8)
+    pts = np.array([[0.0, 1.0, -1.0, 0.5, 2.0],
+                    [0.0, 1.0, 1.0, 0.5, 2.0],               # coincide
+                    [0.0, np.nan, -1.0, 0.5, 2.0],
+                    [0.0, 1.0, np.inf, 0.5, 2.0],
+                    [0.0, 1.0, -1.0, 0.5, 1e-200],           # |N_i| < 1e-300
+                    [-2.0, 1.0, -1.0, 0.5, 0.0]])            # zero last: valid
+    out = S.run_points(_dev(pts), _dev(np.full(6, 100, np.int32))).cpu().numpy()
+    assert list(out[:, 3]) == [0, 1, 1, 1, 1, 0]
+    assert np.isinf(out[1:5, 0]).all() and np.isfinite(out[[0, 5], 0]).all()
+
+
+# ----------------------------------------------------------------------------
+# searches
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("m,dims", [(7, 1), (8, 1), (7, 2), (8, 2)])
+def test_two_param_search_result_is_scored_like_the_oracle(m, dims):
+    """The (c, d) grid-and-refine search for n = 9, 10 (Tables tab:sota_1d,
+    tab:sota_2d): its reported best is the oracle's score of that (c, d), it
+    is no worse than every coarse-grid candidate it re-scored, and refining
+    never loses ground."""
+    from paper_2201_10369_amd import search
+    r, alpha = 3, m + 2
+    n_pool = 300
+    S, d, g = _make(m, r, dims, n_pool, 1024)
+    res = search.two_param_search(S, grid=24, keep=4, local=8, rounds=2, n_coarse=100)
+    assert res["evaluations"] == 24 * 24 + 4 + 2 * 64
+    assert all(b <= a for a, b in zip(res["history"], res["history"][1:]))
+    e = sweep.candidate_error(alpha, m, r, dims, res["c"], res["d"], d, g, sweep.pool_reference(d, g), n_pool)
+    assert res["mean_abs"] == pytest.approx(e["mean_abs"], rel=1e-3)
+    # the comparison set's score is another run of the same kernels
+    from paper_2201_10369_amd import pointsets as ps
+    pn = search.score_points(S, [ps.comparison_set(alpha, dims)], n_pool)[0]
+    ep = sweep.candidate_error_points(ps.comparison_set(alpha, dims), m, r, dims, d, g,
+                                      sweep.pool_reference(d, g), n_pool)
+    assert pn == pytest.approx(ep["mean_abs"], rel=1e-12)
+
+
+def test_subset_search_orders_the_subsets():
+    """Base-point study of Section 6.2 for F(3,3) with base {1/2}: every
+    subset's curve minimum is the oracle's score at that c, best first."""
+    from paper_2201_10369_amd import pointsets as ps, search
+    m, r, dims = 3, 3, 1
+    S, d, g = _make(m, r, dims, 400, 512)
+    cs = search.log_grid(1.05, 4.0, 64)
+    rows = search.subset_search(S, [0.5], cs)
+    assert len(rows) == len(ps.base_subsets(5, [0.5])) == 6
+    assert all(a["mean_abs"] <= b["mean_abs"] for a, b in zip(rows, rows[1:]))
+    yref = sweep.pool_reference(d, g)
+    for row in rows[:2]:
+        p = ps.subset_lists([0.5], tuple(row["subset"]), [row["c"]])[0]
+        e = sweep.candidate_error_points(p, m, r, dims, d, g, yref, 400)
+        assert row["mean_abs"] == pytest.approx(e["mean_abs"], rel=1e-3)
+        assert row["mean_abs"] == float(np.min(row["curve"]))
+
+
+def test_two_param_families_beat_the_comparison_sets():
+    """Tables tab:sota_1d / tab:sota_2d: for n = 9 and 10 points the searched
+    two-parameter family scores below the comparison sets P9 and P10 and the
+    Chebyshev nodes (2000-sample pool, the bench's search settings)."""
+    from paper_2201_10369_amd import pointsets as ps, search
+    from paper_2201_10369_amd import surrogate as sg
+    for m in (7, 8):
+        alpha = m + 2
+        for dims in (1, 2):
+            S = sg.sweep_for(m, 3, dims=dims, max_cand=4096)
+            best = search.two_param_search(S)["mean_abs"]
+            pn = search.score_points(S, [ps.comparison_set(alpha, dims), ps.chebyshev(alpha)], S.n_pool)
+            assert best < 0.95 * pn[0] and best < pn[1], (alpha, dims, best, pn)
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+def test_f43_proposed_points_beat_every_base_subset(dims):
+    """Table tab:optimal_f43: for F(4,3) the four proposed points
+    {-1/c, -c, c, 1/c} score below every tested base point with a subset."""
+    from paper_2201_10369_amd import search
+    from paper_2201_10369_amd import surrogate as sg
+    S = sg.sweep_for(4, 3, dims=dims, max_cand=4096)
+    cs = search.log_grid(1.001, 4.0, 512)
+    own = search.subset_search(S, [], cs)[0]["mean_abs"]
+    for base in ([0.5], [3.0], [-3.0], [1.0, -1.0]):
+        assert own < search.subset_search(S, base, cs)[0]["mean_abs"], base
