@@ -106,6 +106,8 @@ SWEEP_FLOP_PER_TILE = {1: 2 * 108 + 8, 2: 2 * 1552 + 64}
 # vector fp32 peak without packed instructions (the build does not use
 # them): 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 FP32_VECTOR_TFLOPS = 78.6
+# the published figure counts packed (two-wide) float32 operations
+FP32_PUBLISHED_TFLOPS = 157.3
 
 
 def bench_sweep(wg, torch, reps=5):
@@ -140,7 +142,44 @@ def bench_sweep(wg, torch, reps=5):
                            "best_c": float(c1[best]), "best_mean_abs": float(mean[best]),
                            "roofline": {"bound": "alu", "achieved": round(tflops, 2),
                                         "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                                        "frac": round(tflops / FP32_VECTOR_TFLOPS, 4)}}
+                                        "frac": round(tflops / FP32_VECTOR_TFLOPS, 4),
+                                        "published_peak": FP32_PUBLISHED_TFLOPS,
+                                        "frac_of_published": round(tflops / FP32_PUBLISHED_TFLOPS, 4)}}
+        # the same sweep with float64 transforms and a float32 Hadamard product
+        S.set_precision("mixed")
+        S.run(c1, c2, counts, out)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            S.run(c1, c2, counts, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        o = out.cpu().numpy()
+        mean = o[:, 0] / np.maximum(o[:, 2], 1)
+        best = int(np.nanargmin(np.where(o[:, 3] > 0, np.inf, mean)))
+        res[f"{dims}d"]["mixed"] = {"ms": round(ms, 4), "best_c": float(c1[best]),
+                                    "best_mean_abs": float(mean[best])}
+    return res
+
+
+def bench_error_curve(wg, torch):
+    """The error curve of Section 6.1: F(4,3) with {-1/c, -c, 0, c, 1/c},
+    c from 1.1 to 2.5 in steps of 1e-3, 1D and 2D, float32 and mixed
+    precision, every candidate on the whole 2000-sample pool."""
+    c = torch.from_numpy(synth.linear_grid(1.1, 2.5, 1e-3)).cuda()
+    ones = torch.ones_like(c)
+    counts = torch.full((c.numel(),), 2000, dtype=torch.int32, device="cuda")
+    res = {}
+    for dims in (1, 2):
+        d, g = synth.tile_pool(2000, 6, 3, dims)
+        S = wg.Sweep(4, 3, dims, torch.from_numpy(d).cuda(), torch.from_numpy(g).cuda(), c.numel())
+        for mode in ("f32", "mixed"):
+            S.set_precision(mode)
+            o = S.run(c, ones, counts).cpu().numpy()
+            mean = o[:, 0] / np.maximum(o[:, 2], 1)
+            j = int(np.argmin(mean))
+            res[f"{mode}_{dims}d"] = {"best_c": round(float(c[j]), 4), "mean_abs": float(mean[j])}
     return res
 
 
@@ -309,6 +348,7 @@ def main():
                       "gemm_tiles_per_block": f["plan"].gemm_tiles} for d, f in forms.items()},
     }
     out["sweep"] = bench_sweep(wg, torch)
+    out["error_curve_f43"] = bench_error_curve(wg, torch)
     out["two_param"] = bench_two_param(torch)
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(torch)

@@ -325,6 +325,29 @@ int wg_sweep_tuning(const wg_sweep* sweep, int* block, int* chunk, int* blocks_p
  * outputs, sizes as wg_transforms) and its flag; synchronous. */
 int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, float* BT, int* flag);
 
+/* Precision of the evaluated tiles (Section 6: besides the plain float32
+ * evaluation the paper scores a mixed-precision one, float64 transforms with
+ * a float32 Hadamard product).
+ *   WG_SWEEP_F32   (default): every step in float32, one fused multiply-add
+ *                  per term.
+ *   WG_SWEEP_MIXED: the float64 matrices (before their float32 rounding)
+ *                  transform filter and tile in float64, U and V are rounded
+ *                  to float32, multiplied in float32, and Y = A^T M A is
+ *                  taken in float64 and rounded to float32; each float64 term
+ *                  is a rounded product followed by a rounded sum, in
+ *                  ascending index order.
+ * Applies to later wg_sweep_run / wg_sweep_run_points calls (the captured
+ * graph is rebuilt).  The first switch to WG_SWEEP_MIXED allocates
+ * max_cand * 2 KB of device memory, kept until the sweep is destroyed.
+ * Errors: WG_EINVAL (null sweep, unknown mode), WG_ENOMEM. */
+enum { WG_SWEEP_F32 = 0, WG_SWEEP_MIXED = 1 };
+int wg_sweep_set_precision(wg_sweep* sweep, int mode);
+
+/* The float64 matrices the last mixed-precision run built for candidate
+ * `cand` (host outputs, sizes as wg_transforms); synchronous.  WG_EINVAL if
+ * the sweep never ran in mixed precision. */
+int wg_sweep_matrices_f64(const wg_sweep* sweep, int cand, double* AT, double* G, double* BT);
+
 /* ------------------------------------------------------------------------
  * Error surrogate (device).  A fully connected network 4 -> 128 -> 128 ->
  * 128 -> 1 with GELU (z * Phi(z), exact erf form) maps a point-family

@@ -125,6 +125,53 @@ def tile_2d_f32(mats, d, g):
     return xform2d(AT, U * V)
 
 
+# ----------------------------------------------------------------------------
+# Mixed precision (Section 6): float64 transforms, float32 Hadamard product
+# ----------------------------------------------------------------------------
+def apply_left_f64(Mat, X, axis):
+    """Z[..i..] = sum_l Mat[i,l] X[..l..] along `axis` in float64: ascending
+    l, acc <- acc + Mat[i,l] * X[l] from acc = 0 (product and sum each
+    rounded; no fused multiply-add)."""
+    Mat = np.asarray(Mat, dtype=F64)
+    X = np.moveaxis(np.asarray(X, dtype=F64), axis, 0)
+    out = np.empty((Mat.shape[0],) + X.shape[1:], dtype=F64)
+    for i in range(Mat.shape[0]):
+        acc = np.zeros(X.shape[1:], dtype=F64)
+        for l in range(Mat.shape[1]):
+            acc = acc + Mat[i, l] * X[l]
+        out[i] = acc
+    return np.moveaxis(out, 0, axis)
+
+
+def xform2d_f64(Mat, X):
+    return apply_left_f64(Mat, apply_left_f64(Mat, X, -2), -1)
+
+
+def tile_1d_mixed(mats64, d, g):
+    """Mixed-precision 1D tiles: U = G g and V = B^T d in float64 with the
+    float64 matrices, each rounded to float32; their product in float32;
+    Y = A^T (U V) in float64, rounded to float32."""
+    AT, G, BT = mats64
+    U = apply_left_f64(G, g, -1).astype(F32)
+    V = apply_left_f64(BT, d, -1).astype(F32)
+    return apply_left_f64(AT, (U * V).astype(F64), -1).astype(F32)
+
+
+def tile_2d_mixed(mats64, d, g):
+    """Mixed-precision 2D tiles (as tile_1d_mixed, two-sided products taken
+    rows first)."""
+    AT, G, BT = mats64
+    U = xform2d_f64(G, g).astype(F32)
+    V = xform2d_f64(BT, d).astype(F32)
+    return xform2d_f64(AT, (U * V).astype(F64)).astype(F32)
+
+
+def mats_f64(points, m, r, modified=True):
+    """(A^T, G, B^T) in float64 for ordered points (exact, then rounded)."""
+    AT, G, BT = tc.transforms(points, m, r, modified)
+    return tuple(np.array([[float(v) for v in row] for row in M_], dtype=F64) for M_ in (AT, G, BT))
+
+
 def direct_tile_f64(d, g):
     """Correlation of each tile with its filter in float64 (1D or 2D batch)."""
     d = np.asarray(d, dtype=F64)

@@ -83,3 +83,14 @@ def candidate_error_points(pts, m, r, dims, d, g, yref, n):
     e = fp.l1_errors(y, yref[:n])
     e["singular"] = False
     return e
+
+
+def candidate_error_mixed(mats64, m, r, dims, d, g, yref, n):
+    """L1 error sums of the mixed-precision evaluation (float64 transforms,
+    float32 Hadamard product; Section 6) with the given float64 matrices on
+    the pool prefix [0, n)."""
+    tile = fp.tile_1d_mixed if dims == 1 else fp.tile_2d_mixed
+    y = tile(mats64, d[:n], g[:n])
+    e = fp.l1_errors(y, yref[:n])
+    e["singular"] = False
+    return e

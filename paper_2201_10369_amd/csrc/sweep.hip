@@ -92,6 +92,8 @@ __device__ void product_poly_snapped(const double* roots, int n, double* coef) {
 // points coincide (|N_i| < 1e-300); it is also flagged when an entry comes
 // out non-finite.  With explicit point lists (pts_in, n_cand x (alpha-1),
 // infinity implied last) a non-finite point flags the candidate instead.
+// mats64 (optional) receives the float64 values before the float32 rounding
+// (the matrices of the mixed-precision evaluation).
 constexpr int kConsRows = 16;
 constexpr int kConsCands = 256 / kConsRows;
 
@@ -100,6 +102,7 @@ __global__ __launch_bounds__(256) void sweep_construct_kernel(const double* __re
                                                               const double* __restrict__ c2,
                                                               const double* __restrict__ pts_in, int n_cand,
                                                               float* __restrict__ mats,
+                                                              double* __restrict__ mats64,
                                                               int* __restrict__ flags) {
     constexpr int A = M + R - 1;
     constexpr int NF = A - 1;
@@ -146,47 +149,51 @@ __global__ __launch_bounds__(256) void sweep_construct_kernel(const double* __re
     float* AT = out;
     float* G = out + M * A;
     float* BT = out + M * A + A * R;
-    float at[M], gr[R], bt[A];
-    for (int j = 0; j < M; ++j) at[j] = 0.0f;
-    for (int k = 0; k < R; ++k) gr[k] = 0.0f;
-    for (int l = 0; l < A; ++l) bt[l] = 0.0f;
+    double at[M], gr[R], bt[A];
+    for (int j = 0; j < M; ++j) at[j] = 0.0;
+    for (int k = 0; k < R; ++k) gr[k] = 0.0;
+    for (int l = 0; l < A; ++l) bt[l] = 0.0;
     if (live && !flag) {
         double coef[A + 1];
         if (i < NF) {
             double pw = 1.0;
             for (int j = 0; j < M; ++j) {
-                at[j] = (float)pw;
+                at[j] = pw;
                 pw *= a;
             }
             pw = 1.0;
             for (int k = 0; k < R; ++k) {
-                gr[k] = (float)(pw / norm);
+                gr[k] = pw / norm;
                 pw *= a;
             }
             product_poly_snapped<A>(others, NF - 1, coef);
 #pragma unroll
-            for (int l = 0; l < NF; ++l) bt[l] = (float)coef[l];
+            for (int l = 0; l < NF; ++l) bt[l] = coef[l];
         } else {
-            at[M - 1] = 1.0f;
-            gr[R - 1] = 1.0f;
+            at[M - 1] = 1.0;
+            gr[R - 1] = 1.0;
             product_poly_snapped<A>(pts, NF, coef);
 #pragma unroll
-            for (int l = 0; l <= NF; ++l) bt[l] = (float)coef[l];
+            for (int l = 0; l <= NF; ++l) bt[l] = coef[l];
         }
     }
     if (live) {
+        double* out64 = mats64 != nullptr ? mats64 + (size_t)cand * kMatStride : nullptr;
         int nonfinite = 0;
         for (int j = 0; j < M; ++j) {
-            AT[j * A + i] = at[j];
-            nonfinite |= !isfinite(at[j]);
+            AT[j * A + i] = (float)at[j];
+            nonfinite |= !isfinite((float)at[j]);
+            if (out64) out64[j * A + i] = at[j];
         }
         for (int k = 0; k < R; ++k) {
-            G[i * R + k] = gr[k];
-            nonfinite |= !isfinite(gr[k]);
+            G[i * R + k] = (float)gr[k];
+            nonfinite |= !isfinite((float)gr[k]);
+            if (out64) out64[M * A + i * R + k] = gr[k];
         }
         for (int l = 0; l < A; ++l) {
-            BT[i * A + l] = bt[l];
-            nonfinite |= !isfinite(bt[l]);
+            BT[i * A + l] = (float)bt[l];
+            nonfinite |= !isfinite((float)bt[l]);
+            if (out64) out64[M * A + A * R + i * A + l] = bt[l];
         }
         if (nonfinite) bad[1][slot] = 1;
     }
@@ -271,17 +278,18 @@ struct EvalLds {
     static constexpr int kSize = kAr + M * AP;
 
     // value of LDS slot q from the candidate's row-major A^T | G | B^T
-    __device__ static float slot(const float* __restrict__ m, int q) {
-        const float* AT = m;
-        const float* G = m + M * A;
-        const float* BT = m + M * A + A * R;
-        if (q < kGc) { const int l = q / AP, i = q % AP; return i < A ? BT[i * A + l] : 0.0f; }
-        if (q < kGr) { q -= kGc; const int v = q / AP, j = q % AP; return j < A ? G[j * R + v] : 0.0f; }
-        if (q < kAc) { q -= kGr; const int i = q / RP, u = q % RP; return u < R ? G[i * R + u] : 0.0f; }
-        if (q < kAr) { q -= kAc; const int i = q / MP, k = q % MP; return k < M ? AT[k * A + i] : 0.0f; }
+    template <typename T>
+    __device__ static T slot(const T* __restrict__ m, int q) {
+        const T* AT = m;
+        const T* G = m + M * A;
+        const T* BT = m + M * A + A * R;
+        if (q < kGc) { const int l = q / AP, i = q % AP; return i < A ? BT[i * A + l] : T(0); }
+        if (q < kGr) { q -= kGc; const int v = q / AP, j = q % AP; return j < A ? G[j * R + v] : T(0); }
+        if (q < kAc) { q -= kGr; const int i = q / RP, u = q % RP; return u < R ? G[i * R + u] : T(0); }
+        if (q < kAr) { q -= kAc; const int i = q / MP, k = q % MP; return k < M ? AT[k * A + i] : T(0); }
         q -= kAr;
         const int qq = q / AP, j = q % AP;
-        return j < A ? AT[qq * A + j] : 0.0f;
+        return j < A ? AT[qq * A + j] : T(0);
     }
 };
 
@@ -324,170 +332,190 @@ __device__ __forceinline__ void lds_vec(const float* p, float (&v)[N]) {
         v[q] = t.x; v[q + 1] = t.y; v[q + 2] = t.z; v[q + 3] = t.w;
     }
 }
+template <int N>
+__device__ __forceinline__ void lds_vec(const double* p, double (&v)[N]) {
+    static_assert(N % 2 == 0, "padded length");
+#pragma unroll
+    for (int q = 0; q < N; q += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(p + q);
+        v[q] = t.x; v[q + 1] = t.y;
+    }
+}
+
+// One term of an ascending-order inner product.  float: one fused
+// multiply-add.  double (the float64 transforms of the mixed-precision
+// evaluation): a rounded product, then a rounded sum.
+__device__ __forceinline__ float madd(float a, float b, float acc) { return __builtin_fmaf(a, b, acc); }
+__device__ __forceinline__ double madd(double a, double b, double acc) { return acc + a * b; }
 
 // One 2D tile: Y = A^T [(G g G^T) .* (B^T d B)] A against the float64
-// reference; `lds` is the staged candidate.
-template <int M, int R, typename Z>
+// reference; `lds` is the staged candidate.  T is the type of the
+// transforms: float (every step in float32), or double (float64 transforms,
+// U and V rounded to float32, their product in float32, Y rounded to
+// float32 at the end: the mixed-precision evaluation).
+template <int M, int R, typename Z, typename T>
 __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
-                                                const double* __restrict__ yref, int s, int np, const float* lds) {
+                                                const double* __restrict__ yref, int s, int np, const T* lds) {
     using L = EvalLds<M, R>;
     constexpr int A = L::A, AP = L::AP, MP = L::MP, RP = L::RP;
-    float gg[R][R];
+    T gg[R][R];
 #pragma unroll
     for (int u = 0; u < R; ++u)
 #pragma unroll
-        for (int v = 0; v < R; ++v) gg[u][v] = g_soa[(size_t)(u * R + v) * np + s];
+        for (int v = 0; v < R; ++v) gg[u][v] = (T)g_soa[(size_t)(u * R + v) * np + s];
     // T1 = B^T d, one row of d at a time
-    float t1[A][A];
+    T t1[A][A];
 #pragma unroll
     for (int i = 0; i < A; ++i)
 #pragma unroll
-        for (int b = 0; b < A; ++b) t1[i][b] = 0.0f;
+        for (int b = 0; b < A; ++b) t1[i][b] = T(0);
 #pragma unroll
     for (int l = 0; l < A; ++l) {
-        float drow[A], bc[AP];
+        T drow[A], bc[AP];
 #pragma unroll
-        for (int b = 0; b < A; ++b) drow[b] = d_soa[(size_t)(l * A + b) * np + s];
+        for (int b = 0; b < A; ++b) drow[b] = (T)d_soa[(size_t)(l * A + b) * np + s];
         lds_vec(lds + L::kBc + l * AP, bc);
 #pragma unroll
         for (int i = 0; i < A; ++i)
             if (Z::bt(i, l)) {
 #pragma unroll
-                for (int b = 0; b < A; ++b) t1[i][b] = __builtin_fmaf(bc[i], drow[b], t1[i][b]);
+                for (int b = 0; b < A; ++b) t1[i][b] = madd(bc[i], drow[b], t1[i][b]);
             }
     }
     // V = T1 B, one column of B^T at a time
-    float vv[A][A];
+    T vv[A][A];
 #pragma unroll
     for (int i = 0; i < A; ++i)
 #pragma unroll
-        for (int j = 0; j < A; ++j) vv[i][j] = 0.0f;
+        for (int j = 0; j < A; ++j) vv[i][j] = T(0);
 #pragma unroll
     for (int l = 0; l < A; ++l) {
-        float bc[AP];
+        T bc[AP];
         lds_vec(lds + L::kBc + l * AP, bc);
 #pragma unroll
         for (int i = 0; i < A; ++i)
 #pragma unroll
             for (int j = 0; j < A; ++j)
-                if (Z::bt(j, l)) vv[i][j] = __builtin_fmaf(t1[i][l], bc[j], vv[i][j]);
+                if (Z::bt(j, l)) vv[i][j] = madd(t1[i][l], bc[j], vv[i][j]);
     }
-    // row i of U = G g G^T, Hadamard with row i of V, accumulate Z = A^T Mh
-    float z[M][A];
+    // row i of U = G g G^T, Hadamard with row i of V (float32), accumulate
+    // Z = A^T Mh
+    T z[M][A];
 #pragma unroll
     for (int k = 0; k < M; ++k)
 #pragma unroll
-        for (int j = 0; j < A; ++j) z[k][j] = 0.0f;
+        for (int j = 0; j < A; ++j) z[k][j] = T(0);
 #pragma unroll
     for (int i = 0; i < A; ++i) {
-        float gr[RP], p1[R], urow[A], ac[MP];
+        T gr[RP], p1[R], urow[A], ac[MP];
         lds_vec(lds + L::kGr + i * RP, gr);
 #pragma unroll
-        for (int v = 0; v < R; ++v) p1[v] = 0.0f;
+        for (int v = 0; v < R; ++v) p1[v] = T(0);
 #pragma unroll
         for (int u = 0; u < R; ++u)
             if (Z::g(i, u)) {
 #pragma unroll
-                for (int v = 0; v < R; ++v) p1[v] = __builtin_fmaf(gr[u], gg[u][v], p1[v]);
+                for (int v = 0; v < R; ++v) p1[v] = madd(gr[u], gg[u][v], p1[v]);
             }
 #pragma unroll
-        for (int j = 0; j < A; ++j) urow[j] = 0.0f;
+        for (int j = 0; j < A; ++j) urow[j] = T(0);
 #pragma unroll
         for (int v = 0; v < R; ++v) {
-            float gc[AP];
+            T gc[AP];
             lds_vec(lds + L::kGc + v * AP, gc);
 #pragma unroll
             for (int j = 0; j < A; ++j)
-                if (Z::g(j, v)) urow[j] = __builtin_fmaf(gc[j], p1[v], urow[j]);
+                if (Z::g(j, v)) urow[j] = madd(gc[j], p1[v], urow[j]);
         }
         lds_vec(lds + L::kAc + i * MP, ac);
 #pragma unroll
         for (int j = 0; j < A; ++j) {
-            const float mh = urow[j] * vv[i][j];
+            const float mh = (float)urow[j] * (float)vv[i][j];
 #pragma unroll
             for (int k = 0; k < M; ++k)
-                if (Z::at(k, i)) z[k][j] = __builtin_fmaf(ac[k], mh, z[k][j]);
+                if (Z::at(k, i)) z[k][j] = madd(ac[k], (T)mh, z[k][j]);
         }
     }
     // Y = Z A, one row of A^T at a time
     double err = 0.0;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-        float ar[AP];
+        T ar[AP];
         lds_vec(lds + L::kAr + q * AP, ar);
 #pragma unroll
         for (int k = 0; k < M; ++k) {
-            float y = 0.0f;
+            T y = T(0);
 #pragma unroll
             for (int j = 0; j < A; ++j)
-                if (Z::at(q, j)) y = __builtin_fmaf(z[k][j], ar[j], y);
-            err += fabs((double)y - yref[(size_t)(k * M + q) * np + s]);
+                if (Z::at(q, j)) y = madd(z[k][j], ar[j], y);
+            err += fabs((double)(float)y - yref[(size_t)(k * M + q) * np + s]);
         }
     }
     return err;
 }
 
-// T 1D tiles per thread (samples s[t]; invalid ones are evaluated on a
-// clamped index and not counted), sharing each matrix value read.
-template <int M, int R, int T, typename Z>
+// NT 1D tiles per thread (samples s[t]; invalid ones are evaluated on a
+// clamped index and not counted), sharing each matrix value read.  T as for
+// the 2D tile.
+template <int M, int R, int NT, typename Z, typename T>
 __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
-                                                const double* __restrict__ yref, const int (&s)[T],
-                                                const bool (&ok)[T], int np, const float* lds) {
+                                                const double* __restrict__ yref, const int (&s)[NT],
+                                                const bool (&ok)[NT], int np, const T* lds) {
     using L = EvalLds<M, R>;
     constexpr int A = L::A, AP = L::AP, MP = L::MP;
-    float gv[T][R], dv[T][A], u[T][A], v[T][A];
+    T gv[NT][R], dv[NT][A], u[NT][A], v[NT][A];
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < NT; ++t) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) gv[t][k] = g_soa[(size_t)k * np + s[t]];
+        for (int k = 0; k < R; ++k) gv[t][k] = (T)g_soa[(size_t)k * np + s[t]];
 #pragma unroll
-        for (int l = 0; l < A; ++l) dv[t][l] = d_soa[(size_t)l * np + s[t]];
+        for (int l = 0; l < A; ++l) dv[t][l] = (T)d_soa[(size_t)l * np + s[t]];
 #pragma unroll
-        for (int i = 0; i < A; ++i) u[t][i] = v[t][i] = 0.0f;
+        for (int i = 0; i < A; ++i) u[t][i] = v[t][i] = T(0);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {                       // U = G g, column k of G
-        float gc[AP];
+        T gc[AP];
         lds_vec(lds + L::kGc + k * AP, gc);
 #pragma unroll
-        for (int t = 0; t < T; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < A; ++i)
-                if (Z::g(i, k)) u[t][i] = __builtin_fmaf(gc[i], gv[t][k], u[t][i]);
+                if (Z::g(i, k)) u[t][i] = madd(gc[i], gv[t][k], u[t][i]);
     }
 #pragma unroll
     for (int l = 0; l < A; ++l) {                       // V = B^T d, column l of B^T
-        float bc[AP];
+        T bc[AP];
         lds_vec(lds + L::kBc + l * AP, bc);
 #pragma unroll
-        for (int t = 0; t < T; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < A; ++i)
-                if (Z::bt(i, l)) v[t][i] = __builtin_fmaf(bc[i], dv[t][l], v[t][i]);
+                if (Z::bt(i, l)) v[t][i] = madd(bc[i], dv[t][l], v[t][i]);
     }
-    float y[T][M];
+    T y[NT][M];
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int j = 0; j < M; ++j) y[t][j] = 0.0f;
+        for (int j = 0; j < M; ++j) y[t][j] = T(0);
 #pragma unroll
     for (int i = 0; i < A; ++i) {                       // Y = A^T Mh, column i of A^T
-        float ac[MP];
+        T ac[MP];
         lds_vec(lds + L::kAc + i * MP, ac);
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const float mh = u[t][i] * v[t][i];
+        for (int t = 0; t < NT; ++t) {
+            const float mh = (float)u[t][i] * (float)v[t][i];
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                if (Z::at(j, i)) y[t][j] = __builtin_fmaf(ac[j], mh, y[t][j]);
+                if (Z::at(j, i)) y[t][j] = madd(ac[j], (T)mh, y[t][j]);
         }
     }
     double err = 0.0;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < NT; ++t) {
         double e = 0.0;
 #pragma unroll
-        for (int j = 0; j < M; ++j) e += fabs((double)y[t][j] - yref[(size_t)j * np + s[t]]);
+        for (int j = 0; j < M; ++j) e += fabs((double)(float)y[t][j] - yref[(size_t)j * np + s[t]]);
         err += ok[t] ? e : 0.0;
     }
     return err;
@@ -496,17 +524,19 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
 constexpr int kTiles1d = 4;
 
 // FAM: candidates are family sets (FamilyZeros applies), else explicit lists.
-template <int M, int R, int DIMS, bool FAM>
+// T: float (float32 evaluation) or double (mixed precision; mats holds the
+// float64 matrices).
+template <int M, int R, int DIMS, bool FAM, typename T>
 __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict__ d_soa,
                                                          const float* __restrict__ g_soa,
                                                          const double* __restrict__ yref,
-                                                         const float* __restrict__ mats,
+                                                         const T* __restrict__ mats,
                                                          const int* __restrict__ flags,
                                                          const int* __restrict__ counts, int n_cand, int n_pool,
                                                          int ipc, int chunk, double* __restrict__ partial) {
     using L = EvalLds<M, R>;
     using Z = typename std::conditional<FAM, FamilyZeros<M, R>, AllTerms<M, R>>::type;
-    __shared__ __align__(16) float sm[L::kSize];
+    __shared__ __align__(16) T sm[L::kSize];
     __shared__ double red[256];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const long items = (long)n_cand * ipc;
@@ -538,13 +568,13 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
                     ok[t] = si < stop;
                     ss[t] = ok[t] ? si : s0;
                 }
-                err += tile_error_1d<M, R, kTiles1d, Z>(d_soa, g_soa, yref, ss, ok, n_pool, sm + z0);
+                err += tile_error_1d<M, R, kTiles1d, Z, T>(d_soa, g_soa, yref, ss, ok, n_pool, sm + z0);
             }
         } else {
             for (int s = start + tid; s < stop; s += nthr) {
                 int z0 = 0;
                 asm volatile("" : "+v"(z0));
-                err += tile_error_2d<M, R, Z>(d_soa, g_soa, yref, s, n_pool, sm + z0);
+                err += tile_error_2d<M, R, Z, T>(d_soa, g_soa, yref, s, n_pool, sm + z0);
             }
         }
         red[tid] = err;
@@ -583,6 +613,13 @@ static int hipc(hipError_t e, const char* what) { return hip_check((int)e, what)
 
 template <int M, int R, int DIMS>
 struct SweepOps {
+    template <bool FAM, typename T>
+    static void eval(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st, long grid, int ipc,
+                     const T* mats) {
+        hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS, FAM, T>), dim3((unsigned)grid), dim3(t.block), 0, st,
+                           S.d_soa, S.g_soa, S.yref, mats, S.flags, a.counts, a.n_cand, S.n_pool, ipc, t.chunk,
+                           S.partial);
+    }
     static void reference(const Sweep& S, hipStream_t st) {
         hipLaunchKernelGGL((sweep_reference_kernel<M, R, DIMS>), dim3((S.n_pool + 255) / 256), dim3(256), 0, st,
                            S.d_pool, S.g_pool, S.n_pool, S.d_soa, S.g_soa, S.yref, S.ref_abs);
@@ -590,20 +627,20 @@ struct SweepOps {
     }
     static void run(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st) {
         const int ipc = (S.n_pool + t.chunk - 1) / t.chunk;
+        double* m64 = S.mixed ? S.mats64 : nullptr;
         hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + kConsCands - 1) / kConsCands),
-                           dim3(256), 0, st, a.c1, a.c2, a.pts, a.n_cand, S.mats, S.flags);
+                           dim3(256), 0, st, a.c1, a.c2, a.pts, a.n_cand, S.mats, m64, S.flags);
         const long items = (long)a.n_cand * ipc;
         long grid = (long)S.n_cu * t.blocks_per_cu;
         if (grid > items) grid = items;
         if (grid < 1) grid = 1;
-        if (a.pts == nullptr)
-            hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS, true>), dim3((unsigned)grid), dim3(t.block), 0, st,
-                               S.d_soa, S.g_soa, S.yref, S.mats, S.flags, a.counts, a.n_cand, S.n_pool, ipc,
-                               t.chunk, S.partial);
-        else
-            hipLaunchKernelGGL((sweep_eval_kernel<M, R, DIMS, false>), dim3((unsigned)grid), dim3(t.block), 0, st,
-                               S.d_soa, S.g_soa, S.yref, S.mats, S.flags, a.counts, a.n_cand, S.n_pool, ipc,
-                               t.chunk, S.partial);
+        if (S.mixed) {
+            if (a.pts == nullptr) eval<true>(S, a, t, st, grid, ipc, (const double*)S.mats64);
+            else eval<false>(S, a, t, st, grid, ipc, (const double*)S.mats64);
+        } else {
+            if (a.pts == nullptr) eval<true>(S, a, t, st, grid, ipc, (const float*)S.mats);
+            else eval<false>(S, a, t, st, grid, ipc, (const float*)S.mats);
+        }
         hipLaunchKernelGGL(sweep_finalize_kernel, dim3((a.n_cand + 255) / 256), dim3(256), 0, st, S.partial,
                            S.prefix, S.flags, a.counts, a.n_cand, S.n_pool, ipc, DIMS == 1 ? M : M * M, a.out);
     }
@@ -657,7 +694,7 @@ static void release(Sweep* S) {
     if (S->exec) (void)hipGraphExecDestroy(S->exec);
     if (S->graph) (void)hipGraphDestroy(S->graph);
     if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
-    void* bufs[] = {S->d_soa, S->g_soa, S->yref, S->ref_abs, S->prefix, S->mats, S->flags, S->partial};
+    void* bufs[] = {S->d_soa, S->g_soa, S->yref, S->ref_abs, S->prefix, S->mats, S->mats64, S->flags, S->partial};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete S;
@@ -815,6 +852,41 @@ int wg_sweep_run_points(wg_sweep* sweep, const double* pts, const int* counts, i
     int st = check_args(S, pts, counts, n_cand, out, "wg_sweep_run_points");
     if (st != WG_OK) return st;
     return run_graph(S, SweepArgs{nullptr, nullptr, counts, n_cand, out, pts}, stream);
+}
+
+int wg_sweep_set_precision(wg_sweep* sweep, int mode) {
+    if (!sweep) return fail(WG_EINVAL, "wg_sweep_set_precision: null sweep");
+    if (mode != WG_SWEEP_F32 && mode != WG_SWEEP_MIXED)
+        return fail(WG_EINVAL, "wg_sweep_set_precision: mode must be WG_SWEEP_F32 or WG_SWEEP_MIXED");
+    Sweep& S = *reinterpret_cast<Sweep*>(sweep);
+    if (mode == WG_SWEEP_MIXED && !S.mats64) {
+        if (hipMalloc(&S.mats64, sizeof(double) * (size_t)S.max_cand * kMatStride) != hipSuccess) {
+            S.mats64 = nullptr;
+            return fail(WG_ENOMEM, "wg_sweep_set_precision: device allocation failed");
+        }
+    }
+    if (S.mixed != (mode == WG_SWEEP_MIXED)) {
+        S.mixed = mode == WG_SWEEP_MIXED;
+        if (S.exec) { (void)hipGraphExecDestroy(S.exec); S.exec = nullptr; }
+        if (S.graph) { (void)hipGraphDestroy(S.graph); S.graph = nullptr; }
+    }
+    return WG_OK;
+}
+
+int wg_sweep_matrices_f64(const wg_sweep* sweep, int cand, double* AT, double* G, double* BT) {
+    if (!sweep || !AT || !G || !BT) return fail(WG_EINVAL, "wg_sweep_matrices_f64: null pointer");
+    const Sweep& S = *reinterpret_cast<const Sweep*>(sweep);
+    if (cand < 0 || cand >= S.max_cand) return fail(WG_EINVAL, "wg_sweep_matrices_f64: candidate out of range");
+    if (!S.mats64) return fail(WG_EINVAL, "wg_sweep_matrices_f64: the sweep has not run in mixed precision");
+    const int m = S.m, r = S.r, A = S.alpha;
+    double buf[kMatStride];
+    int st = hipc(hipMemcpy(buf, S.mats64 + (size_t)cand * kMatStride, sizeof(buf), hipMemcpyDeviceToHost),
+                  "hipMemcpy");
+    if (st != WG_OK) return st;
+    std::memcpy(AT, buf, sizeof(double) * m * A);
+    std::memcpy(G, buf + m * A, sizeof(double) * A * r);
+    std::memcpy(BT, buf + m * A + A * r, sizeof(double) * A * A);
+    return WG_OK;
 }
 
 int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, float* BT, int* flag) {

@@ -38,6 +38,8 @@ struct Sweep {
     double* ref_abs = nullptr;   // sum |yref| per sample
     double* prefix = nullptr;    // prefix sums of ref_abs (n_pool + 1)
     float* mats = nullptr;       // per candidate float32 A^T | G | B^T
+    double* mats64 = nullptr;    // the same in float64 (mixed precision only)
+    int mixed = 0;               // 1: float64 transforms, float32 Hadamard product
     int* flags = nullptr;        // per candidate: 1 = invalid or singular
     double* partial = nullptr;   // per work item error sums
     SweepTune tune{128, 128, 4};

@@ -77,6 +77,8 @@ _SIGS = {
     "wg_sweep_destroy": (c_int, [c_void_p]),
     "wg_sweep_run": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_run_points": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "wg_sweep_set_precision": (c_int, [c_void_p, c_int]),
+    "wg_sweep_matrices_f64": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "wg_sweep_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_tuning": (c_int, [c_void_p, P_int, P_int, P_int]),
     "wg_sweep_matrices": (c_int, [c_void_p, c_int, P_float, P_float, P_float, P_int]),
@@ -435,6 +437,20 @@ class Sweep:
         b, c, k = c_int(), c_int(), c_int()
         tuned = _check(lib().wg_sweep_tuning(self._h, ctypes.byref(b), ctypes.byref(c), ctypes.byref(k)))
         return dict(block=b.value, chunk=c.value, blocks_per_cu=k.value, tuned=bool(tuned))
+
+    def set_precision(self, mode):
+        """'f32' (default) or 'mixed' (float64 transforms, float32 Hadamard)."""
+        code = {"f32": 0, "mixed": 1}[mode]
+        _check(lib().wg_sweep_set_precision(self._h, code))
+        self.precision = mode
+
+    def matrices_f64(self, cand):
+        a, m, r = self.alpha, self.m, self.r
+        AT = np.zeros((m, a), np.float64)
+        G = np.zeros((a, r), np.float64)
+        BT = np.zeros((a, a), np.float64)
+        _check(lib().wg_sweep_matrices_f64(self._h, cand, _dptr(AT), _dptr(G), _dptr(BT)))
+        return AT, G, BT
 
     def matrices(self, cand):
         a, m, r = self.alpha, self.m, self.r

@@ -314,3 +314,51 @@ def test_f43_proposed_points_beat_every_base_subset(dims):
     own = search.subset_search(S, [], cs)[0]["mean_abs"]
     for base in ([0.5], [3.0], [-3.0], [1.0, -1.0]):
         assert own < search.subset_search(S, base, cs)[0]["mean_abs"], base
+
+
+# ----------------------------------------------------------------------------
+# mixed precision: float64 transforms, float32 Hadamard product
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("m,r", [(2, 3), (4, 3), (6, 3), (8, 3), (4, 5)])
+def test_mixed_precision_sweep_matches_oracle(m, r, dims):
+    """Families and explicit lists in mixed precision: every error sum equals
+    the oracle's mixed evaluation with the device's float64 matrices, and
+    those matrices are the exact ones rounded to float64 up to the float64
+    construction's own rounding (zeros exact)."""
+    from paper_2201_10369_amd import pointsets as ps
+    alpha = m + r - 1
+    n_pool = 400
+    S, d, g = _make(m, r, dims, n_pool, 16)
+    rng = np.random.default_rng(300 + 10 * m + r + dims)
+    c1 = np.exp(rng.uniform(np.log(0.3), np.log(4.0), 12))
+    c2 = np.exp(rng.uniform(np.log(0.3), np.log(4.0), 12))
+    c1[0], c2[0] = 2.0, 1.0
+    counts = rng.integers(0, n_pool + 30, 12).astype(np.int32)
+    counts[1] = n_pool
+    f32 = S.run(_dev(c1), _dev(c2), _dev(counts)).clone()
+    S.set_precision("mixed")
+    yref = sweep.pool_reference(d, g)
+    for mode in ("family", "points"):
+        if mode == "family":
+            out = S.run(_dev(c1), _dev(c2), _dev(counts)).cpu().numpy()
+        else:
+            out = S.run_points(_dev(ps.family_lists(alpha, c1, c2)), _dev(counts)).cpu().numpy()
+        for i in range(len(c1)):
+            n = min(int(counts[i]), n_pool)
+            if out[i, 3]:
+                continue
+            mats = S.matrices_f64(i)
+            e = sweep.candidate_error_mixed(mats, m, r, dims, d, g, yref, n)
+            assert out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-12, abs=1e-300), (mode, i)
+            if mode == "family":
+                ex = fp.mats_f64(tc.family_points(alpha, Fr(float(c1[i])), Fr(float(c2[i]))), m, r)
+                for mine, ref in zip(mats, ex):
+                    assert np.array_equal(mine == 0, ref == 0)
+                    assert np.allclose(mine, ref, rtol=1e-12, atol=0)
+    # the mixed form scores lower than float32 on the same candidates
+    fin = np.isfinite(out[:, 0]) & (out[:, 2] > 0)
+    assert out[fin, 0].sum() < f32.cpu().numpy()[fin, 0].sum()
+    # switching back restores the float32 results exactly
+    S.set_precision("f32")
+    assert torch.equal(S.run(_dev(c1), _dev(c2), _dev(counts)), f32)

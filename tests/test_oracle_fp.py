@@ -294,3 +294,99 @@ def test_f43_improvement_over_barabasz_points():
         e_prop = _err(dims, tc.family_points(6, Fr(str(c))), 6)
         imp = 100 * (e_base - e_prop) / e_base
         assert abs(imp - printed[dims]) < 5.0, (dims, imp)
+
+
+# ----------------------------------------------------------------------------
+# Mixed precision: float64 transforms, float32 Hadamard product (Section 6)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("pts", DYADIC_SETS)
+def test_mixed_tiles_exact_on_dyadic_points(dims, pts):
+    mats = fp.mats_f64(pts, 2, 3)
+    shape_d = (300, 4) if dims == 1 else (300, 4, 4)
+    shape_g = (300, 3) if dims == 1 else (300, 3, 3)
+    d = synth.exact_small_ints(shape_d, 1)
+    g = synth.exact_small_ints(shape_g, 2)
+    f = fp.tile_1d_mixed if dims == 1 else fp.tile_2d_mixed
+    assert np.array_equal(f(mats, d, g).astype(np.float64), fp.direct_tile_f64(d, g))
+
+
+def _mixed_tile_scalar(mats64, d, g):
+    """Independent scalar evaluation of one 2D mixed tile: Python floats are
+    float64 (each * and + rounded), np.float32 rounds to float32."""
+    AT, G, BT = ([[float(v) for v in row] for row in M_] for M_ in mats64)
+    a, r, m = len(BT), len(G[0]), len(AT)
+
+    def two_sided(P, X):
+        n, k = len(P), len(X)
+        T = [[0.0] * k for _ in range(n)]
+        for i in range(n):
+            for b in range(k):
+                acc = 0.0
+                for l in range(k):
+                    acc = acc + P[i][l] * X[l][b]
+                T[i][b] = acc
+        out = [[0.0] * n for _ in range(n)]
+        for i in range(n):
+            for j in range(n):
+                acc = 0.0
+                for l in range(k):
+                    acc = acc + T[i][l] * P[j][l]
+                out[i][j] = acc
+        return out
+
+    U = two_sided(G, [[float(v) for v in row] for row in g])
+    V = two_sided(BT, [[float(v) for v in row] for row in d])
+    Mh = [[float(np.float32(np.float32(U[i][j]) * np.float32(V[i][j]))) for j in range(a)] for i in range(a)]
+    Y = two_sided(AT, Mh)
+    return np.array([[np.float32(v) for v in row] for row in Y], dtype=np.float32)
+
+
+def test_mixed_tile_matches_scalar_evaluation():
+    pts = tc.family_points(8, 1.7, 2.3)
+    mats = fp.mats_f64(pts, 6, 3)
+    d, g = synth.tile_pool(6, 8, 3, 2, seed=9)
+    y = fp.tile_2d_mixed(mats, d, g)
+    for n in range(6):
+        assert np.array_equal(y[n], _mixed_tile_scalar(mats, d[n], g[n]))
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("alpha,c", [(6, 1.622), (8, 2.0), (10, 1.3)])
+def test_mixed_tiles_within_float32_rounding_bound(dims, alpha, c):
+    """With float64 transforms only the float32 roundings of U, V, their
+    product and Y remain: |y - y_exact| <= 4u (|A^T| (|U| (.) |V|) |A|) + tiny,
+    u = 2^-24, independent of alpha (the float32 bound grows as 4 alpha u);
+    the mixed tiles also stay below the float32 tiles' largest error."""
+    m = alpha - 2
+    pts = tc.family_points(alpha, c, 2.7)
+    mats = fp.mats_f64(pts, m, 3)
+    AT, G, BT = (np.abs(M_) for M_ in mats)
+    d, g = synth.tile_pool(300, alpha, 3, dims, seed=4)
+    ad, ag = np.abs(d.astype(np.float64)), np.abs(g.astype(np.float64))
+    if dims == 1:
+        y, y32 = fp.tile_1d_mixed(mats, d, g), fp.tile_1d_f32(fp.mats_f32(pts, m, 3), d, g)
+        bound = np.einsum("ji,ni->nj", AT, np.einsum("ik,nk->ni", G, ag) * np.einsum("il,nl->ni", BT, ad))
+    else:
+        y, y32 = fp.tile_2d_mixed(mats, d, g), fp.tile_2d_f32(fp.mats_f32(pts, m, 3), d, g)
+        Ub = np.einsum("ik,nkl,jl->nij", G, ag, G)
+        Vb = np.einsum("ik,nkl,jl->nij", BT, ad, BT)
+        bound = np.einsum("ik,nkl,jl->nij", AT, Ub * Vb, AT)
+    ref = fp.direct_tile_f64(d, g)
+    lim = 4 * 2.0 ** -24 * bound + 1e-12 * bound
+    err = np.abs(y.astype(np.float64) - ref)
+    assert np.all(err <= lim) and err.max() > 0
+    assert err.max() < np.abs(y32.astype(np.float64) - ref).max()
+
+
+@pytest.mark.parametrize("alpha,m,pts", [(6, 4, [Fr(-5, 8), Fr(-8, 5), Fr(0), Fr(8, 5), Fr(5, 8)]),
+                                         (8, 6, None)])
+def test_mixed_precision_lowers_the_error(alpha, m, pts):
+    """Section 6 scores both forms; float64 transforms remove most of the
+    transform rounding (here about half the mean absolute error)."""
+    pts = tc.family_points(8, 2.0, 1.0) if pts is None else pts
+    d, g = synth.tile_pool(300, alpha, 3, 2, seed=2)
+    yref = fp.direct_tile_f64(d, g)
+    e32 = fp.l1_errors(fp.tile_2d_f32(fp.mats_f32(pts, m, 3), d, g), yref)["mean_abs"]
+    emx = fp.l1_errors(fp.tile_2d_mixed(fp.mats_f64(pts, m, 3), d, g), yref)["mean_abs"]
+    assert emx < 0.75 * e32
