@@ -221,6 +221,19 @@ int wg_conv2d_forward(const wg_plan* plan, const float* x, const void* U, float*
  *           discarded. */
 int wg_input_transform(const wg_plan* plan, const float* x, const void* U,
                        void* ws, size_t ws_bytes, wg_stream_t stream);
+
+/* The filter transform of w (as wg_transform_filters) and the input
+ * transform of x (as wg_input_transform) in one launch, after the 16-bit
+ * partial maxima of |w|: both transforms are amortised stages with no
+ * dependence on each other (Section 4.1), so the short filter blocks run
+ * beside the input transform instead of as a launch of their own.  U and the V' part of ws receive exactly what the two separate
+ * calls write (the input blocks derive the 16-bit exponent part t[c] from
+ * the same partial maxima as the filter blocks).  Arguments as for the two
+ * calls; x_absmax may be NULL.  Errors: WG_EINVAL, WG_EWORKSPACE,
+ * WG_EUNSUPPORTED (the limits of both calls), WG_EHIP. */
+int wg_transform_filters_and_input(const wg_plan* plan, const float* w, const float* x_absmax,
+                                   const float* x, void* U, void* ws, size_t ws_bytes,
+                                   wg_stream_t stream);
 int wg_hadamard_gemm(const wg_plan* plan, const void* U, void* ws, size_t ws_bytes,
                      wg_stream_t stream);
 int wg_output_transform(const wg_plan* plan, const void* ws, size_t ws_bytes, float* y,

@@ -10,6 +10,9 @@
 // Layout: V'[e][p][c], c contiguous (the GEMM contraction), p = tile index.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "wg_filter_block.h"
 #include "wg_layer_common.h"
 
 #pragma clang fp contract(off)
@@ -55,25 +58,33 @@ struct BtTerms {
     __device__ static constexpr int hi(int q) { return (S && q < A - 1) ? A - 2 : A - 1; }
 };
 
-template <int M, int R, int DT, bool S>
-__global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float* __restrict__ x,
-                                                                     void* __restrict__ Vout,
-                                                                     const int32_t* __restrict__ t_tab,
-                                                                     Mats<M, R> mt, RowPerm rp, RowExps ex,
-                                                                     Geo g, int twb, int n_twb, int pair_stride,
-                                                                     int n_blocks) {
+struct InputArgs {
+    const float* x;            // N x C x H x W
+    void* V;                   // V'[e][p][c]
+    const int32_t* t_tab;      // t[c] from the filter transform (16-bit stage)
+    const float* part;         // or: partial maxima of |w| per filter chunk ...
+    const float* x_absmax;     // ... with the per-channel max |x| (null: bound 1)
+    int kchunks;
+    int twb, n_twb, pair_stride, n_blocks;
+};
+
+// The block of work item w (image, tile row, tile group, channel group).
+// TP: the 16-bit exponent part t[c] is derived here from the partial maxima
+// (as the filter transform derives it) instead of read from t_tab.
+template <int M, int R, int DT, bool S, bool TP>
+__device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R>& mt, const RowPerm& rp,
+                                            const Geo& g, int w) {
     constexpr int A = M + R - 1;
     constexpr int CS = 2 * (A | 1);
     using T = typename Elem<DT>::T;
     using Terms = BtTerms<A, S>;
+    const float* __restrict__ x = ia.x;
+    const int twb = ia.twb, n_twb = ia.n_twb, pair_stride = ia.pair_stride;
     extern __shared__ float lds[];
     __shared__ int sdB[A];                        // dB of T1 row slot k (RowPerm order)
     __shared__ int srow[A];                       // T1 row index of slot k
     __shared__ int stc[kInCh];
     const int tid = threadIdx.x;
-    const int per_xcd = (int)(gridDim.x / kXcdCount);
-    const int w = (int)(blockIdx.x % kXcdCount) * per_xcd + (int)(blockIdx.x / kXcdCount);
-    if (w >= n_blocks) return;                      // whole block: before any barrier
     const int n_cb = g.C_pad / kInCh;
     int bx = w;
     const int c0 = (bx % n_cb) * kInCh;
@@ -93,8 +104,19 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
             sdB[k] = rp.dB[k];
         }
     }
-    if (DT != kF32 && tid < kInCh) stc[tid] = c0 + tid < g.C ? t_tab[c0 + tid] : 0;
-
+    if (DT != kF32 && !TP && tid < kInCh) stc[tid] = c0 + tid < g.C ? ia.t_tab[c0 + tid] : 0;
+    // 16-bit exponent part t[c] from the partial maxima (TP): eight threads
+    // per channel, each every eighth filter chunk; the first loads are issued
+    // here and reduced after pass 1, so they overlap the input loads
+    constexpr int kPartStep = kInThreads / kInCh, kPartRegs = 4;
+    __shared__ float spart[kPartStep][kInCh];
+    float pv[kPartRegs];
+    const int pcc = c0 + (tid & (kInCh - 1));
+#pragma unroll
+    for (int j = 0; j < kPartRegs; ++j) {
+        const int q = tid / kInCh + j * kPartStep;
+        pv[j] = (DT != kF32 && TP && pcc < g.C && q < ia.kchunks) ? ia.part[(size_t)q * g.C_pad + pcc] : 0.0f;
+    }
     // load + pass 1
     {
         const size_t img = (size_t)g.C * g.H * g.W;
@@ -145,13 +167,30 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
             }
         }
     }
+    if (DT != kF32 && TP) {
+        float aw = fmaxf(fmaxf(pv[0], pv[1]), fmaxf(pv[2], pv[3]));
+        if (pcc < g.C)
+            for (int q = tid / kInCh + kPartRegs * kPartStep; q < ia.kchunks; q += kPartStep)
+                aw = fmaxf(aw, ia.part[(size_t)q * g.C_pad + pcc]);
+        spart[tid / kInCh][tid & (kInCh - 1)] = aw;
+    }
     __syncthreads();
+    if (DT != kF32 && TP) {
+        if (tid < kInCh) {
+            float mw = spart[0][tid];
+#pragma unroll
+            for (int q = 1; q < kInThreads / kInCh; ++q) mw = fmaxf(mw, spart[q][tid]);
+            stc[tid] = c0 + tid < g.C ? bin_exp(ia.x_absmax != nullptr ? ia.x_absmax[c0 + tid] : 1.0f) - bin_exp(mw)
+                                      : 0;
+        }
+        __syncthreads();
+    }
 
     // pass 2: V = T1 B, row by row for pairs of adjacent channels; scaling,
     // rounding, and one store per pair.  The 16-bit exponent
     // -floor((dB[i] + dB[j] + t[c]) / 2) is taken as
     // (1 - dB[i] - t[c] - dB[j]) >> 1 (padded channels hold zeros).
-    T* V = reinterpret_cast<T*>(Vout);
+    T* V = reinterpret_cast<T*>(ia.V);
     const size_t plane = (size_t)g.P_pad * g.C_pad;
     for (int q = tid; q < kInPairs * ntw * A; q += kInThreads) {
         const int pc = q % kInPairs, rest = q / kInPairs;
@@ -190,17 +229,64 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(const float
     }
 }
 
-template <int M, int R, int DT, bool S>
-static void input_launch(dim3 grid, size_t lds_bytes, hipStream_t s, const float* x, void* V,
-                         const int32_t* t_tab, const Mats<M, R>& mt, const RowPerm& rp, const RowExps& ex,
-                         const Geo& g, int twb, int n_twb, int pair_stride, int nb) {
-    allow_lds(input_transform_kernel<M, R, DT, S>, lds_bytes);
-    hipLaunchKernelGGL((input_transform_kernel<M, R, DT, S>), grid, dim3(kInThreads), lds_bytes, s, x, V, t_tab, mt,
-                       rp, ex, g, twb, n_twb, pair_stride, nb);
+// Block b of a grid of n_grid blocks (a multiple of kXcdCount) -> work item:
+// each XCD runs a contiguous range of items.
+__device__ __forceinline__ int xcd_item(int b, int n_grid) {
+    const int per_xcd = n_grid / kXcdCount;
+    return (b % kXcdCount) * per_xcd + b / kXcdCount;
 }
 
+template <int M, int R, int DT, bool S>
+__global__ __launch_bounds__(kInThreads) void input_transform_kernel(InputArgs ia, Mats<M, R> mt, RowPerm rp,
+                                                                     Geo g) {
+    const int w = xcd_item((int)blockIdx.x, (int)gridDim.x);
+    if (w >= ia.n_blocks) return;                   // whole block: before any barrier
+    input_block<M, R, DT, S, false>(ia, mt, rp, g, w);
+}
+
+// Filter and input transforms in one launch: the first gridDim.x - n_in_grid
+// blocks are filter-transform blocks (channel group, filter), dispatched
+// first, the last n_in_grid input-transform blocks (t[c] from the partial
+// maxima), which take over the compute units as the short filter blocks
+// finish; no launch boundary separates the two stages.
+template <int M, int R, int DT, bool S>
+__global__ __launch_bounds__(kInThreads) void filter_input_kernel(InputArgs ia, FilterArgs fa, Mats<M, R> mt,
+                                                                  RowPerm rp, RowExps ex, Geo g, int n_in_grid,
+                                                                  int f_groups) {
+    const int nf = (int)gridDim.x - n_in_grid;
+    const int b = (int)blockIdx.x - nf;
+    if (b >= 0) {
+        const int w = xcd_item(b, n_in_grid);
+        if (w >= ia.n_blocks) return;
+        input_block<M, R, DT, S, true>(ia, mt, rp, g, w);
+    } else {
+        extern __shared__ float lds[];
+        const int f = (int)blockIdx.x;
+        filter_block<M, R, DT>(fa, mt, ex, g, f % f_groups, f / f_groups, reinterpret_cast<int*>(lds));
+    }
+}
+
+template <int M, int R, int DT, bool S>
+static void input_launch(dim3 grid, size_t lds_bytes, hipStream_t s, const InputArgs& ia, const Mats<M, R>& mt,
+                         const RowPerm& rp, const Geo& g) {
+    allow_lds(input_transform_kernel<M, R, DT, S>, lds_bytes);
+    hipLaunchKernelGGL((input_transform_kernel<M, R, DT, S>), grid, dim3(kInThreads), lds_bytes, s, ia, mt, rp, g);
+}
+
+template <int M, int R, int DT, bool S>
+static void filter_input_launch(unsigned n_in_grid, unsigned n_f_blocks, int f_groups, size_t lds_bytes,
+                                hipStream_t s, const InputArgs& ia, const FilterArgs& fa, const Mats<M, R>& mt,
+                                const RowPerm& rp, const RowExps& ex, const Geo& g) {
+    allow_lds(filter_input_kernel<M, R, DT, S>, lds_bytes);
+    hipLaunchKernelGGL((filter_input_kernel<M, R, DT, S>), dim3(n_in_grid + n_f_blocks), dim3(kInThreads), lds_bytes,
+                       s, ia, fa, mt, rp, ex, g, (int)n_in_grid, f_groups);
+}
+
+// fused: w non-null -> the filter transform of w runs in the same launch
+// (after the 16-bit partial maxima), t[c] derived in the input blocks.
 template <int M, int R>
-static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s) {
+static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
+                      const float* x_absmax) {
     constexpr int A = M + R - 1;
     constexpr int CS = 2 * (A | 1);
     const wg_layout& L = p.L;
@@ -233,29 +319,56 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const int n_twb = (L.Tw + twb - 1) / twb;
     const long n_blocks = (long)L.N * L.Th * n_twb * (L.C_pad / kInCh);
     if (n_blocks > (1L << 30)) return fail(WG_EUNSUPPORTED, "input transform: grid too large");
-    const dim3 grid((unsigned)((n_blocks + kXcdCount - 1) / kXcdCount * kXcdCount));
+    const unsigned n_in_grid = (unsigned)((n_blocks + kXcdCount - 1) / kXcdCount * kXcdCount);
+    const dim3 grid(n_in_grid);
     const int32_t* t_tab = reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.chan_offset);
     void* V = static_cast<char*>(ws) + L.v_offset;
-    const int nb = (int)n_blocks;
-#define WG_IN(DT)                                                                                                 \
-    (structured ? input_launch<M, R, DT, true>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb,         \
-                                               pair_stride, nb)                                                   \
-                : input_launch<M, R, DT, false>(grid, lds_bytes, s, x, V, t_tab, mt, rp, ex, g, twb, n_twb,        \
-                                                pair_stride, nb))
-    switch (L.dtype) {
-        case WG_F32: WG_IN(kF32); break;
-        case WG_F16: WG_IN(kF16); break;
-        default: WG_IN(kBF16); break;
-    }
+    if (w == nullptr) {
+        const InputArgs ia{x, V, t_tab, nullptr, nullptr, 0, twb, n_twb, pair_stride, (int)n_blocks};
+#define WG_IN(DT)                                                                                 \
+    (structured ? input_launch<M, R, DT, true>(grid, lds_bytes, s, ia, mt, rp, g)                 \
+                : input_launch<M, R, DT, false>(grid, lds_bytes, s, ia, mt, rp, g))
+        switch (L.dtype) {
+            case WG_F32: WG_IN(kF32); break;
+            case WG_F16: WG_IN(kF16); break;
+            default: WG_IN(kBF16); break;
+        }
 #undef WG_IN
-    return last_launch("input_transform_kernel");
+        return last_launch("input_transform_kernel");
+    }
+    const FilterArgs fa = filter_args(p, w, x_absmax, const_cast<void*>(U));
+    const int st = launch_filter_absmax(p, fa, s);
+    if (st != WG_OK) return st;
+    const InputArgs ia{x, V, t_tab, fa.part, x_absmax, fa.kchunks, twb, n_twb, pair_stride, (int)n_blocks};
+    const int fg = filter_groups(L);
+    const unsigned n_f = (unsigned)fg * (unsigned)L.K_pad;
+    if ((size_t)n_in_grid + n_f > (1u << 31)) return fail(WG_EUNSUPPORTED, "filter and input transform: grid too large");
+    const size_t lds = std::max(lds_bytes, sizeof(int) * (size_t)kFilterLdsWords);
+#define WG_FI(DT)                                                                                           \
+    (structured ? filter_input_launch<M, R, DT, true>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g)     \
+                : filter_input_launch<M, R, DT, false>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g))
+    switch (L.dtype) {
+        case WG_F32: WG_FI(kF32); break;
+        case WG_F16: WG_FI(kF16); break;
+        default: WG_FI(kBF16); break;
+    }
+#undef WG_FI
+    return last_launch("filter_input_kernel");
 }
 
 int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-#define WG_CASE_input(MM, RR) case MM * 16 + RR: return input_impl<MM, RR>(p, x, U, ws, s);
+#define WG_CASE_input(MM, RR) case MM * 16 + RR: return input_impl<MM, RR>(p, x, U, ws, s, nullptr, nullptr);
     WG_DISPATCH(input)
 #undef WG_CASE_input
+}
+
+int launch_filter_input(const Plan& p, const float* w, const float* x_absmax, const float* x, void* U, void* ws,
+                        void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+#define WG_CASE_fi(MM, RR) case MM * 16 + RR: return input_impl<MM, RR>(p, x, U, ws, s, w, x_absmax);
+    WG_DISPATCH(fi)
+#undef WG_CASE_fi
 }
 
 }  // namespace wg

@@ -290,6 +290,15 @@ int wg_input_transform(const wg_plan* plan, const float* x, const void* U, void*
     return launch_input_transform(p, x, U, ws, stream);
 }
 
+int wg_transform_filters_and_input(const wg_plan* plan, const float* w, const float* x_absmax, const float* x,
+                                   void* U, void* ws, size_t ws_bytes, wg_stream_t stream) {
+    if (!plan || !w || !x || !U) return fail(WG_EINVAL, "wg_transform_filters_and_input: null pointer");
+    const Plan& p = *reinterpret_cast<const Plan*>(plan);
+    int st = check_ws(p, ws, ws_bytes, "wg_transform_filters_and_input");
+    if (st != WG_OK) return st;
+    return launch_filter_input(p, w, x_absmax, x, U, ws, stream);
+}
+
 int wg_hadamard_gemm(const wg_plan* plan, const void* U, void* ws, size_t ws_bytes,
                      wg_stream_t stream) {
     if (!plan || !U) return fail(WG_EINVAL, "wg_hadamard_gemm: null pointer");

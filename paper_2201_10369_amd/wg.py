@@ -66,6 +66,8 @@ _SIGS = {
     "wg_transform_filters": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "wg_conv2d_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "wg_input_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "wg_transform_filters_and_input": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                               c_void_p]),
     "wg_hadamard_gemm": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "wg_output_transform": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "wg_channel_absmax": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p]),
@@ -274,6 +276,16 @@ class Plan:
         _check(lib().wg_input_transform(self._h, _tptr(x, torch.float32, "x"), _tptr(U, None, "U"),
                                         _tptr(ws, None, "ws"), ws.numel() * ws.element_size(),
                                         _stream(stream)))
+
+    def transform_filters_and_input(self, w, x, U, ws, x_absmax=None, stream=None):
+        """Filter and input transforms in one launch (same U and V' as
+        transform_filters followed by input_transform)."""
+        torch = _torch()
+        _check(lib().wg_transform_filters_and_input(self._h, _tptr(w, torch.float32, "w"),
+                                                    _tptr(x_absmax, torch.float32, "x_absmax"),
+                                                    _tptr(x, torch.float32, "x"), _tptr(U, None, "U"),
+                                                    _tptr(ws, None, "ws"), ws.numel() * ws.element_size(),
+                                                    _stream(stream)))
 
     def hadamard_gemm(self, U, ws, stream=None):
         _check(lib().wg_hadamard_gemm(self._h, _tptr(U, None, "U"), _tptr(ws, None, "ws"),

@@ -123,6 +123,29 @@ def test_transforms_bitexact(case, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", CASES)
+def test_filter_and_input_in_one_launch_match_separate_calls(case, dtype):
+    """wg_transform_filters_and_input writes the same U' (and 16-bit scale
+    table) and the same V' as wg_transform_filters then wg_input_transform,
+    into buffers that start out filled with garbage."""
+    m, r, fam, N, C, K, H, W, padding = case
+    pts = _pts(fam)
+    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, padding, dtype, x_absmax=True)
+    L = plan.layout
+    ws = plan.empty_workspace()
+    plan.input_transform(xd, U, ws)
+    U2 = plan.empty_filters().fill_(0x7D)
+    ws2 = plan.empty_workspace().fill_(0x7D)
+    plan.transform_filters_and_input(wd, xd, U2, ws2, _dev(ax))
+    torch.cuda.synchronize()
+    assert torch.equal(plan.view_U(U2), plan.view_U(U))
+    if dtype != "f32":
+        assert torch.equal(plan.view_scales(U2), plan.view_scales(U))
+    P = L["P"]
+    assert torch.equal(plan.view_V(ws2)[:, :P], plan.view_V(ws)[:, :P])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("case", CASES[:4] + CASES[-1:])
 def test_gemm_and_output_transform(case, dtype):
     """The MFMA channel-sum GEMM is within the summation-order bound of the
@@ -338,6 +361,16 @@ def test_full_size_sampled_tiles(name, fam, dtype):
     rel = np.sum(diffs) / np.sum(refs)
     if dtype == "f32":
         assert rel <= 1e-5
+    # the launch sequence the benchmark times (filter and input transforms in
+    # one launch, then GEMM and output transform) gives the same output
+    U2 = plan.empty_filters()
+    ws2 = plan.empty_workspace()
+    y2 = plan.empty_output()
+    plan.transform_filters_and_input(wd, xd, U2, ws2)
+    plan.hadamard_gemm(U2, ws2)
+    plan.output_transform(ws2, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y2, y)
     # float64 direct convolution at sampled outputs
     y64 = wg.direct_conv_f64(xd, wd, "same")
     coords = np.stack([rng.integers(0, N, 200), rng.integers(0, K, 200), rng.integers(0, L["Hout"], 200),
