@@ -57,9 +57,9 @@ def algorithmic_bytes(L, dtype):
             "output": M + y}
 
 
-def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup):
+def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup, m=6):
     N, C, K, H, W = (L0[k] for k in ("N", "C", "K", "H", "W"))
-    plan = wg.Plan(6, 3, pts, N, C, K, H, W, "same", dtype)
+    plan = wg.Plan(m, 3, pts, N, C, K, H, W, "same", dtype)
     ax = wg.channel_absmax(x) if dtype != "f32" else None
     U = plan.empty_filters()
     ws = plan.empty_workspace()
@@ -158,6 +158,33 @@ def bench_sweep(wg, torch, reps=5):
         best = int(np.nanargmin(np.where(o[:, 3] > 0, np.inf, mean)))
         res[f"{dims}d"]["mixed"] = {"ms": round(ms, 4), "best_c": float(c1[best]),
                                     "best_mean_abs": float(mean[best])}
+    return res
+
+
+def bench_other_layers(wg, torch, curve_c, steps=50, warmup=5):
+    """The float32 layers of the smaller configurations: F(2x2,3x3) with
+    {0, 1, -1, inf} (N=1, C=K=16, 32x32, uniform data) and F(4x4,3x3) with
+    {0, inf, +-c, +-1/c} at c = 2 and at the error curve's best c (N=32,
+    C=K=256, 56x56), each timed as the bench step and scored against the
+    float64 direct convolution."""
+    res = {}
+    for name, m, cs in (("f2x2_n1_c16_k16_32x32", 2, [None]), ("f4x4_n32_c256_k256_56x56", 4, [2.0, curve_c])):
+        cfg = synth.LAYERS[name]
+        N, C, K, H, W, r = (cfg[k] for k in ("N", "C", "K", "H", "W", "r"))
+        xh, wh = synth.layer_inputs(N, C, K, H, W, r, cfg["dist"])
+        x, w = torch.from_numpy(xh).cuda(), torch.from_numpy(wh).cuda()
+        y64 = wg.direct_conv_f64(x, w, "same")
+        flops = 2.0 * N * K * C * H * W * r * r
+        for c in cs:
+            pts = np.array([0.0, 1.0, -1.0]) if c is None else wg.family_points(6, c)
+            plan, U, y, ms, stage_ms = run_form(wg, torch, "f32", x, w, pts, dict(N=N, C=C, K=K, H=H, W=W),
+                                                steps, warmup, m=m)
+            sc = wg.score_error(y, y64).cpu().numpy()
+            key = name if c is None else f"{name}_c{c:.4g}"
+            res[key] = {"dtype": "f32", "points": "0,1,-1,inf" if c is None else f"0,inf,+-{c:.4g},+-1/{c:.4g}",
+                        "ms_per_step": round(ms, 5), "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                        "rel_l1": float(sc[0] / sc[1]), "mean_abs": float(sc[0] / y.numel()),
+                        "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()}}
     return res
 
 
@@ -347,6 +374,7 @@ def main():
     }
     out["sweep"] = bench_sweep(wg, torch)
     out["error_curve_f43"] = bench_error_curve(wg, torch)
+    out["other_layers"] = bench_other_layers(wg, torch, out["error_curve_f43"]["f32_2d"]["best_c"])
     out["two_param"] = bench_two_param(torch)
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(torch)
