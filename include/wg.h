@@ -222,15 +222,23 @@ int wg_conv2d_forward(const wg_plan* plan, const float* x, const void* U, float*
 int wg_input_transform(const wg_plan* plan, const float* x, const void* U,
                        void* ws, size_t ws_bytes, wg_stream_t stream);
 
+/* The first step of wg_transform_filters on its own: for WG_F16 / WG_BF16
+ * the maxima of |w| over chunks of filters, per channel, kept in U's buffer
+ * (nothing to do for WG_F32).  wg_transform_filters runs it itself;
+ * wg_transform_filters_and_input expects it to have run on the same w and U
+ * before (in stream order).  Errors: WG_EINVAL, WG_EHIP. */
+int wg_filter_maxima(const wg_plan* plan, const float* w, void* U, wg_stream_t stream);
+
 /* The filter transform of w (as wg_transform_filters) and the input
- * transform of x (as wg_input_transform) in one launch, after the 16-bit
- * partial maxima of |w|: both transforms are amortised stages with no
+ * transform of x (as wg_input_transform) in one launch, after
+ * wg_filter_maxima: both transforms are amortised stages with no
  * dependence on each other (Section 4.1), so the short filter blocks run
- * beside the input transform instead of as a launch of their own.  U and the V' part of ws receive exactly what the two separate
- * calls write (the input blocks derive the 16-bit exponent part t[c] from
- * the same partial maxima as the filter blocks).  Arguments as for the two
- * calls; x_absmax may be NULL.  Errors: WG_EINVAL, WG_EWORKSPACE,
- * WG_EUNSUPPORTED (the limits of both calls), WG_EHIP. */
+ * beside the input transform instead of as a launch of their own.  U and
+ * the V' part of ws receive exactly what wg_transform_filters followed by
+ * wg_input_transform write (the input blocks derive the 16-bit exponent
+ * part t[c] from the same partial maxima as the filter blocks).  Arguments
+ * as for the two calls; x_absmax may be NULL.  Errors: WG_EINVAL,
+ * WG_EWORKSPACE, WG_EUNSUPPORTED (the limits of both calls), WG_EHIP. */
 int wg_transform_filters_and_input(const wg_plan* plan, const float* w, const float* x_absmax,
                                    const float* x, void* U, void* ws, size_t ws_bytes,
                                    wg_stream_t stream);

@@ -139,6 +139,10 @@ int launch_filter_transform(const Plan& p, const float* w, const float* x_absmax
 #undef WG_CASE_filter
 }
 
+int launch_filter_maxima(const Plan& p, const float* w, void* U, void* stream) {
+    return launch_filter_absmax(p, filter_args(p, w, nullptr, U), static_cast<hipStream_t>(stream));
+}
+
 int launch_channel_absmax(const float* x, int N, int C, int HW, float* out, void* stream) {
     hipLaunchKernelGGL(channel_absmax_kernel, dim3(C), dim3(256), 0, static_cast<hipStream_t>(stream),
                        x, N, C, HW, out);

@@ -283,7 +283,8 @@ static void filter_input_launch(unsigned n_in_grid, unsigned n_f_blocks, int f_g
 }
 
 // fused: w non-null -> the filter transform of w runs in the same launch
-// (after the 16-bit partial maxima), t[c] derived in the input blocks.
+// (the 16-bit partial maxima of |w| must already be in U), t[c] derived in
+// the input blocks.
 template <int M, int R>
 static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
                       const float* x_absmax) {
@@ -336,9 +337,8 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
 #undef WG_IN
         return last_launch("input_transform_kernel");
     }
+    // the partial maxima of |w| (16-bit stage) are already in U (wg_filter_maxima)
     const FilterArgs fa = filter_args(p, w, x_absmax, const_cast<void*>(U));
-    const int st = launch_filter_absmax(p, fa, s);
-    if (st != WG_OK) return st;
     const InputArgs ia{x, V, t_tab, fa.part, x_absmax, fa.kchunks, twb, n_twb, pair_stride, (int)n_blocks};
     const int fg = filter_groups(L);
     const unsigned n_f = (unsigned)fg * (unsigned)L.K_pad;

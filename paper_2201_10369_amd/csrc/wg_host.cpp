@@ -290,6 +290,11 @@ int wg_input_transform(const wg_plan* plan, const float* x, const void* U, void*
     return launch_input_transform(p, x, U, ws, stream);
 }
 
+int wg_filter_maxima(const wg_plan* plan, const float* w, void* U, wg_stream_t stream) {
+    if (!plan || !w || !U) return fail(WG_EINVAL, "wg_filter_maxima: null pointer");
+    return launch_filter_maxima(*reinterpret_cast<const Plan*>(plan), w, U, stream);
+}
+
 int wg_transform_filters_and_input(const wg_plan* plan, const float* w, const float* x_absmax, const float* x,
                                    void* U, void* ws, size_t ws_bytes, wg_stream_t stream) {
     if (!plan || !w || !x || !U) return fail(WG_EINVAL, "wg_transform_filters_and_input: null pointer");

@@ -44,6 +44,7 @@ int launch_filter_transform(const Plan& p, const float* w, const float* x_absmax
                             void* stream);
 int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws,
                            void* stream);
+int launch_filter_maxima(const Plan& p, const float* w, void* U, void* stream);
 int launch_filter_input(const Plan& p, const float* w, const float* x_absmax, const float* x, void* U, void* ws,
                         void* stream);
 int launch_hadamard_gemm(const Plan& p, const void* U, void* ws, void* stream);

@@ -66,6 +66,7 @@ _SIGS = {
     "wg_transform_filters": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "wg_conv2d_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "wg_input_transform": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "wg_filter_maxima": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "wg_transform_filters_and_input": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                                c_void_p]),
     "wg_hadamard_gemm": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -277,9 +278,15 @@ class Plan:
                                         _tptr(ws, None, "ws"), ws.numel() * ws.element_size(),
                                         _stream(stream)))
 
+    def filter_maxima(self, w, U, stream=None):
+        """The 16-bit partial maxima of |w| into U (no-op for f32)."""
+        torch = _torch()
+        _check(lib().wg_filter_maxima(self._h, _tptr(w, torch.float32, "w"), _tptr(U, None, "U"),
+                                      _stream(stream)))
+
     def transform_filters_and_input(self, w, x, U, ws, x_absmax=None, stream=None):
-        """Filter and input transforms in one launch (same U and V' as
-        transform_filters followed by input_transform)."""
+        """Filter and input transforms in one launch, after filter_maxima
+        (same U and V' as transform_filters followed by input_transform)."""
         torch = _torch()
         _check(lib().wg_transform_filters_and_input(self._h, _tptr(w, torch.float32, "w"),
                                                     _tptr(x_absmax, torch.float32, "x_absmax"),

@@ -136,6 +136,7 @@ def test_filter_and_input_in_one_launch_match_separate_calls(case, dtype):
     plan.input_transform(xd, U, ws)
     U2 = plan.empty_filters().fill_(0x7D)
     ws2 = plan.empty_workspace().fill_(0x7D)
+    plan.filter_maxima(wd, U2)
     plan.transform_filters_and_input(wd, xd, U2, ws2, _dev(ax))
     torch.cuda.synchronize()
     assert torch.equal(plan.view_U(U2), plan.view_U(U))
@@ -366,6 +367,7 @@ def test_full_size_sampled_tiles(name, fam, dtype):
     U2 = plan.empty_filters()
     ws2 = plan.empty_workspace()
     y2 = plan.empty_output()
+    plan.filter_maxima(wd, U2)
     plan.transform_filters_and_input(wd, xd, U2, ws2)
     plan.hadamard_gemm(U2, ws2)
     plan.output_transform(ws2, y2)
