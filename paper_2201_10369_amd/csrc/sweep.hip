@@ -382,21 +382,26 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
                 for (int b = 0; b < A; ++b) t1[i][b] = madd(bc[i], drow[b], t1[i][b]);
             }
     }
-    // V = T1 B, one column of B^T at a time
-    T vv[A][A];
-#pragma unroll
-    for (int i = 0; i < A; ++i)
-#pragma unroll
-        for (int j = 0; j < A; ++j) vv[i][j] = T(0);
-#pragma unroll
-    for (int l = 0; l < A; ++l) {
-        T bc[AP];
-        lds_vec(lds + L::kBc + l * AP, bc);
+    // V = T1 B, one column of B^T at a time (float); in float64 row i of V
+    // is formed only when row i of the Hadamard stage needs it (same terms in
+    // the same order), which keeps the double tile within the registers
+    constexpr bool kRowV = sizeof(T) == 8;
+    T vv[kRowV ? 1 : A][A];
+    if constexpr (!kRowV) {
 #pragma unroll
         for (int i = 0; i < A; ++i)
 #pragma unroll
-            for (int j = 0; j < A; ++j)
-                if (Z::bt(j, l)) vv[i][j] = madd(t1[i][l], bc[j], vv[i][j]);
+            for (int j = 0; j < A; ++j) vv[i][j] = T(0);
+#pragma unroll
+        for (int l = 0; l < A; ++l) {
+            T bc[AP];
+            lds_vec(lds + L::kBc + l * AP, bc);
+#pragma unroll
+            for (int i = 0; i < A; ++i)
+#pragma unroll
+                for (int j = 0; j < A; ++j)
+                    if (Z::bt(j, l)) vv[i][j] = madd(t1[i][l], bc[j], vv[i][j]);
+        }
     }
     // row i of U = G g G^T, Hadamard with row i of V (float32), accumulate
     // Z = A^T Mh
@@ -408,6 +413,21 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
 #pragma unroll
     for (int i = 0; i < A; ++i) {
         T gr[RP], p1[R], urow[A], ac[MP];
+        T* vr = vv[kRowV ? 0 : i];
+        if constexpr (kRowV) asm volatile("" ::: "memory");
+        if constexpr (kRowV) {
+#pragma unroll
+            for (int j = 0; j < A; ++j) vr[j] = T(0);
+#pragma unroll
+            for (int l = 0; l < A; ++l) {
+                asm volatile("" ::: "memory");
+                T bc[AP];
+                lds_vec(lds + L::kBc + l * AP, bc);
+#pragma unroll
+                for (int j = 0; j < A; ++j)
+                    if (Z::bt(j, l)) vr[j] = madd(t1[i][l], bc[j], vr[j]);
+            }
+        }
         lds_vec(lds + L::kGr + i * RP, gr);
 #pragma unroll
         for (int v = 0; v < R; ++v) p1[v] = T(0);
@@ -430,7 +450,7 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
         lds_vec(lds + L::kAc + i * MP, ac);
 #pragma unroll
         for (int j = 0; j < A; ++j) {
-            const float mh = (float)urow[j] * (float)vv[i][j];
+            const float mh = (float)urow[j] * (float)vr[j];
 #pragma unroll
             for (int k = 0; k < M; ++k)
                 if (Z::at(k, i)) z[k][j] = madd(ac[k], (T)mh, z[k][j]);
@@ -535,7 +555,9 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
                                                          const int* __restrict__ counts, int n_cand, int n_pool,
                                                          int ipc, int chunk, double* __restrict__ partial) {
     using L = EvalLds<M, R>;
-    using Z = typename std::conditional<FAM, FamilyZeros<M, R>, AllTerms<M, R>>::type;
+    // (the float64 tiles take every term: skipping the exact zeros changes no
+    // result and made the compiler spill them)
+    using Z = typename std::conditional<FAM && sizeof(T) == 4, FamilyZeros<M, R>, AllTerms<M, R>>::type;
     __shared__ __align__(16) T sm[L::kSize];
     __shared__ double red[256];
     const int tid = threadIdx.x, nthr = blockDim.x;
