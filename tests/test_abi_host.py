@@ -220,3 +220,26 @@ def test_point_sets_of_the_tables():
         ps.base_subsets(4, [1.0, -1.0, 3.0])
     fam = ps.family_lists(10, [2.0, 1.5], [3.0, 1.25])
     assert fam.shape == (2, 9) and np.array_equal(fam[0], wg.family_points(10, 2.0, 3.0))
+
+
+def test_launch_size_limits_are_rejected_before_any_launch():
+    """The 32-bit byte-offset limits of the layer kernels (one image of x,
+    one row of alpha planes of M, 128 rows of a plane) give WG_EUNSUPPORTED
+    from the host checks, before anything is launched.  The buffers are
+    placeholders that are never dereferenced; the test is skipped where a GPU
+    is present, so a missing check can never launch on them."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("host-only check with placeholder device pointers")
+    L = wg.lib()
+    fake = ctypes.c_void_p(1 << 40)
+    pts = wg.family_points(8, 2.0, 1.0)
+    # one image of x: C_pad * H * W * 4 = 2 GiB
+    p = wg.Plan(6, 3, pts, 1, 8192, 64, 256, 256, "same", "f16")
+    assert L.wg_input_transform(p.handle, fake, fake, fake, p.workspace_bytes, None) == -3
+    assert "2 GB" in L.wg_last_error().decode()
+    assert L.wg_transform_filters_and_input(p.handle, fake, None, fake, fake, fake, p.workspace_bytes, None) == -3
+    # one row of alpha planes of M: alpha * K_pad * P_pad * 4 >= 2 GiB
+    p = wg.Plan(6, 3, pts, 16384, 16, 256, 28, 28, "same", "f32")
+    assert L.wg_output_transform(p.handle, fake, p.workspace_bytes, fake, None) == -3
+    assert "planes of M" in L.wg_last_error().decode()
