@@ -59,7 +59,7 @@ def algorithmic_bytes(L, dtype):
 def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup, m=6):
     N, C, K, H, W = (L0[k] for k in ("N", "C", "K", "H", "W"))
     plan = wg.Plan(m, 3, pts, N, C, K, H, W, "same", dtype)
-    ax = wg.channel_absmax(x) if dtype != "f32" else None
+    ax = wg.channel_absmax(x) if dtype in ("f16", "bf16") else None
     U = plan.empty_filters()
     ws = plan.empty_workspace()
     y = plan.empty_output()
@@ -334,7 +334,7 @@ def main():
     flops = 2.0 * N * K * C * H * W * r * r               # 'same': Hout = H, Wout = W
 
     forms = {}
-    for dtype in ("f16", "f32", "bf16"):
+    for dtype in ("f16", "f32", "bf16", "mixed"):
         plan, U, y, ms, stage_ms = run_form(wg, torch, dtype, x, w, pts, L0, args.steps, args.warmup)
         forms[dtype] = dict(plan=plan, y=y, ms=ms, stage_ms=stage_ms)
 

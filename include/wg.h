@@ -57,6 +57,14 @@ typedef enum {
 /* construction flags */
 enum { WG_MODIFIED = 0,    /* alpha-1 finite points + infinity (Section 4.2) */
        WG_UNMODIFIED = 1 };/* alpha finite points (plain Toom-Cook, Section 4.1) */
+/* plan flag (or-ed into the flags of wg_plan_create; dtype WG_F32 only):
+ * the mixed precision of Section 6, float64 transforms with a float32
+ * Hadamard stage.  The filter, input and output transforms use the exact
+ * matrices rounded to float64 and take each term as a rounded float64
+ * product and a rounded float64 sum in ascending order; U' and V' are
+ * rounded to float32, the channel sums are float32, and Y is rounded to
+ * float32. */
+enum { WG_F64_TRANSFORMS = 4 };
 /* padding */
 enum { WG_SAME = 0, WG_VALID = 1 };
 /* element type of the Hadamard (channel-sum) stage */
@@ -119,8 +127,10 @@ int wg_family_points(int alpha, double c1, double c2, double* pts_out);
  * ---------------------------------------------------------------------- */
 typedef struct wg_plan wg_plan;
 
-/* Creates a plan.  Errors: WG_EINVAL (null out/pts, non-positive sizes,
- * padding or dtype out of range, output smaller than 1x1), WG_EUNSUPPORTED
+/* Creates a plan.  flags: WG_MODIFIED, optionally | WG_F64_TRANSFORMS.
+ * Errors: WG_EINVAL (null out/pts, non-positive sizes, padding, dtype or
+ * flags out of range, WG_F64_TRANSFORMS with a 16-bit dtype, output smaller
+ * than 1x1), WG_EUNSUPPORTED
  * ((m, r) not implemented; WG_SAME with even r; WG_UNMODIFIED), WG_ESINGULAR,
  * WG_ENOMEM.  *out is set only on success. */
 int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, int flags,

@@ -327,10 +327,15 @@ def input_tiles(x, m, r, padding, tiles=None):
 
 def transformed_operands(x, w, mats, m, padding, dtype="f32", x_absmax=None, tiles=None):
     """U (K, C, a, a) and V (P, C, a, a) as the Hadamard stage consumes them:
-    float32, or scaled by 2^(+-s) and rounded to float16/bfloat16."""
+    float32, or scaled by 2^(+-s) and rounded to float16/bfloat16; with
+    dtype "mixed" (mats in float64) the float64 transforms of Section 6
+    rounded to float32."""
     AT, G, BT = mats
     r = G.shape[1]
     d = input_tiles(x, m, r, padding, tiles)
+    if dtype == "mixed":
+        return (xform2d_f64(G, np.asarray(w, dtype=F32)).astype(F32),
+                xform2d_f64(BT, d).astype(F32))
     V = xform2d(BT, d)
     U = xform2d(G, np.asarray(w, dtype=F32))
     if dtype == "f32":
@@ -357,6 +362,8 @@ def winograd_layer_tiles(x, w, mats, m, padding, dtype="f32", x_absmax=None, til
     AT, G, BT = mats
     U, V = transformed_operands(x, w, mats, m, padding, dtype, x_absmax, tiles)
     Mh = hadamard_channel_sum(U, V)
+    if dtype == "mixed":
+        return xform2d_f64(AT, Mh).astype(F32)
     return xform2d(AT, Mh)
 
 

@@ -55,10 +55,11 @@ __global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restr
 // ---------------------------------------------------------------------------
 // Filter transform kernel: grid (channel groups of 128, K_pad filters).
 // ---------------------------------------------------------------------------
-template <int M, int R, int DT>
-__global__ __launch_bounds__(256) void filter_transform_kernel(FilterArgs fa, Mats<M, R> mt, RowExps ex, Geo g) {
+template <int M, int R, int DT, typename CT>
+__global__ __launch_bounds__(256) void filter_transform_kernel(FilterArgs fa, Mats<M, R, CT> mt, RowExps ex,
+                                                               Geo g) {
     __shared__ int sm[kFilterLdsWords];
-    filter_block<M, R, DT>(fa, mt, ex, g, (int)blockIdx.x, (int)blockIdx.y, sm);
+    filter_block<M, R, DT, CT>(fa, mt, ex, g, (int)blockIdx.x, (int)blockIdx.y, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -112,21 +113,26 @@ static int filter_impl(const Plan& p, const float* w, const float* x_absmax, voi
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const Mats<M, R> mt = pack_mats<M, R>(p);
+    const Mats<M, R, double> mt64 = pack_mats<M, R, double>(p);
     RowExps ex{};
     for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
     const FilterArgs fa = filter_args(p, w, x_absmax, U);
     const int st = launch_filter_absmax(p, fa, s);
     if (st != WG_OK) return st;
     const dim3 grid((unsigned)filter_groups(L), (unsigned)L.K_pad);
+    if (p.f64t) {
+        hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32, double>), grid, dim3(256), 0, s, fa, mt64, ex, g);
+        return last_launch("filter_transform_kernel");
+    }
     switch (L.dtype) {
         case WG_F32:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32>), grid, dim3(256), 0, s, fa, mt, ex, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF32, float>), grid, dim3(256), 0, s, fa, mt, ex, g);
             break;
         case WG_F16:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16>), grid, dim3(256), 0, s, fa, mt, ex, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kF16, float>), grid, dim3(256), 0, s, fa, mt, ex, g);
             break;
         default:
-            hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16>), grid, dim3(256), 0, s, fa, mt, ex, g);
+            hipLaunchKernelGGL((filter_transform_kernel<M, R, kBF16, float>), grid, dim3(256), 0, s, fa, mt, ex, g);
             break;
     }
     return last_launch("filter_transform_kernel");

@@ -68,19 +68,35 @@ struct InputArgs {
     int twb, n_twb, pair_stride, n_blocks;
 };
 
+// Pair of adjacent channels' values in LDS
+template <typename CT>
+struct PairOf;
+template <>
+struct PairOf<float> {
+    using type = wg_f32x2;
+};
+template <>
+struct PairOf<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
 // The block of work item w (image, tile row, tile group, channel group).
 // TP: the 16-bit exponent part t[c] is derived here from the partial maxima
 // (as the filter transform derives it) instead of read from t_tab.
-template <int M, int R, int DT, bool S, bool TP>
-__device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R>& mt, const RowPerm& rp,
+// CT: float, or double for the float64 transforms (then DT is kF32, T1 is
+// kept in LDS as float64 and each V entry is rounded to float32).
+template <int M, int R, int DT, bool S, bool TP, typename CT = float>
+__device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R, CT>& mt, const RowPerm& rp,
                                             const Geo& g, int w) {
     constexpr int A = M + R - 1;
-    constexpr int CS = 2 * (A | 1);
+    constexpr int CS = 2 * (A | 1);               // LDS elements (CT) per column
     using T = typename Elem<DT>::T;
+    using P2 = typename PairOf<CT>::type;
     using Terms = BtTerms<A, S>;
     const float* __restrict__ x = ia.x;
     const int twb = ia.twb, n_twb = ia.n_twb, pair_stride = ia.pair_stride;
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds_raw[];
+    CT* lds = reinterpret_cast<CT*>(lds_raw);
     __shared__ int sdB[A];                        // dB of T1 row slot k (RowPerm order)
     __shared__ int srow[A];                       // T1 row index of slot k
     __shared__ int stc[kInCh];
@@ -136,28 +152,28 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
             const unsigned base = (unsigned)(cch * hw4 + gj * 4);
             const unsigned voff0 = (cok && cch < g.C) ? base : 0x80000000u;
             const unsigned voff1 = (cok && cch + 1 < g.C) ? base + (unsigned)hw4 : 0x80000000u;
-            float d0[A], d1[A];
+            CT d0[A], d1[A];
 #pragma unroll
             for (int a = 0; a < A; ++a) {
                 const int gi = row0 + a;                      // uniform over the block
                 if (gi >= 0 && gi < g.H) {
-                    d0[a] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, (int)voff0, gi * g.W * 4, 0));
-                    d1[a] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, (int)voff1, gi * g.W * 4, 0));
+                    d0[a] = (CT)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, (int)voff0, gi * g.W * 4, 0));
+                    d1[a] = (CT)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, (int)voff1, gi * g.W * 4, 0));
                 } else {
-                    d0[a] = 0.0f;
-                    d1[a] = 0.0f;
+                    d0[a] = CT(0);
+                    d1[a] = CT(0);
                 }
             }
-            float* dst = lds + pc * pair_stride + col * CS;
+            CT* dst = lds + pc * pair_stride + col * CS;
 #pragma unroll
             for (int k = 0; k < A; ++k) {
-                float t0 = 0.0f, t1 = 0.0f;
+                CT t0 = CT(0), t1 = CT(0);
 #pragma unroll
                 for (int l = Terms::lo(k); l <= Terms::hi(k); ++l) {
-                    t0 = __builtin_fmaf(mt.BT[k][l], d0[l], t0);
-                    t1 = __builtin_fmaf(mt.BT[k][l], d1[l], t1);
+                    t0 = madd(mt.BT[k][l], d0[l], t0);
+                    t1 = madd(mt.BT[k][l], d1[l], t1);
                 }
-                *reinterpret_cast<wg_f32x2*>(dst + 2 * k) = wg_f32x2{t0, t1};
+                *reinterpret_cast<P2*>(dst + 2 * k) = P2{t0, t1};
             }
             col += dcol;
             pc += dpc;
@@ -197,11 +213,11 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
         const int t = rest / A, k = rest - t * A;
         const int i = srow[k];
         const int gc = c0 + 2 * pc;
-        const float* rowp = lds + pc * pair_stride + (t * M) * CS + 2 * k;
-        float r0[A], r1[A];
+        const CT* rowp = lds + pc * pair_stride + (t * M) * CS + 2 * k;
+        CT r0[A], r1[A];
 #pragma unroll
         for (int l = 0; l < A; ++l) {
-            const wg_f32x2 v = *reinterpret_cast<const wg_f32x2*>(rowp + l * CS);
+            const P2 v = *reinterpret_cast<const P2*>(rowp + l * CS);
             r0[l] = v.x;
             r1[l] = v.y;
         }
@@ -214,12 +230,13 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
         T* Vi = V + (size_t)(i * A) * plane + ((size_t)p * g.C_pad + gc);
 #pragma unroll
         for (int kk = 0; kk < A; ++kk) {
-            float a0 = 0.0f, a1 = 0.0f;
+            CT q0 = CT(0), q1 = CT(0);
 #pragma unroll
             for (int l = Terms::lo(kk); l <= Terms::hi(kk); ++l) {
-                a0 = __builtin_fmaf(mt.BT[kk][l], r0[l], a0);
-                a1 = __builtin_fmaf(mt.BT[kk][l], r1[l], a1);
+                q0 = madd(mt.BT[kk][l], r0[l], q0);
+                q1 = madd(mt.BT[kk][l], r1[l], q1);
             }
+            float a0 = (float)q0, a1 = (float)q1;
             if (DT != kF32) {
                 a0 = ldexpf(a0, (nb0 - rp.dB[kk]) >> 1);
                 a1 = ldexpf(a1, (nb1 - rp.dB[kk]) >> 1);
@@ -236,12 +253,12 @@ __device__ __forceinline__ int xcd_item(int b, int n_grid) {
     return (b % kXcdCount) * per_xcd + b / kXcdCount;
 }
 
-template <int M, int R, int DT, bool S>
-__global__ __launch_bounds__(kInThreads) void input_transform_kernel(InputArgs ia, Mats<M, R> mt, RowPerm rp,
+template <int M, int R, int DT, bool S, typename CT>
+__global__ __launch_bounds__(kInThreads) void input_transform_kernel(InputArgs ia, Mats<M, R, CT> mt, RowPerm rp,
                                                                      Geo g) {
     const int w = xcd_item((int)blockIdx.x, (int)gridDim.x);
     if (w >= ia.n_blocks) return;                   // whole block: before any barrier
-    input_block<M, R, DT, S, false>(ia, mt, rp, g, w);
+    input_block<M, R, DT, S, false, CT>(ia, mt, rp, g, w);
 }
 
 // Filter and input transforms in one launch: the first gridDim.x - n_in_grid
@@ -249,8 +266,8 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(InputArgs i
 // first, the last n_in_grid input-transform blocks (t[c] from the partial
 // maxima), which take over the compute units as the short filter blocks
 // finish; no launch boundary separates the two stages.
-template <int M, int R, int DT, bool S>
-__global__ __launch_bounds__(kInThreads) void filter_input_kernel(InputArgs ia, FilterArgs fa, Mats<M, R> mt,
+template <int M, int R, int DT, bool S, typename CT>
+__global__ __launch_bounds__(kInThreads) void filter_input_kernel(InputArgs ia, FilterArgs fa, Mats<M, R, CT> mt,
                                                                   RowPerm rp, RowExps ex, Geo g, int n_in_grid,
                                                                   int f_groups) {
     const int nf = (int)gridDim.x - n_in_grid;
@@ -258,53 +275,57 @@ __global__ __launch_bounds__(kInThreads) void filter_input_kernel(InputArgs ia, 
     if (b >= 0) {
         const int w = xcd_item(b, n_in_grid);
         if (w >= ia.n_blocks) return;
-        input_block<M, R, DT, S, true>(ia, mt, rp, g, w);
+        input_block<M, R, DT, S, true, CT>(ia, mt, rp, g, w);
     } else {
-        extern __shared__ float lds[];
+        extern __shared__ __align__(16) float lds_f[];
         const int f = (int)blockIdx.x;
-        filter_block<M, R, DT>(fa, mt, ex, g, f % f_groups, f / f_groups, reinterpret_cast<int*>(lds));
+        filter_block<M, R, DT, CT>(fa, mt, ex, g, f % f_groups, f / f_groups, reinterpret_cast<int*>(lds_f));
     }
 }
 
-template <int M, int R, int DT, bool S>
-static void input_launch(dim3 grid, size_t lds_bytes, hipStream_t s, const InputArgs& ia, const Mats<M, R>& mt,
-                         const RowPerm& rp, const Geo& g) {
-    allow_lds(input_transform_kernel<M, R, DT, S>, lds_bytes);
-    hipLaunchKernelGGL((input_transform_kernel<M, R, DT, S>), grid, dim3(kInThreads), lds_bytes, s, ia, mt, rp, g);
+template <int M, int R, int DT, bool S, typename CT>
+static void input_launch(dim3 grid, size_t lds_bytes, hipStream_t s, const InputArgs& ia,
+                         const Mats<M, R, CT>& mt, const RowPerm& rp, const Geo& g) {
+    allow_lds(input_transform_kernel<M, R, DT, S, CT>, lds_bytes);
+    hipLaunchKernelGGL((input_transform_kernel<M, R, DT, S, CT>), grid, dim3(kInThreads), lds_bytes, s, ia, mt, rp,
+                       g);
 }
 
-template <int M, int R, int DT, bool S>
+template <int M, int R, int DT, bool S, typename CT>
 static void filter_input_launch(unsigned n_in_grid, unsigned n_f_blocks, int f_groups, size_t lds_bytes,
-                                hipStream_t s, const InputArgs& ia, const FilterArgs& fa, const Mats<M, R>& mt,
+                                hipStream_t s, const InputArgs& ia, const FilterArgs& fa, const Mats<M, R, CT>& mt,
                                 const RowPerm& rp, const RowExps& ex, const Geo& g) {
-    allow_lds(filter_input_kernel<M, R, DT, S>, lds_bytes);
-    hipLaunchKernelGGL((filter_input_kernel<M, R, DT, S>), dim3(n_in_grid + n_f_blocks), dim3(kInThreads), lds_bytes,
-                       s, ia, fa, mt, rp, ex, g, (int)n_in_grid, f_groups);
+    allow_lds(filter_input_kernel<M, R, DT, S, CT>, lds_bytes);
+    hipLaunchKernelGGL((filter_input_kernel<M, R, DT, S, CT>), dim3(n_in_grid + n_f_blocks), dim3(kInThreads),
+                       lds_bytes, s, ia, fa, mt, rp, ex, g, (int)n_in_grid, f_groups);
 }
 
 // fused: w non-null -> the filter transform of w runs in the same launch
 // (the 16-bit partial maxima of |w| must already be in U), t[c] derived in
-// the input blocks.
-template <int M, int R>
+// the input blocks.  CT: the transforms' arithmetic (double: float64
+// transforms, dtype WG_F32 only).
+template <int M, int R, typename CT>
 static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
                       const float* x_absmax) {
     constexpr int A = M + R - 1;
     constexpr int CS = 2 * (A | 1);
+    constexpr bool f64 = sizeof(CT) == 8;
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const bool structured = zero_shape(p).bt;
     const RowPerm rp = bt_row_perm(p, structured, (size_t)L.P_pad * L.C_pad);
     // B^T rows in RowPerm order
-    Mats<M, R> mt = pack_mats<M, R>(p);
+    Mats<M, R, CT> mt = pack_mats<M, R, CT>(p);
     for (int k = 0; k < A; ++k)
-        for (int l = 0; l < A; ++l) mt.BT[k][l] = p.BT[rp.row[k] * A + l];
+        for (int l = 0; l < A; ++l) mt.BT[k][l] = f64 ? (CT)p.BT64[rp.row[k] * A + l] : (CT)p.BT[rp.row[k] * A + l];
     RowExps ex{};
     for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
     // one image's input is addressed with 32-bit byte offsets (channels up to
     // C_pad, and an out-of-range marker at 2^31)
     if ((size_t)L.C_pad * L.H * L.W * sizeof(float) >= (1ull << 31))
         return fail(WG_EUNSUPPORTED, "input transform: one image of the input exceeds 2 GB");
-    // as many tiles of a tile row per block as fit in 40 KB of LDS, split evenly
+    // as many tiles of a tile row per block as fit in 40 KB of LDS, split
+    // evenly; pair_stride in elements of CT (even, 8 mod 64 words for float)
     int nsplit = 1, twb = 0, pair_stride = 0;
     size_t lds_bytes = 0;
     for (;; ++nsplit) {
@@ -312,7 +333,7 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
         const int wl = twb * M + R - 1;
         pair_stride = wl * CS;
         pair_stride += (8 - pair_stride % 64 + 64) % 64;
-        lds_bytes = (size_t)kInPairs * pair_stride * sizeof(float);
+        lds_bytes = (size_t)kInPairs * pair_stride * sizeof(CT);
         if (lds_bytes <= 40 * 1024 || twb == 1) break;
     }
     if (lds_bytes > 128 * 1024) return fail(WG_EUNSUPPORTED, "input transform: tile too large for LDS");
@@ -327,12 +348,16 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     if (w == nullptr) {
         const InputArgs ia{x, V, t_tab, nullptr, nullptr, 0, twb, n_twb, pair_stride, (int)n_blocks};
 #define WG_IN(DT)                                                                                 \
-    (structured ? input_launch<M, R, DT, true>(grid, lds_bytes, s, ia, mt, rp, g)                 \
-                : input_launch<M, R, DT, false>(grid, lds_bytes, s, ia, mt, rp, g))
-        switch (L.dtype) {
-            case WG_F32: WG_IN(kF32); break;
-            case WG_F16: WG_IN(kF16); break;
-            default: WG_IN(kBF16); break;
+    (structured ? input_launch<M, R, DT, true, CT>(grid, lds_bytes, s, ia, mt, rp, g)             \
+                : input_launch<M, R, DT, false, CT>(grid, lds_bytes, s, ia, mt, rp, g))
+        if constexpr (f64) {
+            WG_IN(kF32);
+        } else {
+            switch (L.dtype) {
+                case WG_F32: WG_IN(kF32); break;
+                case WG_F16: WG_IN(kF16); break;
+                default: WG_IN(kBF16); break;
+            }
         }
 #undef WG_IN
         return last_launch("input_transform_kernel");
@@ -344,21 +369,32 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const unsigned n_f = (unsigned)fg * (unsigned)L.K_pad;
     if ((size_t)n_in_grid + n_f > (1u << 31)) return fail(WG_EUNSUPPORTED, "filter and input transform: grid too large");
     const size_t lds = std::max(lds_bytes, sizeof(int) * (size_t)kFilterLdsWords);
-#define WG_FI(DT)                                                                                           \
-    (structured ? filter_input_launch<M, R, DT, true>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g)     \
-                : filter_input_launch<M, R, DT, false>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g))
-    switch (L.dtype) {
-        case WG_F32: WG_FI(kF32); break;
-        case WG_F16: WG_FI(kF16); break;
-        default: WG_FI(kBF16); break;
+#define WG_FI(DT)                                                                                               \
+    (structured ? filter_input_launch<M, R, DT, true, CT>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g)     \
+                : filter_input_launch<M, R, DT, false, CT>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g))
+    if constexpr (f64) {
+        WG_FI(kF32);
+    } else {
+        switch (L.dtype) {
+            case WG_F32: WG_FI(kF32); break;
+            case WG_F16: WG_FI(kF16); break;
+            default: WG_FI(kBF16); break;
+        }
     }
 #undef WG_FI
     return last_launch("filter_input_kernel");
 }
 
+template <int M, int R>
+static int input_dispatch(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
+                          const float* x_absmax) {
+    return p.f64t ? input_impl<M, R, double>(p, x, U, ws, s, w, x_absmax)
+                  : input_impl<M, R, float>(p, x, U, ws, s, w, x_absmax);
+}
+
 int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-#define WG_CASE_input(MM, RR) case MM * 16 + RR: return input_impl<MM, RR>(p, x, U, ws, s, nullptr, nullptr);
+#define WG_CASE_input(MM, RR) case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, nullptr, nullptr);
     WG_DISPATCH(input)
 #undef WG_CASE_input
 }
@@ -366,7 +402,7 @@ int launch_input_transform(const Plan& p, const float* x, const void* U, void* w
 int launch_filter_input(const Plan& p, const float* w, const float* x_absmax, const float* x, void* U, void* ws,
                         void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-#define WG_CASE_fi(MM, RR) case MM * 16 + RR: return input_impl<MM, RR>(p, x, U, ws, s, w, x_absmax);
+#define WG_CASE_fi(MM, RR) case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, w, x_absmax);
     WG_DISPATCH(fi)
 #undef WG_CASE_fi
 }

@@ -28,9 +28,10 @@ namespace wg {
 // ---------------------------------------------------------------------------
 constexpr int kOutThreads = 128;
 
-template <int M, int R>
+// CT: float, or double for the float64 transform (Y rounded to float32).
+template <int M, int R, typename CT>
 __global__ __launch_bounds__(256) void output_transform_kernel(const float* __restrict__ Mbuf,
-                                                               float* __restrict__ y, Mats<M, R> mt,
+                                                               float* __restrict__ y, Mats<M, R, CT> mt,
                                                                Geo g, int nb, unsigned plane_stride,
                                                                unsigned plane_bytes) {
     constexpr int A = M + R - 1;
@@ -55,24 +56,25 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
         // a*A .. a*A+A-1, read through a buffer resource on plane a*A with
         // the plane step as scalar offset and the tile's offset in a VGPR
         const unsigned voff = ((unsigned)k * g.P_pad + (unsigned)(band0 + bl) * g.Tw + tw) * 4u;
-        float z[M][A];
+        CT z[M][A];
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
-            for (int b = 0; b < A; ++b) z[i][b] = 0.0f;
+            for (int b = 0; b < A; ++b) z[i][b] = CT(0);
 #pragma unroll
         for (int a = 0; a < A; ++a) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<float*>(Mbuf) + (size_t)(a * A) * plane_stride, 0, (int)(A * plane_bytes), kBufferWord3);
-            float row[A];
+            CT row[A];
 #pragma unroll
             for (int b = 0; b < A; ++b)
-                row[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)(b * plane_bytes), 0));
+                row[b] = (CT)__uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)(b * plane_bytes), 0));
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                const float av = mt.AT[i][a];
+                const CT av = mt.AT[i][a];
 #pragma unroll
-                for (int b = 0; b < A; ++b) z[i][b] = __builtin_fmaf(av, row[b], z[i][b]);
+                for (int b = 0; b < A; ++b) z[i][b] = madd(av, row[b], z[i][b]);
             }
         }
         const int th = (band0 + bl) % g.Th;
@@ -82,19 +84,19 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
         // Y = Z A one column j at a time: Y[i][j] = sum_l Z[i][l] A^T[j][l]
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            float arow[A];
+            CT arow[A];
 #pragma unroll
             for (int l = 0; l < A; ++l) arow[l] = mt.AT[j][l];
-            float col[M];
+            CT col[M];
 #pragma unroll
-            for (int i = 0; i < M; ++i) col[i] = 0.0f;
+            for (int i = 0; i < M; ++i) col[i] = CT(0);
 #pragma unroll
             for (int l = 0; l < A; ++l)
 #pragma unroll
-                for (int i = 0; i < M; ++i) col[i] = __builtin_fmaf(arow[l], z[i][l], col[i]);
+                for (int i = 0; i < M; ++i) col[i] = madd(arow[l], z[i][l], col[i]);
 #pragma unroll
             for (int i = 0; i < M; ++i)
-                if (i < rows && j < cols) dst[i * g.Wout + j] = col[i];
+                if (i < rows && j < cols) dst[i * g.Wout + j] = (float)col[i];
         }
     }
     __syncthreads();
@@ -114,11 +116,11 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
     }
 }
 
-template <int M, int R>
+template <int M, int R, typename CT>
 static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
-    const Mats<M, R> mt = pack_mats<M, R>(p);
+    const Mats<M, R, CT> mt = pack_mats<M, R, CT>(p);
     const int nthr = kOutThreads;
     int nb = nthr / L.Tw;
     if (nb < 1) nb = 1;
@@ -134,14 +136,16 @@ static int output_impl(const Plan& p, const void* ws, float* y, hipStream_t s) {
     if (items > (1L << 30)) return fail(WG_EUNSUPPORTED, "output transform: grid too large");
     const dim3 grid((unsigned)((items + kXcdCount - 1) / kXcdCount * kXcdCount));
     const float* Mbuf = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.m_offset);
-    hipLaunchKernelGGL((output_transform_kernel<M, R>), grid, dim3(nthr), lds_bytes, s, Mbuf, y, mt, g, nb,
+    hipLaunchKernelGGL((output_transform_kernel<M, R, CT>), grid, dim3(nthr), lds_bytes, s, Mbuf, y, mt, g, nb,
                        (unsigned)plane_elems, (unsigned)(plane_elems * sizeof(float)));
     return last_launch("output_transform_kernel");
 }
 
 int launch_output_transform(const Plan& p, const void* ws, float* y, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-#define WG_CASE_output(MM, RR) case MM * 16 + RR: return output_impl<MM, RR>(p, ws, y, s);
+#define WG_CASE_output(MM, RR)                                                                  \
+    case MM * 16 + RR:                                                                          \
+        return p.f64t ? output_impl<MM, RR, double>(p, ws, y, s) : output_impl<MM, RR, float>(p, ws, y, s);
     WG_DISPATCH(output)
 #undef WG_CASE_output
 }

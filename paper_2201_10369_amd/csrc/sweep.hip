@@ -342,11 +342,6 @@ __device__ __forceinline__ void lds_vec(const double* p, double (&v)[N]) {
     }
 }
 
-// One term of an ascending-order inner product.  float: one fused
-// multiply-add.  double (the float64 transforms of the mixed-precision
-// evaluation): a rounded product, then a rounded sum.
-__device__ __forceinline__ float madd(float a, float b, float acc) { return __builtin_fmaf(a, b, acc); }
-__device__ __forceinline__ double madd(double a, double b, double acc) { return acc + a * b; }
 
 // One 2D tile: Y = A^T [(G g G^T) .* (B^T d B)] A against the float64
 // reference; `lds` is the staged candidate.  T is the type of the

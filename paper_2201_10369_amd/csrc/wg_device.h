@@ -7,17 +7,24 @@
 
 namespace wg {
 
-// The float32 matrices of one F(M x M, R x R) algorithm, passed by value as a
+// The matrices of one F(M x M, R x R) algorithm (float32, or float64 for
+// the float64 transforms of the mixed-precision layer), passed by value as a
 // kernel argument so that every entry is a wave-uniform scalar.
-template <int M_, int R_>
+template <int M_, int R_, typename E = float>
 struct Mats {
     static constexpr int M = M_;
     static constexpr int R = R_;
     static constexpr int A = M_ + R_ - 1;
-    float AT[M_][A];
-    float G[A][R_];
-    float BT[A][A];
+    E AT[M_][A];
+    E G[A][R_];
+    E BT[A][A];
 };
+
+// One term of an ascending-order inner product.  float: one fused
+// multiply-add.  double (float64 transforms): a rounded product, then a
+// rounded sum.
+__device__ __forceinline__ float madd(float a, float b, float acc) { return __builtin_fmaf(a, b, acc); }
+__device__ __forceinline__ double madd(double a, double b, double acc) { return acc + a * b; }
 
 // Returns v unchanged but held in a vector register the compiler cannot see
 // through.  Used for the stride between the planes of a transformed tensor:

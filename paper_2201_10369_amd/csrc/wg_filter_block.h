@@ -50,9 +50,10 @@ int launch_filter_absmax(const Plan& p, const FilterArgs& fa, hipStream_t s);
 constexpr int kFilterLdsWords = 2 * 64 + 2 * 128;
 
 // The block of channel group bx (128 channels) and filter k; sm: LDS
-// scratch of kFilterLdsWords words.
-template <int M, int R, int DT>
-__device__ __forceinline__ void filter_block(const FilterArgs& fa, const Mats<M, R>& mt, const RowExps& ex,
+// scratch of kFilterLdsWords words.  CT: float, or double for the float64
+// transforms (then DT is kF32 and each entry is rounded to float32).
+template <int M, int R, int DT, typename CT = float>
+__device__ __forceinline__ void filter_block(const FilterArgs& fa, const Mats<M, R, CT>& mt, const RowExps& ex,
                                              const Geo& g, int bx, int k, int* sm) {
     constexpr int A = M + R - 1;
     const float* __restrict__ w = fa.w;
@@ -66,14 +67,14 @@ __device__ __forceinline__ void filter_block(const FilterArgs& fa, const Mats<M,
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c = bx * 128 + 2 * lane;                    // channels c, c + 1
     // the filter taps first, so their loads overlap the exponent reduction
-    float g0[R][R], g1[R][R];
+    CT g0[R][R], g1[R][R];
     const bool live0 = k < g.K && c < g.C, live1 = k < g.K && c + 1 < g.C;
 #pragma unroll
     for (int u = 0; u < R; ++u)
 #pragma unroll
         for (int v = 0; v < R; ++v) {
-            g0[u][v] = live0 ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f;
-            g1[u][v] = live1 ? w[(((size_t)k * g.C + c + 1) * R + u) * R + v] : 0.0f;
+            g0[u][v] = (CT)(live0 ? w[(((size_t)k * g.C + c) * R + u) * R + v] : 0.0f);
+            g1[u][v] = (CT)(live1 ? w[(((size_t)k * g.C + c + 1) * R + u) * R + v] : 0.0f);
         }
     int tc0 = 0, tc1 = 0;
     if (DT != kF32) {
@@ -117,27 +118,28 @@ __device__ __forceinline__ void filter_block(const FilterArgs& fa, const Mats<M,
         if ((i & 3) != wv) continue;                  // uniform over the wave
         T* Up = U0 + (size_t)(i * A) * plane;          // plane e = i*A + j, one plane per entry
         // row i of P1 = G g for both channels
-        float p0[R], p1[R];
+        CT p0[R], p1[R];
 #pragma unroll
-        for (int v = 0; v < R; ++v) p0[v] = p1[v] = 0.0f;
+        for (int v = 0; v < R; ++v) p0[v] = p1[v] = CT(0);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-            const float b = mt.G[i][u];
+            const CT b = mt.G[i][u];
 #pragma unroll
             for (int v = 0; v < R; ++v) {
-                p0[v] = __builtin_fmaf(b, g0[u][v], p0[v]);
-                p1[v] = __builtin_fmaf(b, g1[u][v], p1[v]);
+                p0[v] = madd(b, g0[u][v], p0[v]);
+                p1[v] = madd(b, g1[u][v], p1[v]);
             }
         }
         const int si0 = tc0 + ex.dB[i], si1 = tc1 + ex.dB[i];
 #pragma unroll
         for (int j = 0; j < A; ++j) {
-            float a0 = 0.0f, a1 = 0.0f;
+            CT q0 = CT(0), q1 = CT(0);
 #pragma unroll
             for (int v = 0; v < R; ++v) {
-                a0 = __builtin_fmaf(mt.G[j][v], p0[v], a0);
-                a1 = __builtin_fmaf(mt.G[j][v], p1[v], a1);
+                q0 = madd(mt.G[j][v], p0[v], q0);
+                q1 = madd(mt.G[j][v], p1[v], q1);
             }
+            float a0 = (float)q0, a1 = (float)q1;
             if (DT != kF32) {                       // padded channels hold zeros
                 a0 = ldexpf(a0, floor_half(si0 + ex.dB[j]));
                 a1 = ldexpf(a1, floor_half(si1 + ex.dB[j]));

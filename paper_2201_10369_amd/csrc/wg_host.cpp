@@ -143,9 +143,13 @@ int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, in
         return fail(WG_EINVAL, "wg_plan_create: padding must be WG_SAME or WG_VALID");
     if (dtype != WG_F32 && dtype != WG_F16 && dtype != WG_BF16)
         return fail(WG_EINVAL, "wg_plan_create: dtype must be WG_F32, WG_F16 or WG_BF16");
-    if (flags != WG_MODIFIED)
-        return fail(flags == WG_UNMODIFIED ? WG_EUNSUPPORTED : WG_EINVAL,
-                    "wg_plan_create: the layer implements the modified form (WG_MODIFIED) only");
+    if ((flags & ~(WG_UNMODIFIED | WG_F64_TRANSFORMS)) != 0)
+        return fail(WG_EINVAL, "wg_plan_create: unknown flags");
+    if (flags & WG_UNMODIFIED)
+        return fail(WG_EUNSUPPORTED, "wg_plan_create: the layer implements the modified form (WG_MODIFIED) only");
+    const bool f64t = (flags & WG_F64_TRANSFORMS) != 0;
+    if (f64t && dtype != WG_F32)
+        return fail(WG_EINVAL, "wg_plan_create: WG_F64_TRANSFORMS needs dtype WG_F32");
     if (!wg_supported(m, r))
         return fail(WG_EUNSUPPORTED, "wg_plan_create: F(" + std::to_string(m) + "," +
                                          std::to_string(r) + ") is not implemented");
@@ -164,11 +168,13 @@ int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, in
     Plan* plan = new (std::nothrow) Plan();
     if (!plan) return fail(WG_ENOMEM, "wg_plan_create: out of host memory");
     const int alpha = m + r - 1;
-    int st = wg_transforms_f32(m, r, pts, n_pts, flags, plan->AT, plan->G, plan->BT);
+    int st = wg_transforms_f32(m, r, pts, n_pts, WG_MODIFIED, plan->AT, plan->G, plan->BT);
+    if (st == WG_OK) st = wg_transforms(m, r, pts, n_pts, WG_MODIFIED, plan->AT64, plan->G64, plan->BT64);
     if (st != WG_OK) {
         delete plan;
         return st;
     }
+    plan->f64t = f64t;
     for (int i = 0; i < alpha; ++i) {
         double nb = 0.0, ng = 0.0;
         for (int l = 0; l < alpha; ++l) nb += std::fabs((double)plan->BT[i * alpha + l]);

@@ -22,6 +22,11 @@ struct Plan {
     float AT[kMaxAlpha * kMaxAlpha];   // m x alpha
     float G[kMaxAlpha * kMaxAlpha];    // alpha x r
     float BT[kMaxAlpha * kMaxAlpha];   // alpha x alpha
+    // the same rounded to float64 (the float64 transforms of WG_F64_TRANSFORMS)
+    double AT64[kMaxAlpha * kMaxAlpha];
+    double G64[kMaxAlpha * kMaxAlpha];
+    double BT64[kMaxAlpha * kMaxAlpha];
+    bool f64t;                         // float64 transforms, float32 Hadamard stage
     // binary exponents of the float64 row L1 norms of B^T and G
     int eB[kMaxAlpha];
     int eG[kMaxAlpha];

@@ -47,16 +47,17 @@ __device__ __forceinline__ int floor_half(int d) { return d >> 1; }
 // ---------------------------------------------------------------------------
 // Host-side packing and launch helpers
 // ---------------------------------------------------------------------------
-template <int M, int R>
-inline Mats<M, R> pack_mats(const Plan& p) {
+template <int M, int R, typename E = float>
+inline Mats<M, R, E> pack_mats(const Plan& p) {
     constexpr int A = M + R - 1;
-    Mats<M, R> mt;
+    constexpr bool d = sizeof(E) == 8;
+    Mats<M, R, E> mt;
     for (int i = 0; i < M; ++i)
-        for (int j = 0; j < A; ++j) mt.AT[i][j] = p.AT[i * A + j];
+        for (int j = 0; j < A; ++j) mt.AT[i][j] = d ? (E)p.AT64[i * A + j] : (E)p.AT[i * A + j];
     for (int i = 0; i < A; ++i)
-        for (int j = 0; j < R; ++j) mt.G[i][j] = p.G[i * R + j];
+        for (int j = 0; j < R; ++j) mt.G[i][j] = d ? (E)p.G64[i * R + j] : (E)p.G[i * R + j];
     for (int i = 0; i < A; ++i)
-        for (int j = 0; j < A; ++j) mt.BT[i][j] = p.BT[i * A + j];
+        for (int j = 0; j < A; ++j) mt.BT[i][j] = d ? (E)p.BT64[i * A + j] : (E)p.BT[i * A + j];
     return mt;
 }
 

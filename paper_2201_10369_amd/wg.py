@@ -18,7 +18,10 @@ LIB_PATH = os.path.join(_HERE, "libwg.so")
 WG_MODIFIED, WG_UNMODIFIED = 0, 1
 WG_SAME, WG_VALID = 0, 1
 WG_F32, WG_F16, WG_BF16 = 0, 1, 2
-DTYPES = {"f32": WG_F32, "f16": WG_F16, "bf16": WG_BF16}
+WG_F64_TRANSFORMS = 4
+# "mixed": float64 transforms with a float32 Hadamard stage (WG_F32 plan
+# with WG_F64_TRANSFORMS)
+DTYPES = {"f32": WG_F32, "f16": WG_F16, "bf16": WG_BF16, "mixed": WG_F32}
 PADDINGS = {"same": WG_SAME, "valid": WG_VALID}
 STATUS = {0: "WG_OK", -1: "WG_EINVAL", -2: "WG_ESINGULAR", -3: "WG_EUNSUPPORTED",
           -4: "WG_EWORKSPACE", -5: "WG_ENOMEM", -6: "WG_EHIP"}
@@ -192,7 +195,8 @@ class Plan:
     def __init__(self, m, r, pts, N, C, K, H, W, padding="same", dtype="f32"):
         pts = np.ascontiguousarray(pts, dtype=np.float64)
         h = c_void_p()
-        _check(lib().wg_plan_create(ctypes.byref(h), m, r, _dptr(pts), len(pts), WG_MODIFIED,
+        flags = WG_MODIFIED | (WG_F64_TRANSFORMS if dtype == "mixed" else 0)
+        _check(lib().wg_plan_create(ctypes.byref(h), m, r, _dptr(pts), len(pts), flags,
                                     N, C, K, H, W, PADDINGS[padding], DTYPES[dtype]))
         self._h = h
         self.m, self.r, self.dtype, self.padding = m, r, dtype, padding
@@ -315,7 +319,7 @@ class Plan:
     # -- views of the buffers (for tests) --------------------------------------
     def _elem_dtype(self):
         torch = _torch()
-        return {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[self.dtype]
+        return {"f32": torch.float32, "mixed": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[self.dtype]
 
     def view_U(self, U):
         L = self.layout
