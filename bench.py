@@ -56,29 +56,31 @@ def algorithmic_bytes(L, dtype):
     return {"filter_maxima": w, "filter_input": w + U + x + V, "gemm": V + U + M, "output": M + y}
 
 
-def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup, m=6):
+def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup, m=6, r=3):
     N, C, K, H, W = (L0[k] for k in ("N", "C", "K", "H", "W"))
-    plan = wg.Plan(m, 3, pts, N, C, K, H, W, "same", dtype)
+    plan = wg.Plan(m, r, pts, N, C, K, H, W, "same", dtype)
     ax = wg.channel_absmax(x) if dtype in ("f16", "bf16") else None
     U = plan.empty_filters()
     ws = plan.empty_workspace()
     y = plan.empty_output()
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        plan.filter_maxima(w, U)
-        if ev:
-            ev[1].record(stream)
-        plan.transform_filters_and_input(w, x, U, ws, ax)
-        if ev:
-            ev[2].record(stream)
-        plan.hadamard_gemm(U, ws)
-        if ev:
-            ev[3].record(stream)
-        plan.output_transform(ws, y)
-        if ev:
+    names = ["filter_maxima", "filter_input", "gemm", "output"]
+    calls = [lambda: plan.filter_maxima(w, U),
+             lambda: plan.transform_filters_and_input(w, x, U, ws, ax),
+             lambda: plan.hadamard_gemm(U, ws),
+             lambda: plan.output_transform(ws, y)]
+
+    def step(ev=None, around=None):
+        """One step; ev: events recorded between all stages (len 5), or the
+        two events around stage index `around` only."""
+        for j, call in enumerate(calls):
+            if ev is not None and (around is None or j == around):
+                ev[0 if around is not None else j].record(stream)
+            call()
+            if ev is not None and around == j:
+                ev[1].record(stream)
+        if ev is not None and around is None:
             ev[4].record(stream)
 
     # untimed: one step to fill U and V', then the GEMM autotuner
@@ -86,16 +88,25 @@ def run_form(wg, torch, dtype, x, w, pts, L0, steps, warmup, m=6):
     plan.autotune_gemm(U, ws, reps=10)
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
-    t0 = time.perf_counter()
-    for i in range(steps):
+    # untimed: the stage breakdown, events between every stage
+    diag = max(10, min(steps, 50))
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(diag)]
+    for i in range(diag):
         step(evs[i])
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    names = ["filter_maxima", "filter_input", "gemm", "output"]
-    stage_ms = {n: float(np.mean([evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(steps)]))
+    stage_ms = {n: float(np.mean([evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(diag)]))
                 for j, n in enumerate(names)}
+    dom = max(range(len(names)), key=lambda j: stage_ms[names[j]])
+    # timed: K steps with two events around the slowest stage only (each
+    # event adds a few microseconds between launches)
+    evd = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evd[i], around=dom)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms["live_" + names[dom]] = float(np.mean([e[0].elapsed_time(e[1]) for e in evd]))
     return plan, U, y, elapsed / steps * 1e3, stage_ms
 
 
@@ -164,26 +175,32 @@ def bench_sweep(wg, torch, reps=5):
 
 
 def bench_other_layers(wg, torch, curve_c, steps=50, warmup=5):
-    """The float32 layers of the smaller configurations: F(2x2,3x3) with
-    {0, 1, -1, inf} (N=1, C=K=16, 32x32, uniform data) and F(4x4,3x3) with
-    {0, inf, +-c, +-1/c} at c = 2 and at the error curve's best c (N=32,
-    C=K=256, 56x56), each timed as the bench step and scored against the
-    float64 direct convolution."""
+    """The other layer configurations, each timed as the bench step and
+    scored against the float64 direct convolution: float32 F(2x2,3x3) with
+    {0, 1, -1, inf} (N=1, C=K=16, 32x32, uniform data); float32 F(4x4,3x3)
+    with {0, inf, +-c, +-1/c} at c = 2 and at the error curve's best c
+    (N=32, C=K=256, 56x56); F(4x4,5x5) with the 8-point family at c = 2
+    (N=64, C=K=256, 28x28), fp16 and float32."""
     res = {}
-    for name, m, cs in (("f2x2_n1_c16_k16_32x32", 2, [None]), ("f4x4_n32_c256_k256_56x56", 4, [2.0, curve_c])):
+    runs = (("f2x2_n1_c16_k16_32x32", [(None, "f32")]),
+            ("f4x4_n32_c256_k256_56x56", [(2.0, "f32"), (curve_c, "f32")]),
+            ("f4x4r5_n64_c256_k256_28x28", [(2.0, "f16"), (2.0, "f32")]))
+    for name, cases in runs:
         cfg = synth.LAYERS[name]
-        N, C, K, H, W, r = (cfg[k] for k in ("N", "C", "K", "H", "W", "r"))
+        N, C, K, H, W, r, m = (cfg[k] for k in ("N", "C", "K", "H", "W", "r", "m"))
         xh, wh = synth.layer_inputs(N, C, K, H, W, r, cfg["dist"])
         x, w = torch.from_numpy(xh).cuda(), torch.from_numpy(wh).cuda()
         y64 = wg.direct_conv_f64(x, w, "same")
         flops = 2.0 * N * K * C * H * W * r * r
-        for c in cs:
-            pts = np.array([0.0, 1.0, -1.0]) if c is None else wg.family_points(6, c)
-            plan, U, y, ms, stage_ms = run_form(wg, torch, "f32", x, w, pts, dict(N=N, C=C, K=K, H=H, W=W),
-                                                steps, warmup, m=m)
+        for c, dtype in cases:
+            alpha = m + r - 1
+            pts = np.array([0.0, 1.0, -1.0]) if c is None else wg.family_points(alpha, c, 1.0)
+            plan, U, y, ms, stage_ms = run_form(wg, torch, dtype, x, w, pts, dict(N=N, C=C, K=K, H=H, W=W),
+                                                steps, warmup, m=m, r=r)
             sc = wg.score_error(y, y64).cpu().numpy()
-            key = name if c is None else f"{name}_c{c:.4g}"
-            res[key] = {"dtype": "f32", "points": "0,1,-1,inf" if c is None else f"0,inf,+-{c:.4g},+-1/{c:.4g}",
+            key = name if c is None else f"{name}_c{c:.4g}_{dtype}"
+            res[key] = {"dtype": dtype, "points": "0,1,-1,inf" if c is None else
+                        ",".join(f"{v:.4g}" for v in pts) + ",inf",
                         "ms_per_step": round(ms, 5), "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 2),
                         "rel_l1": float(sc[0] / sc[1]), "mean_abs": float(sc[0] / y.numel()),
                         "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()}}
@@ -347,13 +364,15 @@ def main():
 
     L = forms["f16"]["plan"].layout
     ab = algorithmic_bytes(L, "f16")
-    st = forms["f16"]["stage_ms"]
-    dom = max(st, key=st.get)
+    st = {k: v for k, v in forms["f16"]["stage_ms"].items() if not k.startswith("live_")}
+    live = [k for k in forms["f16"]["stage_ms"] if k.startswith("live_")][0]
+    dom = live[len("live_"):]
+    live_ms = forms["f16"]["stage_ms"][live]
     gemm_flops = 2.0 * L["alpha"] ** 2 * K * C * L["P"]
-    achieved_gbs = ab[dom] / (st[dom] * 1e-3) / 1e9
+    achieved_gbs = ab[dom] / (live_ms * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes": ab[dom], "traffic": traffic_for(dom)}
+                "algorithmic_bytes": ab[dom], "launch_ms": round(live_ms, 5), "traffic": traffic_for(dom)}
 
     f16 = forms["f16"]
     value = flops / (f16["ms"] * 1e-3) / 1e12

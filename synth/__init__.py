@@ -32,6 +32,9 @@ LAYERS = {
     # F(6x6,3x3), points {0,inf,+-1,+-c,+-1/c}
     "f6x6_n64_c256_k256_28x28": dict(N=64, C=256, K=256, H=28, W=28, r=3, m=6,
                                      padding="same", dist="normal"),
+    # F(4x4,5x5), the same 8-point family, 5x5 filters
+    "f4x4r5_n64_c256_k256_28x28": dict(N=64, C=256, K=256, H=28, W=28, r=5, m=4,
+                                       padding="same", dist="normal"),
 }
 
 

@@ -338,6 +338,8 @@ FULL = [
     ("f6x6_n64_c256_k256_28x28", (8, 2.0, 1.0), "f16"),
     ("f6x6_n64_c256_k256_28x28", (8, 2.0, 1.0), "bf16"),
     ("f6x6_n64_c256_k256_28x28", (8, 2.0, 1.0), "mixed"),
+    ("f4x4r5_n64_c256_k256_28x28", (8, 2.0, 1.0), "f16"),
+    ("f4x4r5_n64_c256_k256_28x28", (8, 2.0, 1.0), "f32"),
 ]
 
 
