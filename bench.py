@@ -335,7 +335,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the layer would shard along N or K with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(the layer would shard along N or K with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
 

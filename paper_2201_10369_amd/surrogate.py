@@ -4,7 +4,7 @@ The paper finds good points by sweeping the error curve over c, which it
 observes to be smooth (arXiv:2201.10369, Sections 1 and 6.1).  Here a small
 network trained on sweep results predicts the log10 mean absolute error of a
 family (c1, c2) for a tile size F(m, r); its best predictions are re-scored
-by the exact sweep, which stays the judge.
+by the exact sweep, which has the final word.
 
 Everything numeric runs in the HIP library: the sweep (wg_sweep_*), training
 (wg_mlp_train), inference (wg_mlp_predict) and selection (wg_topk_min).  This
