@@ -253,7 +253,23 @@ def bench_surrogate(torch):
     used += 64
     rng = np.random.default_rng(12)
     rand = sg.score(S, grid[rng.choice(4096, used, replace=False)], np.ones(used), np.full(used, sg.POOL))
+    # the two-parameter families of F(7x7,3x3) and F(8x8,3x3) (trained on):
+    # proposals from a 128 x 128 log grid, refined in c and d, against the
+    # grid-and-refine search of the same sweep
+    from paper_2201_10369_amd import search
+    g2 = search.log_grid(0.05, 20.0, 128)
+    G1, G2 = np.meshgrid(g2, g2, indexing="ij")
+    two = {}
+    for mm in (7, 8):
+        S2 = sg.sweep_for(mm, 3, dims=2, max_cand=4096)
+        e2, c2a, c2b, u2 = sg.guided_search(model, S2, mm, 3, G1.ravel(), G2.ravel(), refine_c2=True)
+        ref = search.two_param_search(S2)
+        two[f"F({mm}x{mm},3x3)"] = {"surrogate_best": float(e2), "c": float(c2a), "d": float(c2b),
+                                    "evaluations": int(u2), "grid_best": ref["mean_abs"],
+                                    "grid_evaluations": ref["evaluations"],
+                                    "ratio": round(float(e2) / ref["mean_abs"], 4)}
     return {"held_out": "F(4x4,3x3) 2D", "train_samples": len(both["c1"]),
+            "two_param": two,
             "data_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
             "final_loss": float(losses[-20:].mean().item()),
             "surrogate_best": float(err), "surrogate_c": float(c1), "evaluations": int(used),

@@ -112,10 +112,11 @@ def propose(model, m, r, grid_c1, grid_c2, k=32):
 
 
 def guided_search(model, S, m, r, grid_c1, grid_c2, k=32, refine=32, spans=(0.25, 0.05, 0.01),
-                  n_eval=POOL):
+                  n_eval=POOL, refine_c2=False):
     """Re-score the k best proposals exactly, then refine: for each span,
     `refine` log-spaced values of c1 within a factor (1 +- span) of the best
-    so far (the error curve is smooth, Section 6.1).
+    so far (the error curve is smooth, Section 6.1), and with refine_c2 the
+    same for c2 (the two-parameter families).
     Returns (best error, best c1, best c2, exact evaluations used)."""
     idx = propose(model, m, r, grid_c1, grid_c2, k)
     idx = idx[idx >= 0]
@@ -125,11 +126,13 @@ def guided_search(model, S, m, r, grid_c1, grid_c2, k=32, refine=32, spans=(0.25
     best = (errs[b], c1[b], c2[b])
     used = len(idx)
     for span in (spans if refine else ()):
-        rc1 = best[1] * np.exp(np.linspace(np.log(1 - span), np.log(1 + span), refine))
-        rc2 = np.full(refine, best[2])
-        rerr = score(S, rc1, rc2, np.full(refine, n_eval))
-        j = int(np.argmin(rerr))
-        if rerr[j] < best[0]:
-            best = (rerr[j], rc1[j], rc2[j])
-        used += refine
+        for axis in ((0, 1) if refine_c2 else (0,)):
+            f = np.exp(np.linspace(np.log(1 - span), np.log(1 + span), refine))
+            rc1 = best[1] * f if axis == 0 else np.full(refine, best[1])
+            rc2 = best[2] * f if axis == 1 else np.full(refine, best[2])
+            rerr = score(S, rc1, rc2, np.full(refine, n_eval))
+            j = int(np.argmin(rerr))
+            if rerr[j] < best[0]:
+                best = (rerr[j], rc1[j], rc2[j])
+            used += refine
     return best[0], best[1], best[2], used
