@@ -12,7 +12,7 @@
 //   construct : one thread per (candidate, matrix row), float64
 //               construction -> float32
 //   evaluate  : persistent blocks stride over work items (candidate, chunk
-//               of `chunk` samples); per item a fixed-tree block reduction
+//               of `chunk` samples); per item a fixed-order block reduction
 //               writes one float64 partial sum
 //   finalize  : one thread per candidate adds its partials in index order
 // so the result is bitwise reproducible for a given tuning.
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
     // result and made the compiler spill them)
     using Z = typename std::conditional<FAM && sizeof(T) == 4, FamilyZeros<M, R>, AllTerms<M, R>>::type;
     __shared__ __align__(16) T sm[L::kSize];
-    __shared__ double red[256];
+    __shared__ double red[4];                          // one sum per wave
     const int tid = threadIdx.x, nthr = blockDim.x;
     const long items = (long)n_cand * ipc;
     for (long item = blockIdx.x; item < items; item += gridDim.x) {
@@ -594,13 +594,17 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
                 err += tile_error_2d<M, R, Z, T>(d_soa, g_soa, yref, s, n_pool, sm + z0);
             }
         }
-        red[tid] = err;
+        // fixed-order reduction: a butterfly inside each wave, then the wave
+        // sums in wave order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = err;
         __syncthreads();
-        for (int st = nthr / 2; st > 0; st >>= 1) {
-            if (tid < st) red[tid] += red[tid + st];
-            __syncthreads();
+        if (tid == 0) {
+            double tot = red[0];
+            for (int wv = 1; wv < nthr / 64; ++wv) tot += red[wv];
+            partial[item] = tot;
         }
-        if (tid == 0) partial[item] = red[0];
     }
 }
 
