@@ -23,7 +23,8 @@ namespace wg {
 // threads at consecutive tiles of each plane) and leaves its in-range
 // outputs in LDS laid out exactly like the image rows (pitch Wout); the rows
 // of consecutive bands of one image are contiguous in y, so the block then
-// copies each image's run with consecutive threads.  Zero entries of A^T are
+// copies each image's run with consecutive threads (16-byte copies when the
+// run and its ends are aligned).  Zero entries of A^T are
 // not skipped (fma(0, x, acc) == acc for finite x).
 // ---------------------------------------------------------------------------
 constexpr int kOutThreads = 128;
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
                                                                Geo g, int nb, unsigned plane_stride,
                                                                unsigned plane_bytes) {
     constexpr int A = M + R - 1;
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int tid = threadIdx.x;
     // XCD-aware mapping: each XCD runs a contiguous range of (band group, k)
     // work items, so the partial 128-byte lines of M that neighbouring band
@@ -109,9 +110,16 @@ __global__ __launch_bounds__(256) void output_transform_kernel(const float* __re
         const int row_first = th * M;
         const int row_end = min(g.Hout, (th + (last - bl)) * M);
         const int len = (row_end - row_first) * g.Wout;
-        const float* src = lds + bl * M * g.Wout;
+        const int src_off = bl * M * g.Wout;
+        const float* src = lds + src_off;
         float* dst = y + (((size_t)n * g.K + k) * g.Hout + row_first) * g.Wout;
-        for (int q = tid; q < len; q += nthr) dst[q] = src[q];
+        if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0 && (src_off & 3) == 0 && (len & 3) == 0) {
+            // 16-byte copies where the run and both ends allow them
+            for (int q = tid; q < (len >> 2); q += nthr)
+                reinterpret_cast<float4*>(dst)[q] = reinterpret_cast<const float4*>(src)[q];
+        } else {
+            for (int q = tid; q < len; q += nthr) dst[q] = src[q];
+        }
         bl = last;
     }
 }
