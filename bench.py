@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-tiles", type=int, default=1200)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate search")
+    ap.add_argument("--layer-only", action="store_true",
+                    help="only the F(6x6,3x3) layer forms (no sweeps, searches, other layers or surrogate): "
+                         "the profiling runs, whose per-kernel summaries would otherwise mix layers")
     return ap.parse_args()
 
 
@@ -409,11 +412,12 @@ def main():
                       "rel_l1": f["rel_l1"], "mean_abs": f["mean_abs"],
                       "gemm_tiles_per_block": f["plan"].gemm_tiles} for d, f in forms.items()},
     }
-    out["sweep"] = bench_sweep(wg, torch)
-    out["error_curve_f43"] = bench_error_curve(wg, torch)
-    out["other_layers"] = bench_other_layers(wg, torch, out["error_curve_f43"]["f32_2d"]["best_c"])
-    out["two_param"] = bench_two_param(torch)
-    if not args.no_surrogate:
+    if not args.layer_only:
+        out["sweep"] = bench_sweep(wg, torch)
+        out["error_curve_f43"] = bench_error_curve(wg, torch)
+        out["other_layers"] = bench_other_layers(wg, torch, out["error_curve_f43"]["f32_2d"]["best_c"])
+        out["two_param"] = bench_two_param(torch)
+    if not args.no_surrogate and not args.layer_only:
         out["surrogate"] = bench_surrogate(torch)
     if not args.no_cpu:
         ntiles = min(args.cpu_tiles, L["P"])

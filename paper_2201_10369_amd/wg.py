@@ -109,6 +109,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2201_10369_amd.build")
+        # torch first: its HIP runtime is the one the process uses, so the
+        # library's launches and torch's memory and streams share a runtime
+        # (loading the library first would bring in a second one)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             if hasattr(L, name):
