@@ -243,22 +243,37 @@ __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __re
     }
 }
 
-// Sum of the block partials (block order) -> Adam update or plain gradient.
+// Sum of the block partials -> Adam update or plain gradient.  A block takes
+// kRedParams parameters; its kRedGroups thread groups each add every
+// kRedGroups-th partial (group g: partials g, g + kRedGroups, ...), and the
+// group sums are added in group order, so the result is fixed for a given
+// number of partials.
+constexpr int kRedParams = 64;
+constexpr int kRedGroups = 256 / kRedParams;
+
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ part, int nblk,
                                                          float* __restrict__ P, float* __restrict__ adam,
                                                          float* __restrict__ grad_out, float lr, float b1, float b2,
                                                          float eps, float bc1, float bc2,
                                                          const float* __restrict__ part_loss, float inv_batch,
                                                          float* __restrict__ loss_out) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p == 0 && loss_out) {
+    __shared__ float gs[kRedGroups][kRedParams];
+    const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
+    const int p = blockIdx.x * kRedParams + pl;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
         float l = 0.0f;
         for (int b = 0; b < nblk; ++b) l += part_loss[b];
         *loss_out = l * inv_batch;
     }
-    if (p >= kParams) return;
-    float gsum = 0.0f;
-    for (int b = 0; b < nblk; ++b) gsum += part[(size_t)b * kParams + p];
+    float acc = 0.0f;
+    if (p < kParams)
+        for (int b = grp; b < nblk; b += kRedGroups) acc += part[(size_t)b * kParams + p];
+    gs[grp][pl] = acc;
+    __syncthreads();
+    if (grp != 0 || p >= kParams) return;
+    float gsum = gs[0][pl];
+#pragma unroll
+    for (int g = 1; g < kRedGroups; ++g) gsum += gs[g][pl];
     if (grad_out) {
         grad_out[p] = gsum;
         return;
@@ -378,7 +393,8 @@ int wg_mlp_gradient(wg_mlp* mlp, const float* params, const double* c1, const do
     st = launch_step(M, params, d, 1, nullptr, s);
     if (st != WG_OK) return st;
     const int nblk = (n + kS - 1) / kS;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, M.part, nblk, nullptr,
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, M.part,
+                       nblk, nullptr,
                        nullptr, grad_out, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f, M.part_loss, 1.0f / n, loss_out);
     return hip_check((int)hipGetLastError(), "mlp_reduce_kernel");
 }
@@ -403,7 +419,8 @@ int wg_mlp_train(wg_mlp* mlp, float* params, float* adam_state, int step0, float
             st = launch_step(M, params, d, 1, nullptr, s);
             if (st != WG_OK) return st;
             const float bc1 = 1.0f - powf(b1, (float)t), bc2 = 1.0f - powf(b2, (float)t);
-            hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, M.part,
+            hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s,
+                               M.part,
                                (batch + kS - 1) / kS, params, adam_state, nullptr, lr, b1, b2, eps, bc1, bc2,
                                M.part_loss, 1.0f / batch, losses + (size_t)e * steps + b);
             st = hip_check((int)hipGetLastError(), "mlp_reduce_kernel");
