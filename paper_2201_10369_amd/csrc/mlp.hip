@@ -9,8 +9,9 @@
 //   fwd_bwd : a block takes 16 samples, runs the forward pass with all
 //             activations in LDS and, for training, the backward pass, and
 //             writes its partial gradient (one full parameter vector)
-//   reduce  : one thread per parameter adds the block partials in block order
-//             and applies Adam (or writes the gradient)
+//   reduce  : per parameter, four thread groups add interleaved block
+//             partials, the group sums are added in order, then Adam (or
+//             the gradient is written)
 //   predict : forward pass only
 //   topk    : the k smallest values of a vector (ties -> smaller index)
 #include <hip/hip_runtime.h>
