@@ -311,6 +311,32 @@ def bench_two_param(torch):
     return res
 
 
+def bench_base_subsets(torch):
+    """Section 6.2: for F(2,3), F(3,3) and F(4,3), 1D and 2D, each base-point
+    set with the best subset of {-1/c, -c, c, 1/c} (512 values of c in
+    (1, 4], 2000 samples): the winning subset, its c and error per base."""
+    from paper_2201_10369_amd import search
+    from paper_2201_10369_amd import surrogate as sg
+    cs = search.log_grid(1.001, 4.0, 512)
+    res = {}
+    t0 = time.perf_counter()
+    for m in (2, 3, 4):
+        for dims in (1, 2):
+            S = sg.sweep_for(m, 3, dims=dims, max_cand=4096)
+            rows = {}
+            for base in ([], [0.5], [3.0], [-3.0], [1.0], [-1.0], [1.0, -1.0]):
+                try:
+                    best = search.subset_search(S, base, cs)[0]
+                except ValueError:
+                    continue
+                rows["{" + ",".join(f"{b:g}" for b in [0.0] + base) + ",inf}"] = {
+                    "subset": best["subset"], "c": round(best["c"], 4), "mean_abs": best["mean_abs"]}
+            res[f"F({m},3)_{dims}d"] = rows
+    torch.cuda.synchronize()
+    res["s"] = round(time.perf_counter() - t0, 3)
+    return res
+
+
 def traffic_for(kernel_key):
     """HBM bytes per launch of a kernel from the committed counter summary, or
     None when the kernel's source changed since the counters were taken."""
@@ -417,6 +443,7 @@ def main():
         out["error_curve_f43"] = bench_error_curve(wg, torch)
         out["other_layers"] = bench_other_layers(wg, torch, out["error_curve_f43"]["f32_2d"]["best_c"])
         out["two_param"] = bench_two_param(torch)
+        out["base_subsets"] = bench_base_subsets(torch)
     if not args.no_surrogate and not args.layer_only:
         out["surrogate"] = bench_surrogate(torch)
     if not args.no_cpu:
