@@ -97,18 +97,27 @@ __device__ __forceinline__ void backprop_hidden(float (*DZ)[kH], float (*DH)[kH]
                                                 float* __restrict__ gW, float* __restrict__ gb) {
     const int tid = threadIdx.x;
     {
-        const int j = tid >> 1, i0 = (tid & 1) * 64;
+        // thread: column i of dW for 64 rows j (consecutive lanes hold
+        // consecutive i, so each row of dW is written with whole-wave stores)
+        const int i = tid & (kH - 1), j0 = (tid >> 7) * 64;
         float acc[64];
 #pragma unroll
         for (int u = 0; u < 64; ++u) acc[u] = 0.0f;
         for (int s = 0; s < kS; ++s) {
-            const float dz = DZ[s][j];
+            const float h = Hin[s][i];
+            const float4* dz4 = reinterpret_cast<const float4*>(&DZ[s][j0]);
 #pragma unroll
-            for (int u = 0; u < 64; ++u) acc[u] = fmaf(dz, Hin[s][i0 + u], acc[u]);
+            for (int u4 = 0; u4 < 16; ++u4) {
+                const float4 dz = dz4[u4];
+                acc[4 * u4 + 0] = fmaf(dz.x, h, acc[4 * u4 + 0]);
+                acc[4 * u4 + 1] = fmaf(dz.y, h, acc[4 * u4 + 1]);
+                acc[4 * u4 + 2] = fmaf(dz.z, h, acc[4 * u4 + 2]);
+                acc[4 * u4 + 3] = fmaf(dz.w, h, acc[4 * u4 + 3]);
+            }
         }
-        float* gw = gW + (size_t)j * kH + i0;
+        float* gw = gW + (size_t)j0 * kH + i;
 #pragma unroll
-        for (int u = 0; u < 64; ++u) gw[u] = acc[u];
+        for (int u = 0; u < 64; ++u) gw[(size_t)u * kH] = acc[u];
     }
     if (tid < kH) {
         float a = 0.0f;
