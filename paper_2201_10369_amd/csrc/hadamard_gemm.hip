@@ -38,11 +38,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-constexpr int kXcds = 8;
-// Word 3 of a raw buffer resource on gfx9-family chips (dword data format,
-// no swizzle); out-of-range loads read zero and out-of-range stores are
-// dropped by the hardware.
-constexpr int kBufferWord3 = 0x00020000;
 
 constexpr int kStepBytes = 64;        // bytes of each operand row per pipeline step
 constexpr int kStages = 3;            // LDS ring depth (48 KB: three blocks per CU)
@@ -150,7 +145,7 @@ __global__ __launch_bounds__(256) void hadamard_gemm_kernel(const char* __restri
     // that range, so the blocks running together on one XCD always work on
     // neighbouring tiles (same e, shared operand rows in its L2)
     const int b = blockIdx.x;
-    const int xcd = b % kXcds, slot = b / kXcds;
+    const int xcd = b % kXcdCount, slot = b / kXcdCount;
     const int lo = xcd * tiles_per_xcd, hi = min(total, lo + tiles_per_xcd);
     const int t0 = lo + slot;
     if (t0 >= hi) return;
@@ -267,11 +262,11 @@ static int gemm_launch(const Plan& p, const void* U, void* ws, hipStream_t s) {
         (long)BM * L.C_pad * 4 >= (1L << 31))
         return fail(WG_EUNSUPPORTED, "hadamard gemm: tile rows too long");
     const int tpb = p.gemm_tpb > 0 ? p.gemm_tpb : 1;
-    const int tiles_per_xcd = (int)((total + kXcds - 1) / kXcds);
+    const int tiles_per_xcd = (int)((total + kXcdCount - 1) / kXcdCount);
     const int blocks_per_xcd = (tiles_per_xcd + tpb - 1) / tpb;
     const char* V = static_cast<const char*>(ws) + L.v_offset;
     float* Mb = reinterpret_cast<float*>(static_cast<char*>(ws) + L.m_offset);
-    hipLaunchKernelGGL((hadamard_gemm_kernel<BM, BN, DT>), dim3((unsigned)(blocks_per_xcd * kXcds)), dim3(256), 0, s,
+    hipLaunchKernelGGL((hadamard_gemm_kernel<BM, BN, DT>), dim3((unsigned)(blocks_per_xcd * kXcdCount)), dim3(256), 0, s,
                        static_cast<const char*>(U), V, Mb, L.K, L.K_pad, L.P, L.P_pad, L.C_pad, nKb, nPb, (int)total,
                        tiles_per_xcd, blocks_per_xcd);
     return hip_check((int)hipGetLastError(), "hadamard_gemm_kernel");

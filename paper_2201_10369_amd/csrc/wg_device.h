@@ -7,6 +7,12 @@
 
 namespace wg {
 
+constexpr int kXcdCount = 8;     // XCDs of the chip, each with its own L2
+// Word 3 of a raw buffer resource on gfx9-family chips (dword data format,
+// no swizzle); accesses outside the resource's range are dropped (stores)
+// or read as zero (loads).
+constexpr int kBufferWord3 = 0x00020000;
+
 // The matrices of one F(M x M, R x R) algorithm (float32, or float64 for
 // the float64 transforms of the mixed-precision layer), passed by value as a
 // kernel argument so that every entry is a wave-uniform scalar.
@@ -39,19 +45,6 @@ __device__ __forceinline__ int in_vgpr(int v) {
     return v;
 }
 
-// Round-to-nearest-even float32 -> bfloat16 bits (hardware conversion,
-// v_cvt_pk_bf16_f32 on gfx950; NaN stays NaN).
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-    const __bf16 h = (__bf16)f;
-    return __builtin_bit_cast(uint16_t, h);
-}
-
-// Round-to-nearest-even float32 -> float16 bits (hardware conversion).
-__device__ __forceinline__ uint16_t f32_to_f16_bits(float f) {
-    _Float16 h = (_Float16)f;
-    return __builtin_bit_cast(uint16_t, h);
-}
-
 // Element types of the Hadamard stage.
 enum : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
@@ -61,13 +54,12 @@ typedef float wg_f32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 wg_f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 wg_bf16x2 __attribute__((ext_vector_type(2)));
 
-// from_f32: one element; store2: two adjacent elements (a at the lower
-// address) in one store, rounded to nearest even by the packed conversions
-// (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32 on gfx950).
+// store2: two adjacent elements (a at the lower address) in one store,
+// rounded to nearest even by the packed conversions (v_cvt_pk_f16_f32 /
+// v_cvt_pk_bf16_f32 on gfx950).
 template <>
 struct Elem<kF32> {
     using T = float;
-    __device__ static __forceinline__ float from_f32(float v) { return v; }
     __device__ static __forceinline__ void store2(float* p, float a, float b) {
         *reinterpret_cast<wg_f32x2*>(p) = wg_f32x2{a, b};
     }
@@ -75,7 +67,6 @@ struct Elem<kF32> {
 template <>
 struct Elem<kF16> {
     using T = uint16_t;
-    __device__ static __forceinline__ uint16_t from_f32(float v) { return f32_to_f16_bits(v); }
     __device__ static __forceinline__ void store2(uint16_t* p, float a, float b) {
         const wg_f16x2 h = __builtin_convertvector(wg_f32x2{a, b}, wg_f16x2);
         *reinterpret_cast<uint32_t*>(p) = __builtin_bit_cast(uint32_t, h);
@@ -84,7 +75,6 @@ struct Elem<kF16> {
 template <>
 struct Elem<kBF16> {
     using T = uint16_t;
-    __device__ static __forceinline__ uint16_t from_f32(float v) { return f32_to_bf16_bits(v); }
     __device__ static __forceinline__ void store2(uint16_t* p, float a, float b) {
         const wg_bf16x2 h = __builtin_convertvector(wg_f32x2{a, b}, wg_bf16x2);
         *reinterpret_cast<uint32_t*>(p) = __builtin_bit_cast(uint32_t, h);

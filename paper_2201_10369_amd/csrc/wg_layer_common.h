@@ -17,12 +17,6 @@
 
 namespace wg {
 
-constexpr int kXcdCount = 8;     // XCDs of the chip, each with its own L2
-// Word 3 of a raw buffer resource on gfx9-family chips (dword data format,
-// no swizzle); accesses outside the resource's range are dropped (stores)
-// or read as zero (loads).
-constexpr int kBufferWord3 = 0x00020000;
-
 struct Geo {
     int N, C, K, H, W, pad, Hout, Wout, Th, Tw, P, P_pad, K_pad, C_pad;
 };
