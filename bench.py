@@ -274,6 +274,7 @@ def bench_surrogate(torch):
     return {"held_out": "F(4x4,3x3) 2D", "train_samples": len(both["c1"]),
             "two_param": two,
             "data_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
+            "train_samples_per_s": round(20 * (len(both["c1"]) // 4096) * 4096 / (t2 - t1)),
             "final_loss": float(losses[-20:].mean().item()),
             "surrogate_best": float(err), "surrogate_c": float(c1), "evaluations": int(used),
             "plain_best": float(np.min(plain)), "plain_c": float(grid[int(np.argmin(plain))]),
