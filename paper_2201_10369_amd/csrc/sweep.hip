@@ -11,9 +11,10 @@
 // Launch structure (one hipGraph, replayed):
 //   construct : one thread per (candidate, matrix row), float64
 //               construction -> float32
-//   evaluate  : persistent blocks stride over work items (candidate, chunk
-//               of `chunk` samples); per item a fixed-order block reduction
-//               writes one float64 partial sum
+//   evaluate  : persistent blocks stride over work items (candidate, or
+//               in 1D a group of four candidates that share each loaded
+//               sample; chunk of `chunk` samples); per item a fixed-order
+//               block reduction writes one float64 partial sum per candidate
 //   finalize  : one thread per candidate adds its partials in index order
 // so the result is bitwise reproducible for a given tuning.
 #include <hip/hip_runtime.h>
@@ -469,25 +470,39 @@ __device__ __forceinline__ double tile_error_2d(const float* __restrict__ d_soa,
     return err;
 }
 
-// NT 1D tiles per thread (samples s[t]; invalid ones are evaluated on a
-// clamped index and not counted), sharing each matrix value read.  T as for
-// the 2D tile.
+// The data of NT 1D pool samples (s[t]): tile, filter and float64 reference.
+template <int M, int R, int NT, typename T>
+struct Samples1d {
+    static constexpr int A = M + R - 1;
+    T gv[NT][R], dv[NT][A];
+    double yr[NT][M];
+    __device__ __forceinline__ void load(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
+                                         const double* __restrict__ yref, const int (&s)[NT], int np) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) gv[t][k] = (T)g_soa[(size_t)k * np + s[t]];
+#pragma unroll
+            for (int l = 0; l < A; ++l) dv[t][l] = (T)d_soa[(size_t)l * np + s[t]];
+#pragma unroll
+            for (int j = 0; j < M; ++j) yr[t][j] = yref[(size_t)j * np + s[t]];
+        }
+    }
+};
+
+// NT 1D tiles (loaded samples; the ones with ok[t] false are evaluated and
+// not counted) of the candidate staged at `lds`, sharing each matrix value
+// read.  T as for the 2D tile.
 template <int M, int R, int NT, typename Z, typename T>
-__device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa, const float* __restrict__ g_soa,
-                                                const double* __restrict__ yref, const int (&s)[NT],
-                                                const bool (&ok)[NT], int np, const T* lds) {
+__device__ __forceinline__ double tile_error_1d(const Samples1d<M, R, NT, T>& sp, const bool (&ok)[NT],
+                                                const T* lds) {
     using L = EvalLds<M, R>;
     constexpr int A = L::A, AP = L::AP, MP = L::MP;
-    T gv[NT][R], dv[NT][A], u[NT][A], v[NT][A];
+    T u[NT][A], v[NT][A];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int k = 0; k < R; ++k) gv[t][k] = (T)g_soa[(size_t)k * np + s[t]];
-#pragma unroll
-        for (int l = 0; l < A; ++l) dv[t][l] = (T)d_soa[(size_t)l * np + s[t]];
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int i = 0; i < A; ++i) u[t][i] = v[t][i] = T(0);
-    }
 #pragma unroll
     for (int k = 0; k < R; ++k) {                       // U = G g, column k of G
         T gc[AP];
@@ -496,7 +511,7 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < A; ++i)
-                if (Z::g(i, k)) u[t][i] = madd(gc[i], gv[t][k], u[t][i]);
+                if (Z::g(i, k)) u[t][i] = madd(gc[i], sp.gv[t][k], u[t][i]);
     }
 #pragma unroll
     for (int l = 0; l < A; ++l) {                       // V = B^T d, column l of B^T
@@ -506,7 +521,7 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < A; ++i)
-                if (Z::bt(i, l)) v[t][i] = madd(bc[i], dv[t][l], v[t][i]);
+                if (Z::bt(i, l)) v[t][i] = madd(bc[i], sp.dv[t][l], v[t][i]);
     }
     T y[NT][M];
 #pragma unroll
@@ -530,13 +545,14 @@ __device__ __forceinline__ double tile_error_1d(const float* __restrict__ d_soa,
     for (int t = 0; t < NT; ++t) {
         double e = 0.0;
 #pragma unroll
-        for (int j = 0; j < M; ++j) e += fabs((double)(float)y[t][j] - yref[(size_t)j * np + s[t]]);
+        for (int j = 0; j < M; ++j) e += fabs((double)(float)y[t][j] - sp.yr[t][j]);
         err += ok[t] ? e : 0.0;
     }
     return err;
 }
 
 constexpr int kTiles1d = 4;
+constexpr int kGroup1d = 4;          // candidates per 1D work item
 
 // FAM: candidates are family sets (FamilyZeros applies), else explicit lists.
 // T: float (float32 evaluation) or double (mixed precision; mats holds the
@@ -553,58 +569,94 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
     // (the float64 tiles take every term: skipping the exact zeros changes no
     // result and made the compiler spill them)
     using Z = typename std::conditional<FAM && sizeof(T) == 4, FamilyZeros<M, R>, AllTerms<M, R>>::type;
-    __shared__ __align__(16) T sm[L::kSize];
-    __shared__ double red[4];                          // one sum per wave
+    // 1D items take kGroup1d candidates: each loaded sample serves all of them
+    constexpr int G = DIMS == 1 ? kGroup1d : 1;
+    __shared__ __align__(16) T sm[G][L::kSize];
+    __shared__ double red[G][4];                       // one sum per wave and candidate
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const long items = (long)n_cand * ipc;
+    const int n_grp = (n_cand + G - 1) / G;
+    const long items = (long)n_grp * ipc;
     for (long item = blockIdx.x; item < items; item += gridDim.x) {
-        const int cand = (int)(item / ipc), ch = (int)(item - (long)cand * ipc);
-        int n = counts[cand];
-        n = n < 0 ? 0 : (n > n_pool ? n_pool : n);
+        const int grp = (int)(item / ipc), ch = (int)(item - (long)grp * ipc);
         const int start = ch * chunk;
-        const bool live = flags[cand] == 0 && start < n;      // uniform over the block
-        if (!live) {
-            if (tid == 0) partial[item] = 0.0;
+        int nj[G];
+        bool lj[G];
+        bool any = false;
+        int nmax = 0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int cand = grp * G + j;
+            int n = cand < n_cand ? counts[cand] : 0;
+            n = n < 0 ? 0 : (n > n_pool ? n_pool : n);
+            nj[j] = n;
+            lj[j] = cand < n_cand && flags[cand] == 0 && start < n;    // uniform over the block
+            any |= lj[j];
+            if (lj[j]) nmax = max(nmax, n);
+        }
+        if (!any) {
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (tid == j && grp * G + j < n_cand) partial[(size_t)(grp * G + j) * ipc + ch] = 0.0;
             continue;
         }
         __syncthreads();                                      // previous item done with sm
-        for (int q = tid; q < L::kSize; q += nthr) sm[q] = L::slot(mats + (size_t)cand * kMatStride, q);
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (lj[j])
+                for (int q = tid; q < L::kSize; q += nthr)
+                    sm[j][q] = L::slot(mats + (size_t)(grp * G + j) * kMatStride, q);
         __syncthreads();
-        const int stop = min(n, start + chunk);
-        double err = 0.0;
+        const int stop = min(nmax, start + chunk);
+        double err[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) err[j] = 0.0;
         if (DIMS == 1) {
             for (int s0 = start + tid; s0 < stop; s0 += kTiles1d * nthr) {
-                // an opaque zero offset keeps the matrix reads inside the loop
-                int z0 = 0;
-                asm volatile("" : "+v"(z0));
                 int ss[kTiles1d];
-                bool ok[kTiles1d];
 #pragma unroll
                 for (int t = 0; t < kTiles1d; ++t) {
                     const int si = s0 + t * nthr;
-                    ok[t] = si < stop;
-                    ss[t] = ok[t] ? si : s0;
+                    ss[t] = si < stop ? si : s0;
                 }
-                err += tile_error_1d<M, R, kTiles1d, Z, T>(d_soa, g_soa, yref, ss, ok, n_pool, sm + z0);
+                Samples1d<M, R, kTiles1d, T> sp;
+                sp.load(d_soa, g_soa, yref, ss, n_pool);
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    if (!lj[j]) continue;
+                    asm volatile("" ::: "memory");       // one candidate at a time
+                    // an opaque zero offset keeps the matrix reads inside the loop
+                    int z0 = 0;
+                    asm volatile("" : "+v"(z0));
+                    const int sj = min(nj[j], start + chunk);
+                    bool ok[kTiles1d];
+#pragma unroll
+                    for (int t = 0; t < kTiles1d; ++t) ok[t] = s0 + t * nthr < sj;
+                    err[j] += tile_error_1d<M, R, kTiles1d, Z, T>(sp, ok, &sm[j][0] + z0);
+                }
             }
         } else {
             for (int s = start + tid; s < stop; s += nthr) {
                 int z0 = 0;
                 asm volatile("" : "+v"(z0));
-                err += tile_error_2d<M, R, Z, T>(d_soa, g_soa, yref, s, n_pool, sm + z0);
+                err[0] += tile_error_2d<M, R, Z, T>(d_soa, g_soa, yref, s, n_pool, &sm[0][0] + z0);
             }
         }
         // fixed-order reduction: a butterfly inside each wave, then the wave
         // sums in wave order
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off, 64);
-        if ((tid & 63) == 0) red[tid >> 6] = err;
-        __syncthreads();
-        if (tid == 0) {
-            double tot = red[0];
-            for (int wv = 1; wv < nthr / 64; ++wv) tot += red[wv];
-            partial[item] = tot;
+        for (int j = 0; j < G; ++j) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) err[j] += __shfl_xor(err[j], off, 64);
+            if ((tid & 63) == 0) red[j][tid >> 6] = err[j];
         }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (tid == j && grp * G + j < n_cand) {
+                double tot = red[j][0];
+                for (int wv = 1; wv < nthr / 64; ++wv) tot += red[j][wv];
+                partial[(size_t)(grp * G + j) * ipc + ch] = lj[j] ? tot : 0.0;
+            }
     }
 }
 
@@ -651,7 +703,7 @@ struct SweepOps {
         double* m64 = S.mixed ? S.mats64 : nullptr;
         hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + kConsCands - 1) / kConsCands),
                            dim3(256), 0, st, a.c1, a.c2, a.pts, a.n_cand, S.mats, m64, S.flags);
-        const long items = (long)a.n_cand * ipc;
+        const long items = (long)((a.n_cand + (DIMS == 1 ? kGroup1d : 1) - 1) / (DIMS == 1 ? kGroup1d : 1)) * ipc;
         long grid = (long)S.n_cu * t.blocks_per_cu;
         if (grid > items) grid = items;
         if (grid < 1) grid = 1;
