@@ -760,6 +760,7 @@ static void dispatch_run(const Sweep& S, const SweepArgs& a, const SweepTune& t,
 static const SweepTune kCandidates[] = {
     {64, 64, 8}, {64, 128, 8}, {128, 128, 4}, {128, 256, 4}, {256, 256, 2},
     {256, 512, 2}, {128, 128, 8}, {256, 256, 4}, {64, 256, 8}, {128, 512, 4},
+    {128, 1024, 4}, {256, 1024, 4}, {64, 512, 8}, {128, 2048, 4}, {64, 1024, 8}, {256, 2048, 2},
 };
 
 static void release(Sweep* S) {
@@ -823,7 +824,7 @@ int wg_sweep_create(wg_sweep** out, int m, int r, int dims, const float* d_pool,
     st = hipc(hipGetLastError(), "sweep reference");
     if (st == WG_OK) st = hipc(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "sweep reference");
     if (st != WG_OK) { release(S); return st; }
-    S->tune = SweepTune{128, 128, 4};
+    S->tune = SweepTune{128, 2048, 4};      // the shape the autotuner picks for F(6,3) on 2000 samples
     *out = reinterpret_cast<wg_sweep*>(S);
     return WG_OK;
 }

@@ -42,7 +42,7 @@ struct Sweep {
     int mixed = 0;               // 1: float64 transforms, float32 Hadamard product
     int* flags = nullptr;        // per candidate: 1 = invalid or singular
     double* partial = nullptr;   // per work item error sums
-    SweepTune tune{128, 128, 4};
+    SweepTune tune{128, 2048, 4};
     bool tuned = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
