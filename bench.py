@@ -122,6 +122,8 @@ SWEEP_FLOP_PER_TILE = {1: 2 * 108 + 8, 2: 2 * 1552 + 64}
 FP32_VECTOR_TFLOPS = 78.6
 # the published figure counts packed (two-wide) float32 operations
 FP32_PUBLISHED_TFLOPS = 157.3
+# float64 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+FP64_VECTOR_TFLOPS = 78.6
 
 
 def bench_sweep(wg, torch, reps=5):
@@ -282,6 +284,35 @@ def bench_surrogate(torch):
             "within_1pct": bool(err <= 1.01 * np.min(plain))}
 
 
+def bench_scoring(wg, torch, x, w, y64, y, flops, reps=5):
+    """The error scoring of the layer: the float64 direct convolution (FP64
+    VALU bound) and the L1 sums of y against it (HBM bound), timed with
+    events on the current stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wg.direct_conv_f64(x, w, "same", y=y64)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        wg.direct_conv_f64(x, w, "same", y=y64)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_d = e0.elapsed_time(e1) / reps
+    out = wg.score_error(y, y64)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        wg.score_error(y, y64, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1) / reps
+    tf = flops / (ms_d * 1e-3) / 1e12
+    score_bytes = y.numel() * (4 + 8)
+    return {"direct_f64_ms": round(ms_d, 4), "direct_f64_tflops": round(tf, 2),
+            "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / FP64_VECTOR_TFLOPS, 4)},
+            "score_ms": round(ms_s, 4), "score_gbs": round(score_bytes / (ms_s * 1e-3) / 1e9, 1)}
+
+
 def bench_two_param(torch):
     """(c, d) grid-and-refine search for the two-parameter families of
     n = 9 and 10 points (F(7,3), F(8,3); Tables tab:sota_1d, tab:sota_2d),
@@ -403,6 +434,7 @@ def main():
 
     # errors against the float64 direct convolution (outside the timed region)
     y64 = wg.direct_conv_f64(x, w, "same")
+    scoring = bench_scoring(wg, torch, x, w, y64, forms["f16"]["y"], flops)
     for dtype, f in forms.items():
         s = wg.score_error(f["y"], y64).cpu().numpy()
         f["rel_l1"] = float(s[0] / s[1])
@@ -431,6 +463,7 @@ def main():
                    "N": N, "C": C, "K": K, "H": H, "W": W, "m": 6, "r": 3, "padding": "same",
                    "step": "16-bit |w| maxima, filter+input transforms (one launch), gemm, output transform"},
         "rel_l1": f16["rel_l1"],
+        "scoring": scoring,
         "roofline": roofline,
         "stages_ms": {d: {k: round(v, 5) for k, v in f["stage_ms"].items()} for d, f in forms.items()},
         "stage_gbs_f16": {k: round(ab[k] / (st[k] * 1e-3) / 1e9, 1) for k in st},
