@@ -269,7 +269,9 @@ int wg_channel_absmax(const float* x, int N, int C, int H, int W, float* out,
 /* float64 direct convolution of the float32 inputs (eq. conv as a zero-padded
  * cross-correlation): y_ref[n][k][i][j] = sum_{c,u,v} x[n][c][i+u-p][j+v-p]
  * w[k][c][u][v].  x, w: device float32; y_ref: device float64 N x K x Hout x
- * Wout.  1 <= r <= 7.  Errors: WG_EINVAL. */
+ * Wout.  1 <= r <= 7.  Every product is exact in float64; the sums run on the
+ * float64 matrix cores in a blocked order (the result is reproducible for
+ * given sizes).  Errors: WG_EINVAL. */
 int wg_direct_conv_f64(const float* x, const float* w, double* y_ref,
                        int N, int C, int K, int H, int W, int r, int padding,
                        wg_stream_t stream);

@@ -3,13 +3,17 @@
 // error sums against it, with a fixed reduction tree.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "wg_device.h"
 #include "wg_internal.h"
 
 namespace wg {
 
 // ---------------------------------------------------------------------------
-// float64 direct convolution.  A block computes a 32 x 32 output patch of 16
-// output channels of one image; each thread owns 2 x 2 pixels x 16 channels.
+// float64 direct convolution on the vector units, for images whose output
+// rows are too wide for the matrix-core form below.  A block computes a
+// 32 x 32 output patch of 16 output channels of one image; each thread owns 2 x 2 pixels x 16 channels.
 // Per input channel the (32+r-1)^2 input patch and the 16 x r x r filter taps
 // are staged in LDS as float64.
 // ---------------------------------------------------------------------------
@@ -86,9 +90,196 @@ __global__ __launch_bounds__(256) void direct_f64_kernel(const float* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// float64 direct convolution as an implicit GEMM on the float64 matrix cores:
+// Y[k][p] = sum_q Wt[k][q] X[q][p] with q = (c, u, v) flattened (w's own row
+// layout) and p an output pixel, X[q][p] the zero-padded input under tap
+// (u, v) of channel c.  A block owns 16 output channels and TH whole output
+// rows of one image; each wave holds up to kDfTiles 16 x 16 accumulator
+// tiles (16 channels x 16 consecutive pixels of the block's rows) and issues
+// v_mfma_f64_16x16x4 over four reduction terms at a time.  The reduction runs
+// in stages of kDfCh channels: the stage's input patch ((TH + R - 1) rows x
+// (Wout + R - 1) columns per channel, zeros outside the image) and its
+// 16 x kDfCh R^2 weights sit in LDS as float64, and the next stage's floats
+// are loaded into registers while the current stage computes.  Every product
+// of two floats is exact in float64; only the order of the sums differs from
+// the plain loop.
+// ---------------------------------------------------------------------------
+constexpr int kDfWaves = 4;
+constexpr int kDfTiles = 13;                 // 16-pixel tiles per wave (832 pixels per block)
+constexpr int kDfCh = 4;                     // channels per stage (4 R^2 terms: whole MFMA steps)
+constexpr int kDfPatch = 1024;               // max patch elements per channel
+constexpr int kDfXPerThread = kDfCh * kDfPatch / 256;
+
+using f64x4 = double __attribute__((ext_vector_type(4)));
+
+struct DirectGeo {
+    int C, K, H, W, pad, Hout, Wout;
+    int TH, NRB, NKB, n_items;               // rows per block, row blocks, channel blocks, blocks
+    int PH, PW;                              // patch rows and columns
+};
+
+template <int R>
+__global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __restrict__ x,
+                                                              const float* __restrict__ w,
+                                                              double* __restrict__ y, DirectGeo g) {
+    constexpr int RR = R * R;
+    constexpr int KK = kDfCh * RR;           // reduction terms per stage
+    constexpr int WS = KK + 1;               // LDS row stride of the stage's weights
+    constexpr int WPT = (16 * KK + 255) / 256;
+    __shared__ double xs[kDfCh * kDfPatch];
+    __shared__ double wsh[16 * WS];
+
+    // consecutive items (the channel blocks of one image's rows, which read
+    // the same input patch) go to one XCD and share its L2
+    const int item = (int)(blockIdx.x % kXcdCount) * (int)(gridDim.x / kXcdCount) + (int)(blockIdx.x / kXcdCount);
+    if (item >= g.n_items) return;           // whole block, before any barrier
+    const int kb = item % g.NKB;
+    const int rb = (item / g.NKB) % g.NRB;
+    const int n = item / (g.NKB * g.NRB);
+    const int k0 = kb * 16, oy0 = rb * g.TH;
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int col = lane & 15, grp = lane >> 4;
+    // rotate which wave takes the block's extra tile over the SIMDs
+    const int wv = (__builtin_amdgcn_readfirstlane(tid >> 6) + item) & (kDfWaves - 1);
+    const int PHPW = g.PH * g.PW;
+    const int stage_elems = kDfCh * PHPW;
+    const int HW = g.H * g.W;
+    const int CRR = g.C * RR;
+
+    // input offset of each staged element relative to the stage's first
+    // channel (-1: zero padding); the same for every stage
+    int goff[kDfXPerThread];
+#pragma unroll
+    for (int j = 0; j < kDfXPerThread; ++j) {
+        const int e = tid + 256 * j;
+        int o = -1;
+        if (e < stage_elems) {
+            const int cl = e / PHPW, rem = e - cl * PHPW;
+            const int i = rem / g.PW, jj = rem - i * g.PW;
+            const int gi = oy0 - g.pad + i, gj = jj - g.pad;
+            if (gi >= 0 && gi < g.H && gj >= 0 && gj < g.W) o = cl * HW + gi * g.W + gj;
+        }
+        goff[j] = o;
+    }
+    // patch offset of each owned pixel (0 for the padding lanes of the last tile)
+    const int npx = min(g.TH, g.Hout - oy0) * g.Wout;
+    const int ntiles = (npx + 15) / 16;
+    const int nt_w = (ntiles - wv + kDfWaves - 1) / kDfWaves;   // this wave's tiles (wave-uniform)
+    int pix[kDfTiles];
+#pragma unroll
+    for (int t = 0; t < kDfTiles; ++t) {
+        const int q = min((wv + kDfWaves * t) * 16 + col, npx - 1);
+        const int oy = q / g.Wout;
+        pix[t] = oy * g.PW + (q - oy * g.Wout);
+    }
+
+    float xr[kDfXPerThread], wr[WPT];
+    auto load_stage = [&](int c0) {
+        const float* xb = x + ((size_t)n * g.C + c0) * HW;
+        const int lim = (g.C - c0) * PHPW;   // elements of channels below C
+#pragma unroll
+        for (int j = 0; j < kDfXPerThread; ++j)
+            xr[j] = (goff[j] >= 0 && tid + 256 * j < lim) ? xb[goff[j]] : 0.f;
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            const int f = tid + 256 * j;
+            const int r = f / KK, kl = f - r * KK;
+            const int q = c0 * RR + kl;
+            wr[j] = (f < 16 * KK && k0 + r < g.K && q < CRR) ? w[(size_t)(k0 + r) * CRR + q] : 0.f;
+        }
+    };
+
+    f64x4 acc[kDfTiles];
+#pragma unroll
+    for (int t = 0; t < kDfTiles; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    const int n_stages = (g.C + kDfCh - 1) / kDfCh;
+    load_stage(0);
+    for (int s = 0; s < n_stages; ++s) {
+        __syncthreads();                     // the previous stage's reads are done
+#pragma unroll
+        for (int j = 0; j < kDfXPerThread; ++j)
+            if (tid + 256 * j < stage_elems) xs[tid + 256 * j] = (double)xr[j];
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            const int f = tid + 256 * j;
+            if (f < 16 * KK) {
+                const int r = f / KK, kl = f - r * KK;
+                wsh[r * WS + kl] = (double)wr[j];
+            }
+        }
+        __syncthreads();
+        if (s + 1 < n_stages) load_stage((s + 1) * kDfCh);
+#pragma unroll 1
+        for (int st = 0; st < RR; ++st) {
+            // lane (col, grp) supplies A[col][grp] = weight of channel k0 + col at
+            // term 4 st + grp and B[grp][col] = the input under that term at pixel col
+            const int kl = 4 * st + grp;
+            const int cl = kl / RR, uv = kl - cl * RR, u = uv / R, v = uv - u * R;
+            const int koff = cl * PHPW + u * g.PW + v;
+            const double a = wsh[col * WS + kl];
+            double b[kDfTiles];
+#pragma unroll
+            for (int t = 0; t < kDfTiles; ++t) b[t] = xs[koff + pix[t]];
+#pragma unroll
+            for (int t = 0; t < kDfTiles; ++t)
+                if (t < nt_w) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t], 0, 0, 0);
+        }
+    }
+    // accumulator element i of lane (col, grp) is row grp + 4 i of the 16 x 16
+    // tile (channel k0 + grp + 4 i) at column col (pixel col): the float64
+    // matrix instruction interleaves its rows over the lane groups
+#pragma unroll
+    for (int t = 0; t < kDfTiles; ++t) {
+        const int q = (wv + kDfWaves * t) * 16 + col;
+        if (t >= nt_w || q >= npx) continue;
+        const int oyl = q / g.Wout, ox = q - oyl * g.Wout;
+        double* yp = y + ((size_t)n * g.K * g.Hout + oy0 + oyl) * g.Wout + ox;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = k0 + grp + 4 * i;
+            if (k < g.K) yp[(size_t)k * g.Hout * g.Wout] = acc[t][i];
+        }
+    }
+}
+
+// Rows per block for the MFMA form: as many whole output rows as fit in
+// kDfWaves * kDfTiles tiles and a kDfPatch-element patch, balanced over the
+// row blocks; 0 when not even one row fits.
+int direct_rows_per_block(int r, int Hout, int Wout) {
+    const int PW = Wout + r - 1;
+    int th = std::min(Hout, kDfWaves * kDfTiles * 16 / Wout);
+    while (th >= 1 && (th + r - 1) * PW > kDfPatch) --th;
+    if (th < 1) return 0;
+    const int nrb = (Hout + th - 1) / th;
+    return (Hout + nrb - 1) / nrb;
+}
+
 int launch_direct_f64(const float* x, const float* w, double* y, int N, int C, int K, int H, int W,
                       int r, int pad, int Hout, int Wout, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (r < 1 || r > 7) return fail(WG_EINVAL, "direct conv: r out of range");
+    const int th = direct_rows_per_block(r, Hout, Wout);
+    if (th >= 1) {
+        DirectGeo g{C, K, H, W, pad, Hout, Wout, th, (Hout + th - 1) / th, (K + 15) / 16, 0, th + r - 1,
+                    Wout + r - 1};
+        const long long items = (long long)N * g.NRB * g.NKB;
+        const long long grid = (items + kXcdCount - 1) / kXcdCount * kXcdCount;
+        if (grid > 0x7fffffffLL) return fail(WG_EINVAL, "direct conv: too many blocks");
+        g.n_items = (int)items;
+        switch (r) {
+#define WG_DIRECT_MFMA_CASE(RR)                                                                    \
+    case RR:                                                                                       \
+        hipLaunchKernelGGL((direct_f64_mfma_kernel<RR>), dim3((unsigned)grid), dim3(256), 0, s, x, \
+                           w, y, g);                                                               \
+        break;
+            WG_DIRECT_MFMA_CASE(1) WG_DIRECT_MFMA_CASE(2) WG_DIRECT_MFMA_CASE(3) WG_DIRECT_MFMA_CASE(4)
+            WG_DIRECT_MFMA_CASE(5) WG_DIRECT_MFMA_CASE(6) WG_DIRECT_MFMA_CASE(7)
+#undef WG_DIRECT_MFMA_CASE
+        }
+        return hip_check((int)hipGetLastError(), "direct_f64_mfma_kernel");
+    }
     const int tiles_y = (Hout + kDTile - 1) / kDTile, tiles_x = (Wout + kDTile - 1) / kDTile;
     const dim3 grid((unsigned)(tiles_y * tiles_x), (unsigned)((K + kDK - 1) / kDK), (unsigned)N);
     switch (r) {
@@ -100,7 +291,6 @@ int launch_direct_f64(const float* x, const float* w, double* y, int N, int C, i
         WG_DIRECT_CASE(1) WG_DIRECT_CASE(2) WG_DIRECT_CASE(3) WG_DIRECT_CASE(4) WG_DIRECT_CASE(5)
         WG_DIRECT_CASE(6) WG_DIRECT_CASE(7)
 #undef WG_DIRECT_CASE
-        default: return fail(WG_EINVAL, "direct conv: r out of range");
     }
     return hip_check((int)hipGetLastError(), "direct_f64_kernel");
 }

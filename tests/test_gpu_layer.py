@@ -286,7 +286,12 @@ def test_classic_f23_layer_is_exact_on_integers():
 # scoring kernels
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("shape,r,padding", [((2, 5, 7, 19, 23), 3, "same"), ((1, 3, 20, 40, 33), 5, "valid"),
-                                             ((3, 17, 9, 5, 6), 3, "valid"), ((1, 2, 1, 1, 1), 1, "same")])
+                                             ((3, 17, 9, 5, 6), 3, "valid"), ((1, 2, 1, 1, 1), 1, "same"),
+                                             # several row blocks, the last one shorter
+                                             ((1, 4, 16, 70, 28), 3, "same"), ((1, 6, 18, 30, 31), 7, "same"),
+                                             ((2, 9, 33, 12, 17), 2, "valid"), ((1, 1, 16, 3, 40), 3, "same"),
+                                             # rows wider than the matrix-core form takes: vector form
+                                             ((1, 3, 5, 4, 900), 3, "same")])
 def test_direct_f64_matches_oracle(shape, r, padding):
     wg = _wg()
     N, C, K, H, W = shape
