@@ -109,7 +109,8 @@ constexpr int kDfWaves = 4;
 constexpr int kDfTiles = 13;                 // 16-pixel tiles per wave (832 pixels per block)
 constexpr int kDfCh = 4;                     // channels per stage (4 R^2 terms: whole MFMA steps)
 constexpr int kDfPatch = 1024;               // max patch elements per channel
-constexpr int kDfXPerThread = kDfCh * kDfPatch / 256;
+constexpr int kDfThreads = 64 * kDfWaves;
+constexpr int kDfXPerThread = kDfCh * kDfPatch / kDfThreads;
 
 using f64x4 = double __attribute__((ext_vector_type(4)));
 
@@ -120,13 +121,14 @@ struct DirectGeo {
 };
 
 template <int R>
-__global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __restrict__ x,
+__global__ __launch_bounds__(kDfThreads) void direct_f64_mfma_kernel(const float* __restrict__ x,
                                                               const float* __restrict__ w,
                                                               double* __restrict__ y, DirectGeo g) {
     constexpr int RR = R * R;
     constexpr int KK = kDfCh * RR;           // reduction terms per stage
+    static_assert(KK % 4 == 0, "a stage must hold whole matrix-instruction steps");
     constexpr int WS = KK + 1;               // LDS row stride of the stage's weights
-    constexpr int WPT = (16 * KK + 255) / 256;
+    constexpr int WPT = (16 * KK + kDfThreads - 1) / kDfThreads;
     __shared__ double xs[kDfCh * kDfPatch];
     __shared__ double wsh[16 * WS];
 
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __res
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int col = lane & 15, grp = lane >> 4;
     // rotate which wave takes the block's extra tile over the SIMDs
-    const int wv = (__builtin_amdgcn_readfirstlane(tid >> 6) + item) & (kDfWaves - 1);
+    const int wv = (__builtin_amdgcn_readfirstlane(tid >> 6) + item) % kDfWaves;
     const int PHPW = g.PH * g.PW;
     const int stage_elems = kDfCh * PHPW;
     const int HW = g.H * g.W;
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __res
     int goff[kDfXPerThread];
 #pragma unroll
     for (int j = 0; j < kDfXPerThread; ++j) {
-        const int e = tid + 256 * j;
+        const int e = tid + kDfThreads * j;
         int o = -1;
         if (e < stage_elems) {
             const int cl = e / PHPW, rem = e - cl * PHPW;
@@ -180,10 +182,10 @@ __global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __res
         const int lim = (g.C - c0) * PHPW;   // elements of channels below C
 #pragma unroll
         for (int j = 0; j < kDfXPerThread; ++j)
-            xr[j] = (goff[j] >= 0 && tid + 256 * j < lim) ? xb[goff[j]] : 0.f;
+            xr[j] = (goff[j] >= 0 && tid + kDfThreads * j < lim) ? xb[goff[j]] : 0.f;
 #pragma unroll
         for (int j = 0; j < WPT; ++j) {
-            const int f = tid + 256 * j;
+            const int f = tid + kDfThreads * j;
             const int r = f / KK, kl = f - r * KK;
             const int q = c0 * RR + kl;
             wr[j] = (f < 16 * KK && k0 + r < g.K && q < CRR) ? w[(size_t)(k0 + r) * CRR + q] : 0.f;
@@ -200,10 +202,10 @@ __global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __res
         __syncthreads();                     // the previous stage's reads are done
 #pragma unroll
         for (int j = 0; j < kDfXPerThread; ++j)
-            if (tid + 256 * j < stage_elems) xs[tid + 256 * j] = (double)xr[j];
+            if (tid + kDfThreads * j < stage_elems) xs[tid + kDfThreads * j] = (double)xr[j];
 #pragma unroll
         for (int j = 0; j < WPT; ++j) {
-            const int f = tid + 256 * j;
+            const int f = tid + kDfThreads * j;
             if (f < 16 * KK) {
                 const int r = f / KK, kl = f - r * KK;
                 wsh[r * WS + kl] = (double)wr[j];
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __res
         __syncthreads();
         if (s + 1 < n_stages) load_stage((s + 1) * kDfCh);
 #pragma unroll 1
-        for (int st = 0; st < RR; ++st) {
+        for (int st = 0; st < KK / 4; ++st) {
             // lane (col, grp) supplies A[col][grp] = weight of channel k0 + col at
             // term 4 st + grp and B[grp][col] = the input under that term at pixel col
             const int kl = 4 * st + grp;
@@ -222,9 +224,12 @@ __global__ __launch_bounds__(256) void direct_f64_mfma_kernel(const float* __res
             double b[kDfTiles];
 #pragma unroll
             for (int t = 0; t < kDfTiles; ++t) b[t] = xs[koff + pix[t]];
+            // every wave issues all kDfTiles products: a wave with fewer tiles
+            // accumulates its clamped padding pixels and drops them at the
+            // store, which keeps the step free of branches
 #pragma unroll
             for (int t = 0; t < kDfTiles; ++t)
-                if (t < nt_w) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t], 0, 0, 0);
         }
     }
     // accumulator element i of lane (col, grp) is row grp + 4 i of the 16 x 16
@@ -271,7 +276,7 @@ int launch_direct_f64(const float* x, const float* w, double* y, int N, int C, i
         switch (r) {
 #define WG_DIRECT_MFMA_CASE(RR)                                                                    \
     case RR:                                                                                       \
-        hipLaunchKernelGGL((direct_f64_mfma_kernel<RR>), dim3((unsigned)grid), dim3(256), 0, s, x, \
+        hipLaunchKernelGGL((direct_f64_mfma_kernel<RR>), dim3((unsigned)grid), dim3(kDfThreads), 0, s, x, \
                            w, y, g);                                                               \
         break;
             WG_DIRECT_MFMA_CASE(1) WG_DIRECT_MFMA_CASE(2) WG_DIRECT_MFMA_CASE(3) WG_DIRECT_MFMA_CASE(4)
