@@ -121,7 +121,7 @@ struct DirectGeo {
 };
 
 template <int R>
-__global__ __launch_bounds__(kDfThreads) void direct_f64_mfma_kernel(const float* __restrict__ x,
+__global__ __launch_bounds__(kDfThreads, 2) void direct_f64_mfma_kernel(const float* __restrict__ x,
                                                               const float* __restrict__ w,
                                                               double* __restrict__ y, DirectGeo g) {
     constexpr int RR = R * R;
@@ -150,8 +150,10 @@ __global__ __launch_bounds__(kDfThreads) void direct_f64_mfma_kernel(const float
     const int CRR = g.C * RR;
 
     // input offset of each staged element relative to the stage's first
-    // channel (-1: zero padding); the same for every stage
-    int goff[kDfXPerThread];
+    // channel (-1: zero padding), the same for every stage; kept in LDS (each
+    // thread reads back only its own entries) to leave registers for the
+    // operands of two steps
+    __shared__ int goffs[kDfCh * kDfPatch];
 #pragma unroll
     for (int j = 0; j < kDfXPerThread; ++j) {
         const int e = tid + kDfThreads * j;
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kDfThreads) void direct_f64_mfma_kernel(const float
             const int gi = oy0 - g.pad + i, gj = jj - g.pad;
             if (gi >= 0 && gi < g.H && gj >= 0 && gj < g.W) o = cl * HW + gi * g.W + gj;
         }
-        goff[j] = o;
+        goffs[tid + kDfThreads * j] = o;
     }
     // patch offset of each owned pixel (0 for the padding lanes of the last tile)
     const int npx = min(g.TH, g.Hout - oy0) * g.Wout;
@@ -182,7 +184,10 @@ __global__ __launch_bounds__(kDfThreads) void direct_f64_mfma_kernel(const float
         const int lim = (g.C - c0) * PHPW;   // elements of channels below C
 #pragma unroll
         for (int j = 0; j < kDfXPerThread; ++j)
-            xr[j] = (goff[j] >= 0 && tid + kDfThreads * j < lim) ? xb[goff[j]] : 0.f;
+        {
+            const int o = goffs[tid + kDfThreads * j];
+            xr[j] = (o >= 0 && tid + kDfThreads * j < lim) ? xb[o] : 0.f;
+        }
 #pragma unroll
         for (int j = 0; j < WPT; ++j) {
             const int f = tid + kDfThreads * j;
@@ -213,23 +218,47 @@ __global__ __launch_bounds__(kDfThreads) void direct_f64_mfma_kernel(const float
         }
         __syncthreads();
         if (s + 1 < n_stages) load_stage((s + 1) * kDfCh);
-#pragma unroll 1
-        for (int st = 0; st < KK / 4; ++st) {
-            // lane (col, grp) supplies A[col][grp] = weight of channel k0 + col at
-            // term 4 st + grp and B[grp][col] = the input under that term at pixel col
-            const int kl = 4 * st + grp;
+        // For step st, lane (col, grp) supplies A[col][grp] = weight of channel
+        // k0 + col at term 4 st + grp and B[grp][col] = the input under that
+        // term at pixel col.  The operands of step st + 1 are read while the
+        // products of step st issue.
+        double bn[kDfTiles], an;
+        {
+            const int kl = grp;
             const int cl = kl / RR, uv = kl - cl * RR, u = uv / R, v = uv - u * R;
             const int koff = cl * PHPW + u * g.PW + v;
-            const double a = wsh[col * WS + kl];
+            an = wsh[col * WS + kl];
+#pragma unroll
+            for (int t = 0; t < kDfTiles; ++t) bn[t] = xs[koff + pix[t]];
+        }
+#pragma unroll 1
+        for (int st = 0; st < KK / 4; ++st) {
             double b[kDfTiles];
 #pragma unroll
-            for (int t = 0; t < kDfTiles; ++t) b[t] = xs[koff + pix[t]];
+            for (int t = 0; t < kDfTiles; ++t) b[t] = bn[t];
+            const double a = an;
+            {
+                // operands of the next step (the last step re-reads its own)
+                const int kl = 4 * min(st + 1, KK / 4 - 1) + grp;
+                const int cl = kl / RR, uv = kl - cl * RR, u = uv / R, v = uv - u * R;
+                const int koff = cl * PHPW + u * g.PW + v;
+                an = wsh[col * WS + kl];
+#pragma unroll
+                for (int t = 0; t < kDfTiles; ++t) bn[t] = xs[koff + pix[t]];
+            }
             // every wave issues all kDfTiles products: a wave with fewer tiles
             // accumulates its clamped padding pixels and drops them at the
             // store, which keeps the step free of branches
 #pragma unroll
             for (int t = 0; t < kDfTiles; ++t)
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t], 0, 0, 0);
+            // scheduling: alternate one LDS read (mask 0x100) and one matrix
+            // instruction (mask 0x008)
+#pragma unroll
+            for (int t = 0; t < kDfTiles; ++t) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
         }
     }
     // accumulator element i of lane (col, grp) is row grp + 4 i of the 16 x 16
