@@ -290,6 +290,7 @@ def test_classic_f23_layer_is_exact_on_integers():
                                              # several row blocks, the last one shorter
                                              ((1, 4, 16, 70, 28), 3, "same"), ((1, 6, 18, 30, 31), 7, "same"),
                                              ((2, 9, 33, 12, 17), 2, "valid"), ((1, 1, 16, 3, 40), 3, "same"),
+                                             ((1, 5, 9, 14, 17), 6, "valid"), ((2, 3, 20, 9, 11), 4, "valid"),
                                              # rows wider than the matrix-core form takes: vector form
                                              ((1, 3, 5, 4, 900), 3, "same")])
 def test_direct_f64_matches_oracle(shape, r, padding):
