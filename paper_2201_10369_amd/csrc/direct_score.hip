@@ -122,8 +122,8 @@ struct DirectGeo {
 
 template <int R>
 __global__ __launch_bounds__(kDfThreads, 2) void direct_f64_mfma_kernel(const float* __restrict__ x,
-                                                              const float* __restrict__ w,
-                                                              double* __restrict__ y, DirectGeo g) {
+                                                                         const float* __restrict__ w,
+                                                                         double* __restrict__ y, DirectGeo g) {
     constexpr int RR = R * R;
     constexpr int KK = kDfCh * RR;           // reduction terms per stage
     static_assert(KK % 4 == 0, "a stage must hold whole matrix-instruction steps");
