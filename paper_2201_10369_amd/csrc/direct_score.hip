@@ -294,7 +294,9 @@ int launch_direct_f64(const float* x, const float* w, double* y, int N, int C, i
                       int r, int pad, int Hout, int Wout, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (r < 1 || r > 7) return fail(WG_EINVAL, "direct conv: r out of range");
-    const int th = direct_rows_per_block(r, Hout, Wout);
+    // the matrix-core form keeps input offsets within a stage in 32 bits
+    const bool small_planes = (long long)kDfCh * H * W <= 0x7fffffffLL;
+    const int th = small_planes ? direct_rows_per_block(r, Hout, Wout) : 0;
     if (th >= 1) {
         DirectGeo g{C, K, H, W, pad, Hout, Wout, th, (Hout + th - 1) / th, (K + 15) / 16, 0, th + r - 1,
                     Wout + r - 1};
