@@ -270,14 +270,33 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict
     __shared__ float gs[kRedGroups][kRedParams];
     const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
     const int p = blockIdx.x * kRedParams + pl;
+    // both sums issue their loads eight at a time and add them in the same
+    // order as a plain loop
     if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
         float l = 0.0f;
-        for (int b = 0; b < nblk; ++b) l += part_loss[b];
+        int b = 0;
+        for (; b + 8 <= nblk; b += 8) {
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = part_loss[b + i];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) l += v[i];
+        }
+        for (; b < nblk; ++b) l += part_loss[b];
         *loss_out = l * inv_batch;
     }
     float acc = 0.0f;
-    if (p < kParams)
-        for (int b = grp; b < nblk; b += kRedGroups) acc += part[(size_t)b * kParams + p];
+    if (p < kParams) {
+        int b = grp;
+        for (; b + 7 * kRedGroups < nblk; b += 8 * kRedGroups) {
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = part[(size_t)(b + i * kRedGroups) * kParams + p];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc += v[i];
+        }
+        for (; b < nblk; b += kRedGroups) acc += part[(size_t)b * kParams + p];
+    }
     gs[grp][pl] = acc;
     __syncthreads();
     if (grp != 0 || p >= kParams) return;
