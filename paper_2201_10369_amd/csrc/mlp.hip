@@ -68,17 +68,23 @@ __device__ __forceinline__ void dense128(const float* __restrict__ W, const floa
     float acc[kS / 2];
 #pragma unroll
     for (int q = 0; q < kS / 2; ++q) acc[q] = 0.0f;
+    // weights are loaded eight float4 at a time ahead of their products;
+    // each sum still runs over i in ascending order
     const float4* wr = reinterpret_cast<const float4*>(W + (size_t)j * kH);
-    for (int i4 = 0; i4 < kH / 4; ++i4) {
-        const float4 w = wr[i4];
+    for (int i4 = 0; i4 < kH / 4; i4 += 8) {
+        float4 w[8];
 #pragma unroll
-        for (int q = 0; q < kS / 2; ++q) {
-            const float4 h = *reinterpret_cast<const float4*>(&in[half + 2 * q][4 * i4]);
-            acc[q] = fmaf(w.x, h.x, acc[q]);
-            acc[q] = fmaf(w.y, h.y, acc[q]);
-            acc[q] = fmaf(w.z, h.z, acc[q]);
-            acc[q] = fmaf(w.w, h.w, acc[q]);
-        }
+        for (int u = 0; u < 8; ++u) w[u] = wr[i4 + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < kS / 2; ++q) {
+                const float4 h = *reinterpret_cast<const float4*>(&in[half + 2 * q][4 * (i4 + u)]);
+                acc[q] = fmaf(w[u].x, h.x, acc[q]);
+                acc[q] = fmaf(w[u].y, h.y, acc[q]);
+                acc[q] = fmaf(w[u].z, h.z, acc[q]);
+                acc[q] = fmaf(w[u].w, h.w, acc[q]);
+            }
     }
     const float bj = b[j];
 #pragma unroll
@@ -129,10 +135,14 @@ __device__ __forceinline__ void backprop_hidden(float (*DZ)[kH], float (*DH)[kH]
         float acc[kS / 2];
 #pragma unroll
         for (int q = 0; q < kS / 2; ++q) acc[q] = 0.0f;
-        for (int jj = 0; jj < kH; ++jj) {
-            const float w = W[(size_t)jj * kH + i];
+        for (int jj = 0; jj < kH; jj += 8) {
+            float w[8];                          // eight loads ahead, jj ascending
 #pragma unroll
-            for (int q = 0; q < kS / 2; ++q) acc[q] = fmaf(DZ[half + 2 * q][jj], w, acc[q]);
+            for (int u = 0; u < 8; ++u) w[u] = W[(size_t)(jj + u) * kH + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int q = 0; q < kS / 2; ++q) acc[q] = fmaf(DZ[half + 2 * q][jj + u], w[u], acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < kS / 2; ++q) DH[half + 2 * q][i] = acc[q];
