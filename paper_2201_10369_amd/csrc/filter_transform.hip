@@ -149,7 +149,47 @@ int launch_filter_maxima(const Plan& p, const float* w, void* U, void* stream) {
     return launch_filter_absmax(p, filter_args(p, w, nullptr, U), static_cast<hipStream_t>(stream));
 }
 
+// The same maximum when every plane is a whole number of 16-byte vectors:
+// the block walks (image, vector) pairs as one flat index and keeps eight
+// vector loads in flight per thread (a maximum does not depend on order).
+__global__ __launch_bounds__(256) void channel_absmax4_kernel(const float* __restrict__ x, int N, int C,
+                                                              int HW, float* __restrict__ out) {
+    __shared__ float red[256];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int hw4 = HW / 4;
+    const long long total = (long long)N * hw4;
+    float mx = 0.0f;
+    for (long long i0 = tid; i0 < total; i0 += 256 * 8) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long long i = i0 + 256 * u;
+            v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (i < total) {
+                const long long n = i / hw4;
+                const float4* plane = reinterpret_cast<const float4*>(x + ((size_t)n * C + c) * HW);
+                v[u] = plane[i - n * hw4];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
+    }
+    red[tid] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) out[c] = red[0];
+}
+
 int launch_channel_absmax(const float* x, int N, int C, int HW, float* out, void* stream) {
+    if (HW % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) {
+        hipLaunchKernelGGL(channel_absmax4_kernel, dim3(C), dim3(256), 0, static_cast<hipStream_t>(stream),
+                           x, N, C, HW, out);
+        return last_launch("channel_absmax4_kernel");
+    }
     hipLaunchKernelGGL(channel_absmax_kernel, dim3(C), dim3(256), 0, static_cast<hipStream_t>(stream),
                        x, N, C, HW, out);
     return last_launch("channel_absmax_kernel");

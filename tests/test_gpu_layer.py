@@ -316,9 +316,14 @@ def test_score_matches_oracle_and_is_reproducible():
     assert np.array_equal(out, again)
 
 
-def test_channel_absmax():
+@pytest.mark.parametrize("shape", [(3, 7, 9, 11),          # planes of 99 floats: scalar form
+                                   (5, 6, 12, 12),         # 16-byte vectors, one partial batch
+                                   (64, 3, 28, 28)])       # several batches of eight, ragged tail
+def test_channel_absmax(shape):
     wg = _wg()
-    x, _ = synth.layer_inputs(3, 7, 1, 9, 11, 3, "normal")
+    N, C, H, W = shape
+    x, _ = synth.layer_inputs(N, C, 1, H, W, 3, "normal")
+    x[N - 1, C - 1, H - 1, W - 1] = -50.0                  # the maximum in the very last element
     got = _host(wg.channel_absmax(_dev(x)))
     assert np.array_equal(got, np.abs(x).max(axis=(0, 2, 3)))
 
