@@ -326,21 +326,24 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict
     P[p] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// k smallest entries of v (k <= 64), ascending, ties to the smaller index.
+// k smallest entries of v (k <= 64), ascending, ties to the smaller index;
+// NaN entries are never chosen and missing ranks are -1.  The winners come
+// out in increasing (value, index) order, so each round takes the smallest
+// (value, index) pair after the previous round's winner.
 __global__ __launch_bounds__(1024) void topk_min_kernel(const float* __restrict__ v, int n, int k,
                                                         int* __restrict__ idx_out) {
     __shared__ float sv[1024];
     __shared__ int si[1024];
-    __shared__ int chosen[64];
     const int tid = threadIdx.x;
+    float pv = -INFINITY;                  // previous winner
+    int pi = -1;
     for (int round = 0; round < k; ++round) {
         float best = INFINITY;
         int bi = 0x7fffffff;
         for (int q = tid; q < n; q += 1024) {
-            bool taken = false;
-            for (int t = 0; t < round; ++t) taken |= (chosen[t] == q);
             const float x = v[q];
-            if (!taken && !(x != x) && (x < best || (x == best && q < bi))) {
+            const bool after = x > pv || (x == pv && q > pi);
+            if (!(x != x) && after && (x < best || (x == best && q < bi))) {
                 best = x;
                 bi = q;
             }
@@ -359,11 +362,10 @@ __global__ __launch_bounds__(1024) void topk_min_kernel(const float* __restrict_
             }
             __syncthreads();
         }
-        if (tid == 0) {
-            chosen[round] = si[0];
-            idx_out[round] = si[0] == 0x7fffffff ? -1 : si[0];
-        }
-        __syncthreads();
+        pv = sv[0];
+        pi = si[0];
+        if (tid == 0) idx_out[round] = pi == 0x7fffffff ? -1 : pi;
+        __syncthreads();                   // sv, si are rewritten next round
     }
 }
 

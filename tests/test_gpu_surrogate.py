@@ -97,6 +97,16 @@ def test_topk_matches_numpy():
     assert list(idx[:2]) == [123, 456]
 
 
+def test_topk_infinities_nan_and_short_input():
+    wg = _wg()
+    v = np.array([3.0, np.inf, -np.inf, np.nan, 3.0, np.inf, -1.0, np.nan, -np.inf, 0.5], np.float32)
+    idx = wg.topk_min(_dev(v), 12).cpu().numpy()
+    ok = np.flatnonzero(~np.isnan(v))
+    order = ok[np.argsort(v[ok], kind="stable")]
+    assert list(idx) == list(order) + [-1] * (12 - len(order))
+    assert list(idx[:2]) == [2, 8] and list(idx[5:8]) == [4, 1, 5]
+
+
 def test_surrogate_gain_over_plain_and_random_search():
     """Hold out F(4x4,3x3): the surrogate is trained on sweep errors of the
     other 11 tile sizes (F(2..8,3), F(2..6,5); 2D), plus 64 exact samples of
