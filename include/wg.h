@@ -252,6 +252,32 @@ int wg_filter_maxima(const wg_plan* plan, const float* w, void* U, wg_stream_t s
 int wg_transform_filters_and_input(const wg_plan* plan, const float* w, const float* x_absmax,
                                    const float* x, void* U, void* ws, size_t ws_bytes,
                                    wg_stream_t stream);
+
+/* Per-batch 16-bit scaling: the calls a caller makes for every new input
+ * when max |x_c| is not known beforehand (the scaling of the Hadamard stage
+ * then follows each batch; Section 4.1 amortises both transforms, so they
+ * share one launch):
+ *   wg_layer_maxima:    for WG_F16 / WG_BF16 the maxima of |w| over chunks
+ *                       of 8 filters and of |x| over chunks of images
+ *                       (min(N, 8) chunks of ceil(N / min(N, 8)) images),
+ *                       per channel, into the library scratch of U; nothing
+ *                       to do for WG_F32.
+ *   wg_transform_layer: then the filter and input transforms in one launch
+ *                       as wg_transform_filters_and_input, with
+ *                       x_absmax[c] = the maximum of those partial maxima of
+ *                       |x| (for WG_F32: wg_transform_filters_and_input with
+ *                       x_absmax NULL).
+ * U, the scale tables and V' equal bit for bit what wg_channel_absmax,
+ * wg_filter_maxima and wg_transform_filters_and_input with that x_absmax
+ * write, since a maximum does not depend on how it is split.
+ * x, w: device float32 as for the other calls; U: device, filter_bytes;
+ * ws: device workspace of at least workspace_bytes.
+ * Errors: WG_EINVAL (null pointer), WG_EWORKSPACE, WG_EUNSUPPORTED (the
+ * limits of wg_transform_filters_and_input), WG_EHIP. */
+int wg_layer_maxima(const wg_plan* plan, const float* w, const float* x, void* U, wg_stream_t stream);
+int wg_transform_layer(const wg_plan* plan, const float* w, const float* x, void* U, void* ws,
+                       size_t ws_bytes, wg_stream_t stream);
+
 int wg_hadamard_gemm(const wg_plan* plan, const void* U, void* ws, size_t ws_bytes,
                      wg_stream_t stream);
 int wg_output_transform(const wg_plan* plan, const void* ws, size_t ws_bytes, float* y,

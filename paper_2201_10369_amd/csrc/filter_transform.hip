@@ -18,31 +18,27 @@
 namespace wg {
 
 // ---------------------------------------------------------------------------
-// 16-bit Hadamard stage: partial maxima of |w| over chunks of kKChunk
+// 16-bit Hadamard stage: partial maxima of |w| over chunks of kKChunkW
 // filters for 64 channels per block (coalesced: a wave reads 64 consecutive
 // channels' r*r taps).  part[kc][c] for filter chunk kc.
 // ---------------------------------------------------------------------------
-constexpr int kKChunk = 8;
-
 template <int RR>
-__global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restrict__ w,
-                                                            float* __restrict__ part, int K, int C,
-                                                            int C_pad) {
+__device__ __forceinline__ void w_absmax_block(const float* __restrict__ w, float* __restrict__ part, int K, int C,
+                                               int C_pad, int bx, int kc) {
     __shared__ float red[4][64];
     const int cl = threadIdx.x & 63, kq = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + cl;
-    const int kc = blockIdx.y;
+    const int c = bx * 64 + cl;
     float mx = 0.0f;
     if (c < C) {
-        float v[kKChunk / 4][RR];
+        float v[kKChunkW / 4][RR];
 #pragma unroll
-        for (int i = 0; i < kKChunk / 4; ++i) {
-            const int k = kc * kKChunk + kq + 4 * i;
+        for (int i = 0; i < kKChunkW / 4; ++i) {
+            const int k = kc * kKChunkW + kq + 4 * i;
 #pragma unroll
             for (int t = 0; t < RR; ++t) v[i][t] = k < K ? w[((size_t)k * C + c) * RR + t] : 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < kKChunk / 4; ++i)
+        for (int i = 0; i < kKChunkW / 4; ++i)
 #pragma unroll
             for (int t = 0; t < RR; ++t) mx = fmaxf(mx, fabsf(v[i][t]));
     }
@@ -50,6 +46,77 @@ __global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restr
     __syncthreads();
     if (kq == 0 && c < C_pad)
         part[(size_t)kc * C_pad + c] = fmaxf(fmaxf(red[0][cl], red[1][cl]), fmaxf(red[2][cl], red[3][cl]));
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restrict__ w,
+                                                            float* __restrict__ part, int K, int C,
+                                                            int C_pad) {
+    w_absmax_block<RR>(w, part, K, C, C_pad, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// Partial maximum of |x| over images [n0, n1) of channel c, written to
+// xpart[q][c].  vec: every plane is a whole number of 16-byte vectors at a
+// 16-byte aligned address; then the block walks (image, vector) pairs as one
+// flat index with eight vector loads in flight per thread (a maximum does
+// not depend on the order).
+__device__ __forceinline__ void x_absmax_block(const float* __restrict__ x, float* __restrict__ xpart, int C,
+                                               int C_pad, int HW, int c, int q, int n0, int n1, bool vec) {
+    __shared__ float red[256];
+    const int tid = threadIdx.x;
+    float mx = 0.0f;
+    if (vec) {
+        const int hw4 = HW / 4;
+        const long long total = (long long)(n1 - n0) * hw4;
+        for (long long i0 = tid; i0 < total; i0 += 256 * 8) {
+            float4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const long long i = i0 + 256 * u;
+                v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (i < total) {
+                    const long long nn = i / hw4;
+                    const float4* plane = reinterpret_cast<const float4*>(x + ((size_t)(n0 + nn) * C + c) * HW);
+                    v[u] = plane[i - nn * hw4];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
+        }
+    } else {
+        for (int n = n0; n < n1; ++n) {
+            const float* src = x + ((size_t)n * C + c) * HW;
+            for (int i = tid; i < HW; i += 256) mx = fmaxf(mx, fabsf(src[i]));
+        }
+    }
+    red[tid] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) xpart[(size_t)q * C_pad + c] = red[0];
+}
+
+// Both partial maxima of the per-batch 16-bit scaling in one launch: blocks
+// [0, n_wblocks) take (64 channels, filter chunk) of |w|, the rest (channel,
+// image chunk) of |x|, consecutive blocks on consecutive channels of one
+// image chunk (adjacent planes of x).
+template <int RR>
+__global__ __launch_bounds__(256) void layer_maxima_kernel(const float* __restrict__ w, float* __restrict__ wpart,
+                                                           int K, int C, int C_pad, int nwx, int n_wblocks,
+                                                           const float* __restrict__ x, float* __restrict__ xpart,
+                                                           int N, int HW, int ipc, int vec) {
+    const int b = (int)blockIdx.x;
+    if (b < n_wblocks) {
+        w_absmax_block<RR>(w, wpart, K, C, C_pad, b % nwx, b / nwx);
+        return;
+    }
+    const int bx = b - n_wblocks;
+    const int c = bx % C, q = bx / C;
+    const int n0 = q * ipc, n1 = min(N, n0 + ipc);
+    x_absmax_block(x, xpart, C, C_pad, HW, c, q, n0, n1, vec != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -91,8 +158,15 @@ FilterArgs filter_args(const Plan& p, const float* w, const float* x_absmax, voi
     char* Ub = static_cast<char*>(U);
     int32_t* s_tab = reinterpret_cast<int32_t*>(Ub + L.scale_offset);
     int32_t* t_tab = reinterpret_cast<int32_t*>(Ub + L.chan_offset);
-    float* part = reinterpret_cast<float*>(Ub + L.chan_offset + round_up((size_t)L.C_pad * 4, 256));
-    return FilterArgs{w, U, part, x_absmax, s_tab, t_tab, (L.K + kKChunk - 1) / kKChunk};
+    float* part = reinterpret_cast<float*>(Ub + wpart_offset(L));
+    return FilterArgs{w, U, part, x_absmax, nullptr, s_tab, t_tab, w_chunks(L), 0};
+}
+
+FilterArgs filter_args_xpart(const Plan& p, const float* w, void* U) {
+    FilterArgs fa = filter_args(p, w, nullptr, U);
+    fa.xpart = reinterpret_cast<const float*>(static_cast<char*>(U) + xpart_offset(p.L));
+    fa.xchunks = x_chunks(p.L);
+    return fa;
 }
 
 int launch_filter_absmax(const Plan& p, const FilterArgs& fa, hipStream_t s) {
@@ -147,6 +221,34 @@ int launch_filter_transform(const Plan& p, const float* w, const float* x_absmax
 
 int launch_filter_maxima(const Plan& p, const float* w, void* U, void* stream) {
     return launch_filter_absmax(p, filter_args(p, w, nullptr, U), static_cast<hipStream_t>(stream));
+}
+
+int launch_layer_maxima(const Plan& p, const float* w, const float* x, void* U, void* stream) {
+    const wg_layout& L = p.L;
+    if (L.dtype == WG_F32) return WG_OK;
+    const FilterArgs fa = filter_args_xpart(p, w, U);
+    const int nwx = (L.C_pad + 63) / 64;
+    const long n_w = (long)nwx * fa.kchunks, n_x = (long)L.C * fa.xchunks;
+    if (n_w + n_x >= (1L << 31)) return fail(WG_EUNSUPPORTED, "layer maxima: grid too large");
+    const int HW = L.H * L.W;
+    const int vec = (HW % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) ? 1 : 0;
+    const dim3 grid((unsigned)(n_w + n_x));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* wpart = const_cast<float*>(fa.part);
+    float* xpart = const_cast<float*>(fa.xpart);
+    const int ipc = x_images_per_chunk(L);
+    switch (L.r) {
+        case 3:
+            hipLaunchKernelGGL((layer_maxima_kernel<9>), grid, dim3(256), 0, s, w, wpart, L.K, L.C, L.C_pad, nwx,
+                               (int)n_w, x, xpart, L.N, HW, ipc, vec);
+            break;
+        case 5:
+            hipLaunchKernelGGL((layer_maxima_kernel<25>), grid, dim3(256), 0, s, w, wpart, L.K, L.C, L.C_pad, nwx,
+                               (int)n_w, x, xpart, L.N, HW, ipc, vec);
+            break;
+        default: return fail(WG_EUNSUPPORTED, "layer maxima: r not compiled");
+    }
+    return last_launch("layer_maxima_kernel");
 }
 
 // The same maximum when every plane is a whole number of 16-byte vectors:

@@ -63,8 +63,9 @@ struct InputArgs {
     void* V;                   // V'[e][p][c]
     const int32_t* t_tab;      // t[c] from the filter transform (16-bit stage)
     const float* part;         // or: partial maxima of |w| per filter chunk ...
-    const float* x_absmax;     // ... with the per-channel max |x| (null: bound 1)
-    int kchunks;
+    const float* x_absmax;     // ... with the per-channel max |x| (null: bound 1),
+    const float* xpart;        // or the partial maxima of |x| per image chunk
+    int kchunks, xchunks;
     int twb, n_twb, pair_stride, n_blocks;
 };
 
@@ -196,8 +197,9 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
             float mw = spart[0][tid];
 #pragma unroll
             for (int q = 1; q < kInThreads / kInCh; ++q) mw = fmaxf(mw, spart[q][tid]);
-            stc[tid] = c0 + tid < g.C ? bin_exp(ia.x_absmax != nullptr ? ia.x_absmax[c0 + tid] : 1.0f) - bin_exp(mw)
-                                      : 0;
+            stc[tid] = c0 + tid < g.C
+                           ? bin_exp(x_bound(ia.x_absmax, ia.xpart, ia.xchunks, g.C_pad, c0 + tid)) - bin_exp(mw)
+                           : 0;
         }
         __syncthreads();
     }
@@ -306,7 +308,7 @@ static void filter_input_launch(unsigned n_in_grid, unsigned n_f_blocks, int f_g
 // transforms, dtype WG_F32 only).
 template <int M, int R, typename CT>
 static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
-                      const float* x_absmax) {
+                      const float* x_absmax, bool x_from_u) {
     constexpr int A = M + R - 1;
     constexpr int CS = 2 * (A | 1);
     constexpr bool f64 = sizeof(CT) == 8;
@@ -346,7 +348,7 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const int32_t* t_tab = reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.chan_offset);
     void* V = static_cast<char*>(ws) + L.v_offset;
     if (w == nullptr) {
-        const InputArgs ia{x, V, t_tab, nullptr, nullptr, 0, twb, n_twb, pair_stride, (int)n_blocks};
+        const InputArgs ia{x, V, t_tab, nullptr, nullptr, nullptr, 0, 0, twb, n_twb, pair_stride, (int)n_blocks};
 #define WG_IN(DT)                                                                                 \
     (structured ? input_launch<M, R, DT, true, CT>(grid, lds_bytes, s, ia, mt, rp, g)             \
                 : input_launch<M, R, DT, false, CT>(grid, lds_bytes, s, ia, mt, rp, g))
@@ -363,8 +365,10 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
         return last_launch("input_transform_kernel");
     }
     // the partial maxima of |w| (16-bit stage) are already in U (wg_filter_maxima)
-    const FilterArgs fa = filter_args(p, w, x_absmax, const_cast<void*>(U));
-    const InputArgs ia{x, V, t_tab, fa.part, x_absmax, fa.kchunks, twb, n_twb, pair_stride, (int)n_blocks};
+    const FilterArgs fa = x_from_u ? filter_args_xpart(p, w, const_cast<void*>(U))
+                                   : filter_args(p, w, x_absmax, const_cast<void*>(U));
+    const InputArgs ia{x,          V,           t_tab, fa.part, fa.x_absmax, fa.xpart, fa.kchunks, fa.xchunks,
+                       twb,        n_twb,       pair_stride, (int)n_blocks};
     const int fg = filter_groups(L);
     const unsigned n_f = (unsigned)fg * (unsigned)L.K_pad;
     if ((size_t)n_in_grid + n_f > (1u << 31)) return fail(WG_EUNSUPPORTED, "filter and input transform: grid too large");
@@ -387,22 +391,24 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
 
 template <int M, int R>
 static int input_dispatch(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
-                          const float* x_absmax) {
-    return p.f64t ? input_impl<M, R, double>(p, x, U, ws, s, w, x_absmax)
-                  : input_impl<M, R, float>(p, x, U, ws, s, w, x_absmax);
+                          const float* x_absmax, bool x_from_u) {
+    return p.f64t ? input_impl<M, R, double>(p, x, U, ws, s, w, x_absmax, x_from_u)
+                  : input_impl<M, R, float>(p, x, U, ws, s, w, x_absmax, x_from_u);
 }
 
 int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-#define WG_CASE_input(MM, RR) case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, nullptr, nullptr);
+#define WG_CASE_input(MM, RR) \
+    case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, nullptr, nullptr, false);
     WG_DISPATCH(input)
 #undef WG_CASE_input
 }
 
 int launch_filter_input(const Plan& p, const float* w, const float* x_absmax, const float* x, void* U, void* ws,
-                        void* stream) {
+                        void* stream, bool x_from_u) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-#define WG_CASE_fi(MM, RR) case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, w, x_absmax);
+#define WG_CASE_fi(MM, RR) \
+    case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, w, x_absmax, x_from_u);
     WG_DISPATCH(fi)
 #undef WG_CASE_fi
 }

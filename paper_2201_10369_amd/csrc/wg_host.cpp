@@ -215,12 +215,10 @@ int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, in
     const size_t ubytes = E * L.K_pad * L.C_pad * L.elem_bytes;
     L.scale_offset = round_up(ubytes, 256);
     L.chan_offset = round_up(L.scale_offset + E * L.C_pad * sizeof(int32_t), 256);
-    // scratch after the per-channel table: partial maxima of |w| per 8 filters
-    const size_t kchunks = (size_t)(K + 7) / 8;
-    L.filter_bytes = dtype == WG_F32
-                         ? round_up(ubytes, 256)
-                         : round_up(L.chan_offset + L.C_pad * sizeof(int32_t) + 256 +
-                                        kchunks * L.C_pad * sizeof(float), 256);
+    // scratch after the per-channel table: partial maxima of |w| per 8
+    // filters, then partial maxima of |x| per chunk of images
+    L.filter_bytes = dtype == WG_F32 ? round_up(ubytes, 256)
+                                     : round_up(xpart_offset(L) + (size_t)kXChunks * L.C_pad * sizeof(float), 256);
     L.v_offset = 0;
     L.m_offset = round_up(E * L.P_pad * L.C_pad * L.elem_bytes, 256);
     L.workspace_bytes = round_up(L.m_offset + E * L.K_pad * L.P_pad * sizeof(float), 256);
@@ -308,6 +306,20 @@ int wg_transform_filters_and_input(const wg_plan* plan, const float* w, const fl
     int st = check_ws(p, ws, ws_bytes, "wg_transform_filters_and_input");
     if (st != WG_OK) return st;
     return launch_filter_input(p, w, x_absmax, x, U, ws, stream);
+}
+
+int wg_layer_maxima(const wg_plan* plan, const float* w, const float* x, void* U, wg_stream_t stream) {
+    if (!plan || !w || !x || !U) return fail(WG_EINVAL, "wg_layer_maxima: null pointer");
+    return launch_layer_maxima(*reinterpret_cast<const Plan*>(plan), w, x, U, stream);
+}
+
+int wg_transform_layer(const wg_plan* plan, const float* w, const float* x, void* U, void* ws, size_t ws_bytes,
+                       wg_stream_t stream) {
+    if (!plan || !w || !x || !U) return fail(WG_EINVAL, "wg_transform_layer: null pointer");
+    const Plan& p = *reinterpret_cast<const Plan*>(plan);
+    int st = check_ws(p, ws, ws_bytes, "wg_transform_layer");
+    if (st != WG_OK) return st;
+    return launch_filter_input(p, w, nullptr, x, U, ws, stream, p.L.dtype != WG_F32);
 }
 
 int wg_hadamard_gemm(const wg_plan* plan, const void* U, void* ws, size_t ws_bytes,

@@ -8,14 +8,12 @@ by the exact sweep, which has the final word.
 
 Everything numeric runs in the HIP library: the sweep (wg_sweep_*), training
 (wg_mlp_train), inference (wg_mlp_predict) and selection (wg_topk_min).  This
-module only arranges the calls.  Random inputs (parameter pairs, sample
-counts, initial weights, minibatch orders) come from the `synth` module.
+module only arranges the calls.  Every random input (sample pools, parameter
+pairs, sample counts, initial weights, minibatch orders) is an argument.
 """
 from __future__ import annotations
 
 import numpy as np
-
-import synth
 
 from . import wg
 
@@ -27,11 +25,12 @@ def _torch():
     return torch
 
 
-def sweep_for(m, r, dims=2, pool_n=POOL, max_cand=65536, seed=2):
-    """A sweep object for one tile size with its own seeded sample pool."""
+def sweep_for(m, r, d_pool, g_pool, dims=2, max_cand=65536):
+    """A sweep object for one tile size over the given sample pool (host
+    float32 arrays: d_pool n x alpha (x alpha), g_pool n x r (x r))."""
     torch = _torch()
-    d, g = synth.tile_pool(pool_n, m + r - 1, r, dims, seed=seed)
-    return wg.Sweep(m, r, dims, torch.from_numpy(d).cuda(), torch.from_numpy(g).cuda(), max_cand)
+    return wg.Sweep(m, r, dims, torch.from_numpy(np.ascontiguousarray(d_pool, np.float32)).cuda(),
+                    torch.from_numpy(np.ascontiguousarray(g_pool, np.float32)).cuda(), max_cand)
 
 
 def score(S, c1, c2, counts):
@@ -50,20 +49,28 @@ def score(S, c1, c2, counts):
     return np.concatenate(means)
 
 
-def make_dataset(sizes, n_per_size, dims=2, seed=5, sweeps=None):
-    """Labelled samples: (c1, c2) log-uniform over [0.05, 20]^2, each scored by
-    the sweep of its size on an uneven 500-2000 sample prefix; the label is
-    log10 of the mean absolute error, capped at 0 (flagged sets get 0)."""
+def make_dataset(sweeps, pairs, counts):
+    """Labelled samples for the tile sizes keyed in `pairs`: each (c1, c2) of
+    pairs[(m, r)] (n x 2) scored by sweeps[(m, r)] on the pool prefix
+    counts[(m, r)][i]; the label is log10 of the mean absolute error, capped
+    at 0 (flagged sets get 0)."""
     rows = []
-    for k, (m, r) in enumerate(sizes):
-        S = sweeps[(m, r)] if sweeps is not None else sweep_for(m, r, dims)
-        pairs = synth.surrogate_pairs(n_per_size, seed=seed * 1000 + k)
-        counts = synth.sample_counts(n_per_size, seed=seed * 1000 + k)
-        mean = score(S, pairs[:, 0], pairs[:, 1], counts)
+    for (m, r), pr in pairs.items():
+        mean = score(sweeps[(m, r)], pr[:, 0], pr[:, 1], counts[(m, r)])
         lab = np.minimum(np.log10(np.where(np.isfinite(mean) & (mean > 0), mean, 1.0)), 0.0)
-        rows.append((pairs[:, 0], pairs[:, 1], np.full(n_per_size, m), np.full(n_per_size, r), lab))
+        n = len(pr)
+        rows.append((pr[:, 0], pr[:, 1], np.full(n, m), np.full(n, r), lab))
     c1, c2, mm, rr, lab = (np.concatenate(x) for x in zip(*rows))
     return dict(c1=c1, c2=c2, m=mm.astype(np.int32), r=rr.astype(np.int32), target=lab.astype(np.float32))
+
+
+def select(data, keep):
+    """The samples of `data` where the boolean mask `keep` is set."""
+    return {k: v[keep] for k, v in data.items()}
+
+
+def concat(*parts):
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
 
 
 class Model:
@@ -74,20 +81,25 @@ class Model:
         self.params, self.mean, self.std = params, mean, std
 
 
-def train(data, epochs=20, batch=4096, lr=1e-3, seed=7):
-    """Adam on the mean squared error of standardised log10 errors; returns
-    (Model, per-step losses)."""
+def train(data, init_params, perm, batch=4096, lr=1e-3):
+    """Adam on the mean squared error of standardised log10 errors from the
+    initial parameters init_params ([(W, b), ...] per layer, W (out, in)),
+    one epoch per row of perm (int32 permutations of the n samples);
+    returns (Model, per-step losses)."""
     torch = _torch()
     n = len(data["c1"])
+    perm = np.ascontiguousarray(perm, np.int32)
+    if perm.ndim != 2 or perm.shape[1] != n:
+        raise ValueError("perm must have shape (epochs, n)")
     t = np.asarray(data["target"], np.float64)
     mean, std = float(t.mean()), float(t.std()) or 1.0
-    params = torch.from_numpy(wg.mlp_pack(synth.mlp_init((4, 128, 128, 128, 1), seed=seed))).cuda()
+    params = torch.from_numpy(wg.mlp_pack(init_params)).cuda()
     adam = torch.zeros(2 * params.numel(), dtype=torch.float32, device="cuda")
-    perm = torch.from_numpy(synth.minibatch_order(n, epochs, seed=seed + 1)).cuda()
+    permd = torch.from_numpy(perm).cuda()
     dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in data.items() if k != "target"}
     tz = torch.from_numpy(((t - mean) / std).astype(np.float32)).cuda()
     ctx = wg.Mlp(batch)
-    losses = ctx.train(params, adam, 1, lr, dev["c1"], dev["c2"], dev["m"], dev["r"], tz, perm, batch)
+    losses = ctx.train(params, adam, 1, lr, dev["c1"], dev["c2"], dev["m"], dev["r"], tz, permd, batch)
     return Model(params, mean, std), losses
 
 

@@ -72,6 +72,8 @@ _SIGS = {
     "wg_filter_maxima": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "wg_transform_filters_and_input": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                                c_void_p]),
+    "wg_layer_maxima": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "wg_transform_layer": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "wg_hadamard_gemm": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "wg_output_transform": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "wg_channel_absmax": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p]),
@@ -301,6 +303,21 @@ class Plan:
                                                     _tptr(x, torch.float32, "x"), _tptr(U, None, "U"),
                                                     _tptr(ws, None, "ws"), ws.numel() * ws.element_size(),
                                                     _stream(stream)))
+
+    def layer_maxima(self, w, x, U, stream=None):
+        """Per-batch 16-bit scaling, first call: partial maxima of |w| and
+        |x| into U (no-op for f32)."""
+        torch = _torch()
+        _check(lib().wg_layer_maxima(self._h, _tptr(w, torch.float32, "w"), _tptr(x, torch.float32, "x"),
+                                     _tptr(U, None, "U"), _stream(stream)))
+
+    def transform_layer(self, w, x, U, ws, stream=None):
+        """Per-batch 16-bit scaling, second call: filter and input transforms
+        in one launch with max |x_c| from the partial maxima in U."""
+        torch = _torch()
+        _check(lib().wg_transform_layer(self._h, _tptr(w, torch.float32, "w"), _tptr(x, torch.float32, "x"),
+                                        _tptr(U, None, "U"), _tptr(ws, None, "ws"), ws.numel() * ws.element_size(),
+                                        _stream(stream)))
 
     def hadamard_gemm(self, U, ws, stream=None):
         _check(lib().wg_hadamard_gemm(self._h, _tptr(U, None, "U"), _tptr(ws, None, "ws"),

@@ -98,12 +98,22 @@ def splitmix64(x):
     return z ^ (z >> 31)
 
 
+def splitmix64_array(x):
+    """splitmix64 over a uint64 array (numpy's uint64 arithmetic wraps modulo
+    2^64, which is what the published definition asks for)."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(x, dtype=np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
 def sample_counts(n_cand, seed=2, lo=500, hi=2000):
     """Uneven per-candidate sample counts in [lo, hi]: candidate i scores the
     pool prefix [0, n_i) with n_i = lo + splitmix64(seed ^ i) mod (hi-lo+1)."""
     span = hi - lo + 1
-    return np.array([lo + splitmix64((seed ^ i) & MASK64) % span
-                     for i in range(n_cand)], dtype=np.int32)
+    i = np.arange(n_cand, dtype=np.uint64) ^ np.uint64(seed & MASK64)
+    return (lo + splitmix64_array(i) % np.uint64(span)).astype(np.int32)
 
 
 def candidate_grid(n=4096, lo=0.05, hi=20.0):
@@ -130,6 +140,17 @@ def surrogate_pairs(n, seed=5, lo=0.05, hi=20.0):
     g = np.random.default_rng(seed)
     u = g.uniform(np.log(lo), np.log(hi), size=(n, 2))
     return np.exp(u)
+
+
+def surrogate_inputs(sizes, n_per_size, seed=5):
+    """Per tile size (m, r) of `sizes` (k-th entry): n_per_size (c1, c2)
+    pairs and pool-prefix counts, both keyed on seed * 1000 + k.  Returns
+    two dicts keyed by (m, r)."""
+    pairs, counts = {}, {}
+    for k, s in enumerate(sizes):
+        pairs[tuple(s)] = surrogate_pairs(n_per_size, seed=seed * 1000 + k)
+        counts[tuple(s)] = sample_counts(n_per_size, seed=seed * 1000 + k)
+    return pairs, counts
 
 
 def mlp_init(widths, seed=7):

@@ -91,6 +91,19 @@ CASES = [
     (6, 5, (10, 1.272, 2.099), 1, 8, 9, 15, 11, "valid"),
     # points without 0: the kernels for general zero patterns
     (4, 3, ("pts", (-2.0, -1.0, -0.5, 0.5, 1.5)), 1, 20, 12, 11, 10, "same"),
+    # the other compiled sizes: every (m, r) the library accepts runs here
+    (1, 3, ("pts", (0.0, -1.0)), 2, 9, 7, 5, 6, "same"),
+    (3, 3, (5, 1.5, 1.0), 1, 17, 11, 10, 9, "same"),
+    (5, 3, (7, 1.6, 2.5), 1, 12, 13, 12, 14, "valid"),
+    (7, 3, (9, 1.24, 0.356), 1, 10, 9, 16, 15, "same"),
+    (8, 3, (10, 1.287, 0.338), 1, 9, 10, 17, 18, "same"),
+    (1, 5, (5, 2.0, 1.0), 1, 8, 6, 7, 9, "same"),
+    (2, 5, (6, 1.8, 1.0), 2, 11, 9, 8, 9, "valid"),
+    # (alpha 9..12 are ill-conditioned: their layers are large enough for the
+    # error each order reports to be pinned to a few percent)
+    (5, 5, (9, 1.3, 2.0), 2, 7, 9, 26, 26, "same"),
+    (7, 5, ("pts", (0.0, -1.0, 1.0, -0.5, 0.5, -2.0, 2.0, -1.5, 1.5, -0.25)), 2, 6, 5, 29, 29, "same"),
+    (8, 5, ("pts", (0.0, -1.0, 1.0, -0.5, 0.5, -2.0, 2.0, -1.5, 1.5, -0.25, 0.75)), 2, 5, 6, 36, 36, "valid"),
 ]
 
 
@@ -157,8 +170,47 @@ def test_filter_and_input_in_one_launch_match_separate_calls(case, dtype):
     assert torch.equal(plan.view_V(ws2)[:, :P], plan.view_V(ws)[:, :P])
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", CASES[:3] + [CASES[4], CASES[9], (6, 3, (8, 2.0, 1.0), 11, 20, 9, 13, 7, "same")])
+def test_per_batch_maxima_match_explicit_absmax(case, dtype):
+    """The per-batch scaling calls (wg_layer_maxima, then wg_transform_layer:
+    partial maxima of |w| and |x| in one launch, both transforms in the next)
+    write exactly the U', scale tables and V' of wg_channel_absmax,
+    wg_filter_maxima and wg_transform_filters_and_input with those maxima,
+    into buffers that start out filled with garbage (N = 11 gives image
+    chunks of two with a ragged and two empty chunks; 13 x 7 planes are not
+    whole 16-byte vectors)."""
+    wg = _wg()
+    m, r, fam, N, C, K, H, W, padding = case
+    pts = _pts(fam)
+    x, w = synth.layer_inputs(N, C, K, H, W, r, "normal")
+    # channel magnitudes over ten binades, so the exponents differ per channel
+    x = np.ascontiguousarray(x * (2.0 ** (np.arange(C) % 11 - 5)).astype(np.float32)[None, :, None, None])
+    plan = wg.Plan(m, r, pts, N, C, K, H, W, padding, dtype)
+    xd, wd = _dev(x), _dev(w)
+    ax = wg.channel_absmax(xd)
+    assert np.array_equal(_host(ax), np.abs(x).max(axis=(0, 2, 3)))
+    U1, ws1 = plan.empty_filters(), plan.empty_workspace()
+    plan.filter_maxima(wd, U1)
+    plan.transform_filters_and_input(wd, xd, U1, ws1, ax if dtype in SIXTEEN else None)
+    U2 = plan.empty_filters().fill_(0x7D)
+    ws2 = plan.empty_workspace().fill_(0x7D)
+    plan.layer_maxima(wd, xd, U2)
+    plan.transform_layer(wd, xd, U2, ws2)
+    torch.cuda.synchronize()
+    assert torch.equal(plan.view_U(U2), plan.view_U(U1))
+    if dtype in SIXTEEN:
+        assert torch.equal(plan.view_scales(U2), plan.view_scales(U1))
+        mats = _oracle_mats(pts, m, r)
+        a = plan.layout["alpha"]
+        s = _host(plan.view_scales(U2)).reshape(a, a, -1)[:, :, :C]
+        assert np.array_equal(s, fp.scale_exponents(mats, w, np.abs(x).max(axis=(0, 2, 3))))
+    P = plan.layout["P"]
+    assert torch.equal(plan.view_V(ws2)[:, :P], plan.view_V(ws1)[:, :P])
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "mixed"])
-@pytest.mark.parametrize("case", CASES[:4] + CASES[-1:])
+@pytest.mark.parametrize("case", CASES[:4] + [CASES[6], CASES[-1]])
 def test_gemm_and_output_transform(case, dtype):
     """The MFMA channel-sum GEMM is within the summation-order bound of the
     oracle's ascending sum; the output transform, fed the oracle's own M, is
@@ -249,15 +301,21 @@ def test_forward_matches_oracle(case, dtype):
     bound = fp.assemble_tiles(_propagated_bound(mats, Uo, Vo, Mo), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
     diff = np.abs(y.astype(np.float64) - yo)
     assert np.all(diff <= bound), (diff.max(), bound[diff > bound][:4])
+    _check_error_gate(y, yo, x, w, padding, dtype)
+
+
+def _check_error_gate(y, yo, x, w, padding, dtype):
+    """The float32 parity gate: relative L1 to the oracle at most 1e-5 where
+    the oracle's own error against float64 is at most 3e-6; where it exceeds
+    3e-6 (16-bit stage, ill-conditioned points) two valid summation orders
+    may differ by more than 1e-5, and the error the GPU reports must match
+    the oracle's within 5% plus the sampling spread 1/sqrt(outputs) of a
+    small layer."""
     e = fp.l1_errors(y, yo)
-    if dtype in ("f32", "mixed"):
-        assert e["rel_l1"] <= 1e-5
-    # where the oracle's own error against float64 exceeds 3e-6 (16-bit stage,
-    # ill-conditioned points) two valid summation orders may differ by more
-    # than 1e-5; there the error the GPU reports must match the oracle's
-    # within 5% plus the sampling spread 1/sqrt(outputs) of a small layer
     y64 = fp.direct_layer_f64(x, w, padding)
     eg, eo = fp.l1_errors(y, y64)["rel_l1"], fp.l1_errors(yo, y64)["rel_l1"]
+    if dtype in ("f32", "mixed") and eo <= 3e-6:
+        assert e["rel_l1"] <= 1e-5
     if dtype == "mixed":
         # float64 transforms leave mostly the float32 channel sums, whose
         # order differs (MFMA against ascending): the errors are of the same
@@ -359,19 +417,29 @@ def test_full_size_sampled_tiles(name, fam, dtype):
     """At the full layer sizes the GPU output on 48 sampled tiles (including the
     first, the last and ragged edge tiles) is within the propagated bound of the
     oracle and, in float32, within 1e-5 relative L1; the float64 direct
-    convolution agrees with the oracle at 200 sampled outputs."""
+    convolution agrees with the oracle at 200 sampled outputs.  The 16-bit
+    forms are checked in the configuration the benchmark times: the
+    per-channel input maxima measured on the device from this very input."""
     wg = _wg()
     cfg = synth.LAYERS[name]
     N, C, K, H, W, r, m = (cfg[k] for k in ("N", "C", "K", "H", "W", "r", "m"))
     pts = wg.family_points(*fam)
-    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, "same", dtype, cfg["dist"])
+    x, w = synth.layer_inputs(N, C, K, H, W, r, cfg["dist"])
+    plan = wg.Plan(m, r, pts, N, C, K, H, W, "same", dtype)
+    xd, wd = _dev(x), _dev(w)
+    ax, axd = None, None
+    if dtype in SIXTEEN:
+        axd = wg.channel_absmax(xd)
+        ax = _host(axd)
+        assert np.array_equal(ax, np.abs(x).max(axis=(0, 2, 3)))
+    U = plan.transform_filters(wd, axd)
     L = plan.layout
     y = plan.forward(xd, U)
     rng = np.random.default_rng(17)
     P = L["P"]
     tiles = np.unique(np.concatenate([[0, P - 1, L["Tw"] - 1, P - L["Tw"]], rng.integers(0, P, 44)]))
     mats = _oracle_mats(pts, m, r, dtype)
-    Uo, Vo = fp.transformed_operands(x, w, mats, m, "same", dtype, tiles=tiles)
+    Uo, Vo = fp.transformed_operands(x, w, mats, m, "same", dtype, tiles=tiles, x_absmax=ax)
     Mo = fp.hadamard_channel_sum(Uo, Vo)
     Yo = _out_xform(mats, Mo, dtype)                       # (K, S, m, m)
     bound = _propagated_bound(mats, Uo, Vo, Mo)
@@ -392,17 +460,24 @@ def test_full_size_sampled_tiles(name, fam, dtype):
     rel = np.sum(diffs) / np.sum(refs)
     if dtype in ("f32", "mixed"):
         assert rel <= 1e-5
-    # the launch sequence the benchmark times (filter and input transforms in
-    # one launch, then GEMM and output transform) gives the same output
-    U2 = plan.empty_filters()
-    ws2 = plan.empty_workspace()
-    y2 = plan.empty_output()
-    plan.filter_maxima(wd, U2)
-    plan.transform_filters_and_input(wd, xd, U2, ws2)
-    plan.hadamard_gemm(U2, ws2)
-    plan.output_transform(ws2, y2)
-    torch.cuda.synchronize()
-    assert torch.equal(y2, y)
+    # the launch sequence the benchmark times (the partial maxima of |w| and
+    # |x| in one launch, filter and input transforms in the next, then GEMM
+    # and output transform) and the one with explicit maxima give the same
+    # output
+    for per_batch in (True, False):
+        U2 = plan.empty_filters()
+        ws2 = plan.empty_workspace()
+        y2 = plan.empty_output()
+        if per_batch:
+            plan.layer_maxima(wd, xd, U2)
+            plan.transform_layer(wd, xd, U2, ws2)
+        else:
+            plan.filter_maxima(wd, U2)
+            plan.transform_filters_and_input(wd, xd, U2, ws2, axd)
+        plan.hadamard_gemm(U2, ws2)
+        plan.output_transform(ws2, y2)
+        torch.cuda.synchronize()
+        assert torch.equal(y2, y)
     # float64 direct convolution at sampled outputs
     y64 = wg.direct_conv_f64(xd, wd, "same")
     coords = np.stack([rng.integers(0, N, 200), rng.integers(0, K, 200), rng.integers(0, L["Hout"], 200),
@@ -412,3 +487,64 @@ def test_full_size_sampled_tiles(name, fam, dtype):
     ref = fp.direct_points_f64(x, w, "same", coords)
     got = _host(y64)[coords[:, 0], coords[:, 1], coords[:, 2], coords[:, 3]]
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# ill-conditioned points and the range of the 16-bit stage
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f32", "mixed", "f16"])
+@pytest.mark.parametrize("c", [1.1, 1.05])
+def test_ill_conditioned_points_match_oracle(c, dtype):
+    """F(4x4,3x3) with {0, inf, +-c, +-1/c} near c = 1, where the oracle's own
+    error against float64 exceeds 3e-6: the GPU layer stays within the
+    propagated summation-order bound of the oracle elementwise, and the error
+    it reports against float64 is the oracle's within 5% (plus the sampling
+    spread of the layer)."""
+    wg = _wg()
+    m, r, N, C, K, H, W = 4, 3, 2, 48, 40, 17, 15
+    pts = wg.family_points(6, c, 1.0)
+    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, "same", dtype)
+    mats = _oracle_mats(pts, m, r, dtype)
+    L = plan.layout
+    y = _host(plan.forward(xd, U))
+    Uo, Vo = fp.transformed_operands(x, w, mats, m, "same", dtype)
+    Mo = fp.hadamard_channel_sum(Uo, Vo)
+    yo = fp.assemble_tiles(_out_xform(mats, Mo, dtype), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
+    bound = fp.assemble_tiles(_propagated_bound(mats, Uo, Vo, Mo), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
+    assert np.all(np.abs(y.astype(np.float64) - yo) <= bound)
+    y64 = fp.direct_layer_f64(x, w, "same")
+    eo = fp.l1_errors(yo, y64)["rel_l1"]
+    if dtype != "mixed":
+        assert eo > 3e-6                        # the regime the 5% gate is for
+    _check_error_gate(y, yo, x, w, "same", dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("c", [0.05, 20.0])
+def test_16bit_stage_does_not_overflow_at_the_ends_of_the_sweep(c, dtype):
+    """F(6x6,3x3) with {0, inf, +-1, +-c, +-1/c} at the ends of the swept
+    range, c = 0.05 and 20 (transform entries up to 20^6): the power-of-two
+    scaling keeps every operand of the 16-bit stage finite (float16 tops out
+    at 65504), the scaled operands are the oracle's, and the output is
+    finite and within the propagated bound of the oracle."""
+    wg = _wg()
+    m, r, N, C, K, H, W = 6, 3, 1, 24, 16, 20, 19
+    pts = wg.family_points(8, c, 1.0)
+    plan, x, w, xd, wd, U, ax = _setup(m, r, pts, N, C, K, H, W, "same", dtype, x_absmax=True)
+    mats = _oracle_mats(pts, m, r)
+    L = plan.layout
+    ws = plan.empty_workspace()
+    y = plan.forward(xd, U, ws=ws)
+    Ug = plan.view_U(U)[:, :K, :C].float()
+    Vg = plan.view_V(ws)[:, :L["P"], :C].float()
+    assert bool(torch.isfinite(Ug).all()) and bool(torch.isfinite(Vg).all())
+    Uo, Vo = fp.transformed_operands(x, w, mats, m, "same", dtype, x_absmax=ax)
+    assert np.isfinite(Uo).all() and np.isfinite(Vo).all()
+    a = L["alpha"]
+    assert np.array_equal(_host(Vg).reshape(a, a, L["P"], C).transpose(2, 3, 0, 1), Vo)
+    yh = _host(y)
+    assert np.isfinite(yh).all()
+    Mo = fp.hadamard_channel_sum(Uo, Vo)
+    yo = fp.assemble_tiles(fp.xform2d(mats[0], Mo), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
+    bound = fp.assemble_tiles(_propagated_bound(mats, Uo, Vo, Mo), N, L["Th"], L["Tw"], L["Hout"], L["Wout"])
+    assert np.all(np.abs(yh.astype(np.float64) - yo) <= bound)

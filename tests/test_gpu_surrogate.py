@@ -79,10 +79,21 @@ def test_adam_training_matches_oracle():
         ref_losses.append(loss)
         p64 = omlp.adam_step(p64, grads, state, step + 1, lr=1e-3)
     assert np.allclose(losses.cpu().numpy(), ref_losses, rtol=1e-4)
-    got = np.concatenate([np.ravel(a) for pair in wg.mlp_unpack(P.cpu().numpy()) for a in pair])
-    ref = omlp.flatten(p64)
-    moved = np.abs(ref - wg.mlp_pack(params).astype(np.float64))
-    assert np.mean(np.abs(got - ref) <= 1e-2 * moved + 1e-7) > 0.99
+    # every parameter group separately (W1, b1, ..., W4, b4): its distance to
+    # the oracle is a small part of how far the group moved, and nearly every
+    # entry is within 1% of its own move (Adam's normalised step can turn the
+    # sign of a few updates whose gradient is at float32 rounding level)
+    got = wg.mlp_unpack(P.cpu().numpy())
+    for li, ((gW, gb), (oW, ob), (iW, ib)) in enumerate(zip(got, p64, params)):
+        for name, g_, o_, i_ in (("W", gW, oW, iW), ("b", gb, ob, ib)):
+            moved = np.abs(o_ - i_.astype(np.float64))
+            d = np.abs(g_.astype(np.float64) - o_)
+            ratio = np.linalg.norm(d) / np.linalg.norm(moved)
+            frac = np.mean(d <= 1e-2 * moved + 1e-7)
+            print(f"layer {li + 1} {name}: |got-ref|/|moved| = {ratio:.2e}, within 1% of the move: {frac:.4f}")
+            assert np.linalg.norm(moved) > 0
+            assert ratio <= 2e-2, (li, name, ratio)
+            assert frac >= (0.98 if g_.size > 1 else 1.0), (li, name, frac)
 
 
 def test_topk_matches_numpy():
@@ -107,8 +118,9 @@ def test_topk_infinities_nan_and_short_input():
     assert list(idx[:2]) == [2, 8] and list(idx[5:8]) == [4, 1, 5]
 
 
-def test_surrogate_gain_over_plain_and_random_search():
-    """Hold out F(4x4,3x3): the surrogate is trained on sweep errors of the
+@pytest.mark.parametrize("m,r", [(4, 3), (6, 5)])
+def test_surrogate_gain_over_plain_and_random_search(m, r):
+    """Hold out one tile size: the surrogate is trained on sweep errors of the
     other 11 tile sizes (F(2..8,3), F(2..6,5); 2D), plus 64 exact samples of
     the held-out size, all of which count as evaluations.  Its 32 best
     proposals on a 4096-point grid over c in [0.05, 20] and three 32-point
@@ -116,15 +128,19 @@ def test_surrogate_gain_over_plain_and_random_search():
     than the 4096 of the plain sweep) the best error is within 1% of the plain
     sweep's best, and no worse than random search with the same budget."""
     from paper_2201_10369_amd import surrogate as sg
-    m, r = 4, 3
-    others = [s for s in synth.SURROGATE_SIZES if s != (m, r)]
-    data = sg.make_dataset(others, 83334)
-    shots = sg.make_dataset([(m, r)], 64, seed=11)
-    both = {k: np.concatenate([data[k], shots[k]]) for k in data}
-    model, losses = sg.train(both, epochs=20, batch=4096)
+    sizes = synth.SURROGATE_SIZES
+    sweeps = {s: sg.sweep_for(*s, *synth.tile_pool(sg.POOL, s[0] + s[1] - 1, s[1], 2)) for s in sizes}
+    others = [s for s in sizes if s != (m, r)]
+    pairs, counts = synth.surrogate_inputs(sizes, 83334, seed=5)
+    data = sg.make_dataset(sweeps, {s: pairs[s] for s in others}, {s: counts[s] for s in others})
+    pairs, counts = synth.surrogate_inputs(sizes, 64, seed=11)
+    shots = sg.make_dataset(sweeps, {(m, r): pairs[(m, r)]}, {(m, r): counts[(m, r)]})
+    both = sg.concat(data, shots)
+    n = len(both["c1"])
+    model, losses = sg.train(both, synth.mlp_init(omlp.WIDTHS, seed=7), synth.minibatch_order(n, 20, seed=8))
     losses = losses.cpu().numpy()
     assert losses[-20:].mean() < 0.2 * losses[:20].mean()
-    S = sg.sweep_for(m, r)
+    S = sweeps[(m, r)]
     grid = synth.candidate_grid(4096)
     ones = np.ones_like(grid)
     plain = sg.score(S, grid, ones, np.full(4096, sg.POOL))
@@ -135,7 +151,8 @@ def test_surrogate_gain_over_plain_and_random_search():
     assert used * 10 <= 4096
     rng = np.random.default_rng(12)
     rand = sg.score(S, grid[rng.choice(4096, used, replace=False)], np.ones(used), np.full(used, sg.POOL))
-    print(f"plain best {best_plain:.4e} at c={grid[np.argmin(plain)]:.4f}; surrogate {err:.4e} at c={c1:.4f} "
-          f"with {used} evaluations; random search {np.min(rand):.4e}; final loss {losses[-20:].mean():.4f}")
+    print(f"F({m},{r}): plain best {best_plain:.4e} at c={grid[np.argmin(plain)]:.4f}; surrogate {err:.4e} "
+          f"at c={c1:.4f} with {used} evaluations; random search {np.min(rand):.4e}; "
+          f"final loss {losses[-20:].mean():.4f}")
     assert err <= 1.01 * best_plain
     assert err <= np.min(rand)
