@@ -281,8 +281,6 @@ def bench_surrogate(torch):
     shots = sg.make_dataset(sweeps, *synth.surrogate_inputs(sizes, 64, seed=11))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    grid = synth.candidate_grid(4096)
-    ones = np.ones_like(grid)
     per_size, model0, train_s, n_train = {}, None, None, None
     for (m, r) in HELD_OUT:
         here = lambda d: (d["m"] == m) & (d["r"] == r)          # noqa: E731
@@ -296,15 +294,18 @@ def bench_surrogate(torch):
         if model0 is None:
             model0, train_s, n_train = model, tb - ta, n
         S = sweeps[(m, r)]
-        plain = sg.score(S, grid, ones, np.full(4096, sg.POOL))
-        err, c1, _, used = sg.guided_search(model, S, m, r, grid, ones)
+        pc1, pc2, qc1, qc2, two = sg.search_grids(m + r - 1)
+        plain = sg.score(S, pc1, pc2, np.full(4096, sg.POOL))
+        err, c1, c2, used = sg.guided_search(model, S, m, r, qc1, qc2, refine_c2=two)
         used += 64
         rng = np.random.default_rng(12)
-        rand = sg.score(S, grid[rng.choice(4096, used, replace=False)], np.ones(used), np.full(used, sg.POOL))
+        pick = rng.choice(4096, used, replace=False)
+        rand = sg.score(S, pc1[pick], pc2[pick], np.full(used, sg.POOL))
+        jb = int(np.argmin(plain))
         per_size[f"F({m}x{m},{r}x{r})"] = {
-            "surrogate_best": float(err), "surrogate_c": float(c1), "evaluations": int(used),
-            "plain_best": float(np.min(plain)), "plain_c": float(grid[int(np.argmin(plain))]),
-            "plain_evaluations": 4096, "random_best": float(np.min(rand)),
+            "surrogate_best": float(err), "surrogate_c": [float(c1), float(c2)], "evaluations": int(used),
+            "plain_best": float(np.min(plain)), "plain_c": [float(pc1[jb]), float(pc2[jb])],
+            "plain_evaluations": 4096, "random_best": float(np.min(rand)), "two_parameter": two,
             "ratio": round(float(err) / float(np.min(plain)), 5),
             "within_1pct": bool(err <= 1.01 * np.min(plain)), "final_loss": float(losses[-20:].mean().item())}
     # the two-parameter families of F(7x7,3x3) and F(8x8,3x3) (trained on):

@@ -257,21 +257,20 @@ int wg_transform_filters_and_input(const wg_plan* plan, const float* w, const fl
  * when max |x_c| is not known beforehand (the scaling of the Hadamard stage
  * then follows each batch; Section 4.1 amortises both transforms, so they
  * share one launch):
- *   wg_layer_maxima:    for WG_F16 / WG_BF16 the maxima of |w| over chunks
- *                       of 8 filters and of |x| over chunks of images
- *                       (min(N, 8) chunks of ceil(N / min(N, 8)) images),
- *                       per channel, into the library scratch of U; nothing
- *                       to do for WG_F32.
+ *   wg_layer_maxima:    for WG_F16 / WG_BF16, in one launch with one block
+ *                       per channel: max |x_c| over the batch and max |w_c|
+ *                       over the filters, and from them the per-channel part
+ *                       t[c] = E(max |x_c|) - E(max |w_c|) and the scale
+ *                       table s[e][c] of wg_transform_filters, written into
+ *                       U; nothing to do for WG_F32.
  *   wg_transform_layer: then the filter and input transforms in one launch
- *                       as wg_transform_filters_and_input, with
- *                       x_absmax[c] = the maximum of those partial maxima of
- *                       |x| (for WG_F32: wg_transform_filters_and_input with
- *                       x_absmax NULL).
+ *                       as wg_transform_filters_and_input, both reading t[c]
+ *                       from U (for WG_F32: wg_transform_filters_and_input
+ *                       with x_absmax NULL).
  * U, the scale tables and V' equal bit for bit what wg_channel_absmax,
- * wg_filter_maxima and wg_transform_filters_and_input with that x_absmax
- * write, since a maximum does not depend on how it is split.
- * x, w: device float32 as for the other calls; U: device, filter_bytes;
- * ws: device workspace of at least workspace_bytes.
+ * wg_filter_maxima and wg_transform_filters_and_input with those maxima
+ * write.  x, w: device float32 as for the other calls; U: device,
+ * filter_bytes; ws: device workspace of at least workspace_bytes.
  * Errors: WG_EINVAL (null pointer), WG_EWORKSPACE, WG_EUNSUPPORTED (the
  * limits of wg_transform_filters_and_input), WG_EHIP. */
 int wg_layer_maxima(const wg_plan* plan, const float* w, const float* x, void* U, wg_stream_t stream);

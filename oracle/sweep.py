@@ -5,8 +5,8 @@ F(4,3) with {-1/c, -c, 0, c, 1/c} for c in [1.1, 2.5], step 1e-3) and
 Section 6.3 searches many such combinations; each evaluation scores float32
 Winograd results on random inputs against a float64 direct convolution.
 
-For every candidate: build the family's points, the exact matrices and their
-float32 roundings (toomcook / fp), evaluate float32 tiles on the first n_i
+For every candidate: build the family's points (as float64 numbers), the
+exact matrices of those points and their float32 roundings (toomcook / fp), evaluate float32 tiles on the first n_i
 samples of a shared pool (common random numbers), and accumulate the L1 error
 against the float64 reference.  A candidate whose points coincide is
 reported with infinite error.
@@ -27,9 +27,12 @@ def pool_reference(d, g):
 
 
 def candidate_error(alpha, m, r, dims, c1, c2, d, g, yref, n):
-    """L1 error sums of one candidate on the pool prefix [0, n)."""
+    """L1 error sums of one candidate on the pool prefix [0, n).  The
+    family's points are float64 numbers (1/c rounded to the nearest float64,
+    as for the points of a layer plan); the matrices are built exactly from
+    them."""
     try:
-        pts = tc.family_points(alpha, c1, c2)
+        pts = tc.family_points_f64(alpha, c1, c2)
         mats = fp.mats_f32(pts, m, r)
     except tc.SingularPoints:
         return dict(abs_sum=math.inf, ref_sum=float(np.abs(yref[:n]).sum()),

@@ -177,6 +177,14 @@ def family_points(alpha, c1, c2=None):
     return base + extra[alpha]
 
 
+def family_points_f64(alpha, c1, c2=None):
+    """The family's points as a float64 program holds them: each point of
+    family_points rounded to the nearest float64 (ties to even), kept as the
+    exact rational it denotes.  -c and c are exact; 1/c and 1/d are the float64
+    values nearest to them, which is what a float64 computation of 1/c gives."""
+    return [Fraction(float(p)) for p in family_points(alpha, c1, c2)]
+
+
 def chebyshev_nodes(n):
     """Chebyshev nodes x_k = cos((2k-1) pi / (2n)), k=1..n (Section 2), as
     floats; the comparison family of the paper's network experiments."""

@@ -55,68 +55,74 @@ __global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restr
     w_absmax_block<RR>(w, part, K, C, C_pad, (int)blockIdx.x, (int)blockIdx.y);
 }
 
-// Partial maximum of |x| over images [n0, n1) of channel c, written to
-// xpart[q][c].  vec: every plane is a whole number of 16-byte vectors at a
-// 16-byte aligned address; then the block walks (image, vector) pairs as one
-// flat index with eight vector loads in flight per thread (a maximum does
-// not depend on the order).
-__device__ __forceinline__ void x_absmax_block(const float* __restrict__ x, float* __restrict__ xpart, int C,
-                                               int C_pad, int HW, int c, int q, int n0, int n1, bool vec) {
-    __shared__ float red[256];
-    const int tid = threadIdx.x;
-    float mx = 0.0f;
-    if (vec) {
-        const int hw4 = HW / 4;
-        const long long total = (long long)(n1 - n0) * hw4;
-        for (long long i0 = tid; i0 < total; i0 += 256 * 8) {
-            float4 v[8];
+// Per-batch 16-bit scaling in one launch: block c takes channel c, reduces
+// max |x[., c, ., .]| over every image and max |w[., c, ., .]| over every
+// filter, and writes t[c] = E(max |x_c|) - E(max |w_c|) and the column
+// s[e][c] = floor((dB[e1] + dB[e2] + t[c]) / 2) of the scale table (blocks
+// of padding channels write t = 0 and its column).  vec: every plane of x is
+// a whole number of 16-byte vectors at a 16-byte aligned address; then the
+// block walks (image, vector) pairs as one flat index with eight vector
+// loads in flight per thread (a maximum does not depend on the order).
+constexpr int kScaleThreads = 1024;
+
+__device__ __forceinline__ float block_max(float v, float* red) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const long long i = i0 + 256 * u;
-                v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (i < total) {
-                    const long long nn = i / hw4;
-                    const float4* plane = reinterpret_cast<const float4*>(x + ((size_t)(n0 + nn) * C + c) * HW);
-                    v[u] = plane[i - nn * hw4];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
-        }
-    } else {
-        for (int n = n0; n < n1; ++n) {
-            const float* src = x + ((size_t)n * C + c) * HW;
-            for (int i = tid; i < HW; i += 256) mx = fmaxf(mx, fabsf(src[i]));
-        }
-    }
-    red[tid] = mx;
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wv] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
-        __syncthreads();
-    }
-    if (tid == 0) xpart[(size_t)q * C_pad + c] = red[0];
+    float m = red[0];
+    for (int i = 1; i < kScaleThreads / 64; ++i) m = fmaxf(m, red[i]);
+    return m;
 }
 
-// Both partial maxima of the per-batch 16-bit scaling in one launch: blocks
-// [0, n_wblocks) take (64 channels, filter chunk) of |w|, the rest (channel,
-// image chunk) of |x|, consecutive blocks on consecutive channels of one
-// image chunk (adjacent planes of x).
 template <int RR>
-__global__ __launch_bounds__(256) void layer_maxima_kernel(const float* __restrict__ w, float* __restrict__ wpart,
-                                                           int K, int C, int C_pad, int nwx, int n_wblocks,
-                                                           const float* __restrict__ x, float* __restrict__ xpart,
-                                                           int N, int HW, int ipc, int vec) {
-    const int b = (int)blockIdx.x;
-    if (b < n_wblocks) {
-        w_absmax_block<RR>(w, wpart, K, C, C_pad, b % nwx, b / nwx);
-        return;
+__global__ __launch_bounds__(kScaleThreads) void layer_scale_kernel(const float* __restrict__ x,
+                                                                    const float* __restrict__ w, int N, int C,
+                                                                    int K, int HW, int C_pad, int vec, int alpha,
+                                                                    RowExps ex, int32_t* __restrict__ s_tab,
+                                                                    int32_t* __restrict__ t_tab) {
+    __shared__ float red[2][kScaleThreads / 64];
+    const int c = (int)blockIdx.x, tid = (int)threadIdx.x;
+    int tc = 0;
+    if (c < C) {
+        float mx = 0.0f;
+        if (vec) {
+            const int hw4 = HW / 4;
+            const long long total = (long long)N * hw4;
+            for (long long i0 = tid; i0 < total; i0 += kScaleThreads * 8) {
+                float4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const long long i = i0 + kScaleThreads * u;
+                    v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (i < total) {
+                        const long long n = i / hw4;
+                        v[u] = reinterpret_cast<const float4*>(x + ((size_t)n * C + c) * HW)[i - n * hw4];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
+            }
+        } else {
+            for (int n = 0; n < N; ++n) {
+                const float* src = x + ((size_t)n * C + c) * HW;
+                for (int i = tid; i < HW; i += kScaleThreads) mx = fmaxf(mx, fabsf(src[i]));
+            }
+        }
+        float mw = 0.0f;
+        for (int q = tid; q < K * RR; q += kScaleThreads) {
+            const int k = q / RR, t = q - k * RR;
+            mw = fmaxf(mw, fabsf(w[((size_t)k * C + c) * RR + t]));
+        }
+        mx = block_max(mx, red[0]);
+        mw = block_max(mw, red[1]);
+        tc = bin_exp(mx) - bin_exp(mw);
     }
-    const int bx = b - n_wblocks;
-    const int c = bx % C, q = bx / C;
-    const int n0 = q * ipc, n1 = min(N, n0 + ipc);
-    x_absmax_block(x, xpart, C, C_pad, HW, c, q, n0, n1, vec != 0);
+    if (tid == 0) t_tab[c] = tc;
+    for (int e = tid; e < alpha * alpha; e += kScaleThreads)
+        s_tab[(size_t)e * C_pad + c] = floor_half(ex.dB[e / alpha] + ex.dB[e % alpha] + tc);
 }
 
 // ---------------------------------------------------------------------------
@@ -159,13 +165,12 @@ FilterArgs filter_args(const Plan& p, const float* w, const float* x_absmax, voi
     int32_t* s_tab = reinterpret_cast<int32_t*>(Ub + L.scale_offset);
     int32_t* t_tab = reinterpret_cast<int32_t*>(Ub + L.chan_offset);
     float* part = reinterpret_cast<float*>(Ub + wpart_offset(L));
-    return FilterArgs{w, U, part, x_absmax, nullptr, s_tab, t_tab, w_chunks(L), 0};
+    return FilterArgs{w, U, part, x_absmax, s_tab, t_tab, nullptr, w_chunks(L)};
 }
 
-FilterArgs filter_args_xpart(const Plan& p, const float* w, void* U) {
+FilterArgs filter_args_table(const Plan& p, const float* w, void* U) {
     FilterArgs fa = filter_args(p, w, nullptr, U);
-    fa.xpart = reinterpret_cast<const float*>(static_cast<char*>(U) + xpart_offset(p.L));
-    fa.xchunks = x_chunks(p.L);
+    fa.t_in = fa.t_tab;
     return fa;
 }
 
@@ -226,29 +231,25 @@ int launch_filter_maxima(const Plan& p, const float* w, void* U, void* stream) {
 int launch_layer_maxima(const Plan& p, const float* w, const float* x, void* U, void* stream) {
     const wg_layout& L = p.L;
     if (L.dtype == WG_F32) return WG_OK;
-    const FilterArgs fa = filter_args_xpart(p, w, U);
-    const int nwx = (L.C_pad + 63) / 64;
-    const long n_w = (long)nwx * fa.kchunks, n_x = (long)L.C * fa.xchunks;
-    if (n_w + n_x >= (1L << 31)) return fail(WG_EUNSUPPORTED, "layer maxima: grid too large");
+    const FilterArgs fa = filter_args(p, w, nullptr, U);
+    RowExps ex{};
+    for (int i = 0; i < L.alpha; ++i) ex.dB[i] = p.dB[i];
     const int HW = L.H * L.W;
     const int vec = (HW % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) ? 1 : 0;
-    const dim3 grid((unsigned)(n_w + n_x));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    float* wpart = const_cast<float*>(fa.part);
-    float* xpart = const_cast<float*>(fa.xpart);
-    const int ipc = x_images_per_chunk(L);
+    const dim3 grid((unsigned)L.C_pad);
     switch (L.r) {
         case 3:
-            hipLaunchKernelGGL((layer_maxima_kernel<9>), grid, dim3(256), 0, s, w, wpart, L.K, L.C, L.C_pad, nwx,
-                               (int)n_w, x, xpart, L.N, HW, ipc, vec);
+            hipLaunchKernelGGL((layer_scale_kernel<9>), grid, dim3(kScaleThreads), 0, s, x, w, L.N, L.C, L.K, HW,
+                               L.C_pad, vec, L.alpha, ex, fa.s_tab, fa.t_tab);
             break;
         case 5:
-            hipLaunchKernelGGL((layer_maxima_kernel<25>), grid, dim3(256), 0, s, w, wpart, L.K, L.C, L.C_pad, nwx,
-                               (int)n_w, x, xpart, L.N, HW, ipc, vec);
+            hipLaunchKernelGGL((layer_scale_kernel<25>), grid, dim3(kScaleThreads), 0, s, x, w, L.N, L.C, L.K, HW,
+                               L.C_pad, vec, L.alpha, ex, fa.s_tab, fa.t_tab);
             break;
         default: return fail(WG_EUNSUPPORTED, "layer maxima: r not compiled");
     }
-    return last_launch("layer_maxima_kernel");
+    return last_launch("layer_scale_kernel");
 }
 
 // The same maximum when every plane is a whole number of 16-byte vectors:

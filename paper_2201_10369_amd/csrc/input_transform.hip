@@ -63,9 +63,8 @@ struct InputArgs {
     void* V;                   // V'[e][p][c]
     const int32_t* t_tab;      // t[c] from the filter transform (16-bit stage)
     const float* part;         // or: partial maxima of |w| per filter chunk ...
-    const float* x_absmax;     // ... with the per-channel max |x| (null: bound 1),
-    const float* xpart;        // or the partial maxima of |x| per image chunk
-    int kchunks, xchunks;
+    const float* x_absmax;     // ... with the per-channel max |x| (null: bound 1)
+    int kchunks;
     int twb, n_twb, pair_stride, n_blocks;
 };
 
@@ -198,7 +197,7 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
 #pragma unroll
             for (int q = 1; q < kInThreads / kInCh; ++q) mw = fmaxf(mw, spart[q][tid]);
             stc[tid] = c0 + tid < g.C
-                           ? bin_exp(x_bound(ia.x_absmax, ia.xpart, ia.xchunks, g.C_pad, c0 + tid)) - bin_exp(mw)
+                           ? bin_exp(ia.x_absmax != nullptr ? ia.x_absmax[c0 + tid] : 1.0f) - bin_exp(mw)
                            : 0;
         }
         __syncthreads();
@@ -268,7 +267,7 @@ __global__ __launch_bounds__(kInThreads) void input_transform_kernel(InputArgs i
 // first, the last n_in_grid input-transform blocks (t[c] from the partial
 // maxima), which take over the compute units as the short filter blocks
 // finish; no launch boundary separates the two stages.
-template <int M, int R, int DT, bool S, typename CT>
+template <int M, int R, int DT, bool S, bool TP, typename CT>
 __global__ __launch_bounds__(kInThreads) void filter_input_kernel(InputArgs ia, FilterArgs fa, Mats<M, R, CT> mt,
                                                                   RowPerm rp, RowExps ex, Geo g, int n_in_grid,
                                                                   int f_groups) {
@@ -277,7 +276,7 @@ __global__ __launch_bounds__(kInThreads) void filter_input_kernel(InputArgs ia, 
     if (b >= 0) {
         const int w = xcd_item(b, n_in_grid);
         if (w >= ia.n_blocks) return;
-        input_block<M, R, DT, S, true, CT>(ia, mt, rp, g, w);
+        input_block<M, R, DT, S, TP, CT>(ia, mt, rp, g, w);
     } else {
         extern __shared__ __align__(16) float lds_f[];
         const int f = (int)blockIdx.x;
@@ -293,12 +292,12 @@ static void input_launch(dim3 grid, size_t lds_bytes, hipStream_t s, const Input
                        g);
 }
 
-template <int M, int R, int DT, bool S, typename CT>
+template <int M, int R, int DT, bool S, bool TP, typename CT>
 static void filter_input_launch(unsigned n_in_grid, unsigned n_f_blocks, int f_groups, size_t lds_bytes,
                                 hipStream_t s, const InputArgs& ia, const FilterArgs& fa, const Mats<M, R, CT>& mt,
                                 const RowPerm& rp, const RowExps& ex, const Geo& g) {
-    allow_lds(filter_input_kernel<M, R, DT, S, CT>, lds_bytes);
-    hipLaunchKernelGGL((filter_input_kernel<M, R, DT, S, CT>), dim3(n_in_grid + n_f_blocks), dim3(kInThreads),
+    allow_lds(filter_input_kernel<M, R, DT, S, TP, CT>, lds_bytes);
+    hipLaunchKernelGGL((filter_input_kernel<M, R, DT, S, TP, CT>), dim3(n_in_grid + n_f_blocks), dim3(kInThreads),
                        lds_bytes, s, ia, fa, mt, rp, ex, g, (int)n_in_grid, f_groups);
 }
 
@@ -308,7 +307,7 @@ static void filter_input_launch(unsigned n_in_grid, unsigned n_f_blocks, int f_g
 // transforms, dtype WG_F32 only).
 template <int M, int R, typename CT>
 static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
-                      const float* x_absmax, bool x_from_u) {
+                      const float* x_absmax, bool t_from_table) {
     constexpr int A = M + R - 1;
     constexpr int CS = 2 * (A | 1);
     constexpr bool f64 = sizeof(CT) == 8;
@@ -348,7 +347,7 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const int32_t* t_tab = reinterpret_cast<const int32_t*>(static_cast<const char*>(U) + L.chan_offset);
     void* V = static_cast<char*>(ws) + L.v_offset;
     if (w == nullptr) {
-        const InputArgs ia{x, V, t_tab, nullptr, nullptr, nullptr, 0, 0, twb, n_twb, pair_stride, (int)n_blocks};
+        const InputArgs ia{x, V, t_tab, nullptr, nullptr, 0, twb, n_twb, pair_stride, (int)n_blocks};
 #define WG_IN(DT)                                                                                 \
     (structured ? input_launch<M, R, DT, true, CT>(grid, lds_bytes, s, ia, mt, rp, g)             \
                 : input_launch<M, R, DT, false, CT>(grid, lds_bytes, s, ia, mt, rp, g))
@@ -365,24 +364,30 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
         return last_launch("input_transform_kernel");
     }
     // the partial maxima of |w| (16-bit stage) are already in U (wg_filter_maxima)
-    const FilterArgs fa = x_from_u ? filter_args_xpart(p, w, const_cast<void*>(U))
-                                   : filter_args(p, w, x_absmax, const_cast<void*>(U));
-    const InputArgs ia{x,          V,           t_tab, fa.part, fa.x_absmax, fa.xpart, fa.kchunks, fa.xchunks,
-                       twb,        n_twb,       pair_stride, (int)n_blocks};
+    const FilterArgs fa = t_from_table ? filter_args_table(p, w, const_cast<void*>(U))
+                                       : filter_args(p, w, x_absmax, const_cast<void*>(U));
+    const InputArgs ia{x, V, t_tab, fa.part, fa.x_absmax, fa.kchunks, twb, n_twb, pair_stride, (int)n_blocks};
     const int fg = filter_groups(L);
     const unsigned n_f = (unsigned)fg * (unsigned)L.K_pad;
     if ((size_t)n_in_grid + n_f > (1u << 31)) return fail(WG_EUNSUPPORTED, "filter and input transform: grid too large");
     const size_t lds = std::max(lds_bytes, sizeof(int) * (size_t)kFilterLdsWords);
-#define WG_FI(DT)                                                                                               \
-    (structured ? filter_input_launch<M, R, DT, true, CT>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g)     \
-                : filter_input_launch<M, R, DT, false, CT>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g))
+#define WG_FI(DT, TP)                                                                                             \
+    (structured ? filter_input_launch<M, R, DT, true, TP, CT>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g)   \
+                : filter_input_launch<M, R, DT, false, TP, CT>(n_in_grid, n_f, fg, lds, s, ia, fa, mt, rp, ex, g))
+    // float32 stages have no exponent part: one instantiation
     if constexpr (f64) {
-        WG_FI(kF32);
+        WG_FI(kF32, false);
     } else {
         switch (L.dtype) {
-            case WG_F32: WG_FI(kF32); break;
-            case WG_F16: WG_FI(kF16); break;
-            default: WG_FI(kBF16); break;
+            case WG_F32: WG_FI(kF32, false); break;
+            case WG_F16:
+                if (t_from_table) WG_FI(kF16, false);
+                else WG_FI(kF16, true);
+                break;
+            default:
+                if (t_from_table) WG_FI(kBF16, false);
+                else WG_FI(kBF16, true);
+                break;
         }
     }
 #undef WG_FI
@@ -391,9 +396,9 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
 
 template <int M, int R>
 static int input_dispatch(const Plan& p, const float* x, const void* U, void* ws, hipStream_t s, const float* w,
-                          const float* x_absmax, bool x_from_u) {
-    return p.f64t ? input_impl<M, R, double>(p, x, U, ws, s, w, x_absmax, x_from_u)
-                  : input_impl<M, R, float>(p, x, U, ws, s, w, x_absmax, x_from_u);
+                          const float* x_absmax, bool t_from_table) {
+    return p.f64t ? input_impl<M, R, double>(p, x, U, ws, s, w, x_absmax, t_from_table)
+                  : input_impl<M, R, float>(p, x, U, ws, s, w, x_absmax, t_from_table);
 }
 
 int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws, void* stream) {
@@ -405,10 +410,10 @@ int launch_input_transform(const Plan& p, const float* x, const void* U, void* w
 }
 
 int launch_filter_input(const Plan& p, const float* w, const float* x_absmax, const float* x, void* U, void* ws,
-                        void* stream, bool x_from_u) {
+                        void* stream, bool t_from_table) {
     hipStream_t s = static_cast<hipStream_t>(stream);
 #define WG_CASE_fi(MM, RR) \
-    case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, w, x_absmax, x_from_u);
+    case MM * 16 + RR: return input_dispatch<MM, RR>(p, x, U, ws, s, w, x_absmax, t_from_table);
     WG_DISPATCH(fi)
 #undef WG_CASE_fi
 }

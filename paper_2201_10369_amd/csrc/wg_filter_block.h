@@ -24,9 +24,9 @@ namespace wg {
 //
 // For the 16-bit stage the block first finishes the per-channel exponent
 // part t[c] = E(max |x_c|) - E(max_k |w[k][c]|) from the partial maxima of
-// all filter chunks, and of all image chunks when max |x_c| comes from them
-// (every block of a channel group repeats this small reduction, so no
-// second launch is needed), scales entry (i, j) by 2^s with
+// all filter chunks (every block of a channel group repeats this small
+// reduction, so no second launch is needed), or reads the finished t[c]
+// when the per-batch scaling launch has computed it, scales entry (i, j) by 2^s with
 // s = floor((dB[i] + dB[j] + t[c]) / 2) before rounding, and the blocks of
 // filter 0 also write t and the table s[e][c].
 // ---------------------------------------------------------------------------
@@ -34,31 +34,21 @@ struct FilterArgs {
     const float* w;            // K x C x r x r
     void* U;                   // U'[e][k][c]
     const float* part;         // partial maxima of |w| per filter chunk (16-bit stage)
-    const float* x_absmax;     // per-channel max |x| or null (bound 1) ...
-    const float* xpart;        // ... or partial maxima of |x| per image chunk
+    const float* x_absmax;     // per-channel max |x| or null (bound 1)
     int32_t* s_tab;            // s[e][c] (written by the blocks of filter 0)
     int32_t* t_tab;            // t[c] (likewise)
+    const int32_t* t_in;       // or: t[c] already final (then nothing is reduced
+                               // or written to the tables)
     int kchunks;               // filter chunks of the partial maxima of |w|
-    int xchunks;               // image chunks of the partial maxima of |x|
 };
-
-// The bound of |x| in channel c (c < C): the caller's per-channel maximum,
-// else the maximum over the image chunks of the partial maxima of |x| (the
-// same value: a maximum does not depend on how it is split), else 1.
-__device__ __forceinline__ float x_bound(const float* x_absmax, const float* xpart, int xchunks, int C_pad, int c) {
-    if (x_absmax != nullptr) return x_absmax[c];
-    if (xpart == nullptr) return 1.0f;
-    float mx = 0.0f;
-    for (int q = 0; q < xchunks; ++q) mx = fmaxf(mx, xpart[(size_t)q * C_pad + c]);
-    return mx;
-}
 
 // Host side (filter_transform.hip): the arguments for a plan and buffers,
 // the channel groups of the grid, and the 16-bit partial-maxima launch
 // (nothing to do for WG_F32).
 FilterArgs filter_args(const Plan& p, const float* w, const float* x_absmax, void* U);
-// the same with max |x_c| taken from the partial maxima of |x| in U
-FilterArgs filter_args_xpart(const Plan& p, const float* w, void* U);
+// the same with t[c] read from the table in U (written by the per-batch
+// scaling launch)
+FilterArgs filter_args_table(const Plan& p, const float* w, void* U);
 inline int filter_groups(const wg_layout& L) { return (L.C_pad + 127) / 128; }
 int launch_filter_absmax(const Plan& p, const FilterArgs& fa, hipStream_t s);
 
@@ -93,7 +83,10 @@ __device__ __forceinline__ void filter_block(const FilterArgs& fa, const Mats<M,
             g1[u][v] = (CT)(live1 ? w[(((size_t)k * g.C + c + 1) * R + u) * R + v] : 0.0f);
         }
     int tc0 = 0, tc1 = 0;
-    if (DT != kF32) {
+    if (DT != kF32 && fa.t_in != nullptr) {
+        tc0 = c < g.C ? fa.t_in[c] : 0;
+        tc1 = c + 1 < g.C ? fa.t_in[c + 1] : 0;
+    } else if (DT != kF32) {
         // t[c] from the partial maxima of every filter chunk: the two halves
         // of the block (one thread per channel of the block's 128) take the
         // even and the odd chunks
@@ -109,7 +102,7 @@ __device__ __forceinline__ void filter_block(const FilterArgs& fa, const Mats<M,
         __syncthreads();
         // both halves derive t for channel cl; they split the table rows
         const float mw = fmaxf(sred[0][cl], sred[1][cl]);
-        const int tc = cc < g.C ? bin_exp(x_bound(x_absmax, fa.xpart, fa.xchunks, g.C_pad, cc)) - bin_exp(mw) : 0;
+        const int tc = cc < g.C ? bin_exp(x_absmax != nullptr ? x_absmax[cc] : 1.0f) - bin_exp(mw) : 0;
         if (half == 0) stc[cl & 1][cl >> 1] = tc;
         if (k == 0 && cc < g.C_pad) {
             if (half == 0) t_tab[cc] = tc;

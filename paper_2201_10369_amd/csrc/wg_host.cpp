@@ -215,10 +215,9 @@ int wg_plan_create(wg_plan** out, int m, int r, const double* pts, int n_pts, in
     const size_t ubytes = E * L.K_pad * L.C_pad * L.elem_bytes;
     L.scale_offset = round_up(ubytes, 256);
     L.chan_offset = round_up(L.scale_offset + E * L.C_pad * sizeof(int32_t), 256);
-    // scratch after the per-channel table: partial maxima of |w| per 8
-    // filters, then partial maxima of |x| per chunk of images
+    // scratch after the per-channel table: partial maxima of |w| per 8 filters
     L.filter_bytes = dtype == WG_F32 ? round_up(ubytes, 256)
-                                     : round_up(xpart_offset(L) + (size_t)kXChunks * L.C_pad * sizeof(float), 256);
+                                     : round_up(wpart_offset(L) + (size_t)w_chunks(L) * L.C_pad * sizeof(float), 256);
     L.v_offset = 0;
     L.m_offset = round_up(E * L.P_pad * L.C_pad * L.elem_bytes, 256);
     L.workspace_bytes = round_up(L.m_offset + E * L.K_pad * L.P_pad * sizeof(float), 256);

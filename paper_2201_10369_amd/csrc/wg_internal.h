@@ -50,12 +50,14 @@ int launch_filter_transform(const Plan& p, const float* w, const float* x_absmax
 int launch_input_transform(const Plan& p, const float* x, const void* U, void* ws,
                            void* stream);
 int launch_filter_maxima(const Plan& p, const float* w, void* U, void* stream);
-// partial maxima of |w| and of |x| in one launch (16-bit plans; else nothing)
+// per-batch 16-bit scaling: t[c] and the scale table from max |x_c| and
+// max |w_c| in one launch (16-bit plans; else nothing)
 int launch_layer_maxima(const Plan& p, const float* w, const float* x, void* U, void* stream);
-// x_from_u: the |x| bound of each channel is the maximum of the partial
-// maxima of |x| in U (launch_layer_maxima), else x_absmax (or 1 when null)
+// t_from_table: the transforms read t[c] from U's table (written by
+// launch_layer_maxima), else derive it from x_absmax (or 1 when null) and the
+// partial maxima of |w|
 int launch_filter_input(const Plan& p, const float* w, const float* x_absmax, const float* x, void* U, void* ws,
-                        void* stream, bool x_from_u = false);
+                        void* stream, bool t_from_table = false);
 int launch_hadamard_gemm(const Plan& p, const void* U, void* ws, void* stream);
 // Times each candidate tiles-per-block value on the caller's operands and
 // keeps the fastest in the plan (synchronous on `stream`).
@@ -71,17 +73,9 @@ size_t score_partials(size_t count);
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Library scratch in the U buffer of a 16-bit plan (after the table t[c]):
-// partial maxima of |w| per chunk of kKChunkW filters, [wchunks][C_pad], then
-// partial maxima of |x| per chunk of images, [kXChunks][C_pad] (chunk q holds
-// images [q*ipc, min(N, (q+1)*ipc)) with ipc = ceil(N / kXChunks)).
+// partial maxima of |w| per chunk of kKChunkW filters, [wchunks][C_pad].
 constexpr int kKChunkW = 8;
-constexpr int kXChunks = 8;
 inline int w_chunks(const wg_layout& L) { return (L.K + kKChunkW - 1) / kKChunkW; }
-inline int x_chunks(const wg_layout& L) { return L.N < kXChunks ? L.N : kXChunks; }
-inline int x_images_per_chunk(const wg_layout& L) { return (L.N + x_chunks(L) - 1) / x_chunks(L); }
 inline size_t wpart_offset(const wg_layout& L) { return L.chan_offset + round_up((size_t)L.C_pad * 4, 256); }
-inline size_t xpart_offset(const wg_layout& L) {
-    return wpart_offset(L) + round_up((size_t)w_chunks(L) * L.C_pad * sizeof(float), 256);
-}
 
 }  // namespace wg

@@ -34,8 +34,10 @@ def sweep_for(m, r, d_pool, g_pool, dims=2, max_cand=65536):
 
 
 def score(S, c1, c2, counts):
-    """Exact sweep scores: mean absolute error per candidate (inf if flagged),
-    in runs of at most S.max_cand candidates."""
+    """Exact sweep scores: mean absolute error per candidate, in runs of at
+    most S.max_cand candidates.  A flagged candidate, or one whose float32
+    evaluation overflowed (a NaN or infinite sum: extreme points make the
+    transformed values exceed float32), scores inf."""
     torch = _torch()
     c1, c2, counts = np.asarray(c1, np.float64), np.asarray(c2, np.float64), np.asarray(counts, np.int32)
     means = []
@@ -44,7 +46,7 @@ def score(S, c1, c2, counts):
         out = S.run(torch.from_numpy(c1[a:b].copy()).cuda(), torch.from_numpy(c2[a:b].copy()).cuda(),
                     torch.from_numpy(counts[a:b].copy()).cuda()).cpu().numpy()
         mean = out[:, 0] / np.maximum(out[:, 2], 1)
-        mean[out[:, 3] > 0] = np.inf
+        mean[(out[:, 3] > 0) | ~np.isfinite(mean)] = np.inf
         means.append(mean)
     return np.concatenate(means)
 
@@ -121,6 +123,23 @@ def propose(model, m, r, grid_c1, grid_c2, k=32):
     """Indices into the grid of the k lowest predicted errors."""
     pred = predict(model, grid_c1, grid_c2, m, r)
     return wg.topk_min(pred, k).cpu().numpy()
+
+
+def search_grids(alpha, lo=0.05, hi=20.0):
+    """Candidate grids of the held-out protocol for a family of alpha points:
+    (plain c1, plain c2, proposal c1, proposal c2, two-parameter).  Families
+    with at most 8 points are searched over c alone (c2 = 1; the family of 8
+    points then holds +-1): 4096 log-spaced values, on which the surrogate
+    also proposes.  The families of 9 and 10 points need c2 away from 1
+    (+-1/d and +-d coincide at d = 1): a 64 x 64 log grid over (c1, c2) for
+    the plain search and a 128 x 128 one for the proposals."""
+    from .search import log_grid
+    if alpha <= 8:
+        g = log_grid(lo, hi, 4096)
+        return g, np.ones_like(g), g, np.ones_like(g), False
+    a, b = np.meshgrid(log_grid(lo, hi, 64), log_grid(lo, hi, 64), indexing="ij")
+    p, q = np.meshgrid(log_grid(lo, hi, 128), log_grid(lo, hi, 128), indexing="ij")
+    return a.ravel(), b.ravel(), p.ravel(), q.ravel(), True
 
 
 def guided_search(model, S, m, r, grid_c1, grid_c2, k=32, refine=32, spans=(0.25, 0.05, 0.01),

@@ -173,13 +173,12 @@ def test_filter_and_input_in_one_launch_match_separate_calls(case, dtype):
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("case", CASES[:3] + [CASES[4], CASES[9], (6, 3, (8, 2.0, 1.0), 11, 20, 9, 13, 7, "same")])
 def test_per_batch_maxima_match_explicit_absmax(case, dtype):
-    """The per-batch scaling calls (wg_layer_maxima, then wg_transform_layer:
-    partial maxima of |w| and |x| in one launch, both transforms in the next)
-    write exactly the U', scale tables and V' of wg_channel_absmax,
-    wg_filter_maxima and wg_transform_filters_and_input with those maxima,
-    into buffers that start out filled with garbage (N = 11 gives image
-    chunks of two with a ragged and two empty chunks; 13 x 7 planes are not
-    whole 16-byte vectors)."""
+    """The per-batch scaling calls (wg_layer_maxima: the maxima of |x| and
+    |w| and the scale tables in one launch; wg_transform_layer: both
+    transforms in the next) write exactly the U', scale tables and V' of
+    wg_channel_absmax, wg_filter_maxima and wg_transform_filters_and_input
+    with those maxima, into buffers that start out filled with garbage
+    (13 x 7 planes are not whole 16-byte vectors: the scalar walk)."""
     wg = _wg()
     m, r, fam, N, C, K, H, W, padding = case
     pts = _pts(fam)
