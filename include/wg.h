@@ -309,6 +309,22 @@ size_t wg_score_workspace_bytes(size_t count);
 int wg_score_error(const float* y, const double* y_ref, size_t count, double* out2,
                    void* ws, size_t ws_bytes, wg_stream_t stream);
 
+/* wg_score_error without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels, results bit for bit
+ * those of wg_score_error, with the partial sums in a static device array of
+ * the library (1024 pairs of doubles, 16 KB, one copy per GPU, held until
+ * the process ends; the partial-sum grid never has more than 1024 blocks, so
+ * every count fits).  Nothing is allocated and no library routine that
+ * allocates is called.  The calling thread's current device must be the
+ * device of y, y_ref, out2 and stream; the device address of the array is
+ * looked up on the first call on each device.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be ordered by the caller.
+ * Errors: WG_EINVAL (null pointer, count 0), WG_EHIP. */
+int wg_score_error_noalloc(const float* y, const double* y_ref, size_t count, double* out2,
+                           wg_stream_t stream);
+
 /* ------------------------------------------------------------------------
  * Batched error sweep (device).  Section 6.1 traces the error of a point
  * family as a function of c; Section 6.3 scores many combinations.  For each

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "wg_device.h"
 #include "wg_internal.h"
@@ -401,6 +403,46 @@ int launch_score(const float* y, const double* yref, size_t count, double* out2,
     if (st != WG_OK) return st;
     hipLaunchKernelGGL(score_final_kernel, dim3(1), dim3(256), 0, s, part, nb, out2);
     return hip_check((int)hipGetLastError(), "score_final_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free scoring: the same two kernels with their partial sums in a
+// file-scope device array (one copy per GPU, kept until the process ends)
+// instead of a caller workspace.  The partial-sum grid never exceeds
+// kScorePartials blocks, so the array holds the partials of every count.
+// Host code never passes the array's name to a kernel: its device address is
+// looked up once per device (with that device current) and kept.
+// ---------------------------------------------------------------------------
+constexpr int kScorePartials = 1024;
+static __device__ __align__(256) double scratch[2 * kScorePartials];
+
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_ptr;      // per device; null until looked up
+
+static int scratch_for_current_device(double** out) {
+    int dev = 0;
+    int st = hip_check((int)hipGetDevice(&dev), "wg_score_error_noalloc: hipGetDevice");
+    if (st != WG_OK) return st;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        st = hip_check((int)hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)),
+                       "wg_score_error_noalloc: hipGetSymbolAddress");
+        if (st != WG_OK) return st;
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return WG_OK;
+}
+
+int launch_score_noalloc(const float* y, const double* yref, size_t count, double* out2, void* stream) {
+    if (score_partials(count) > (size_t)kScorePartials)
+        return fail(WG_EUNSUPPORTED, "wg_score_error_noalloc: more partial sums than the static scratch holds");
+    double* part = nullptr;
+    const int st = scratch_for_current_device(&part);
+    if (st != WG_OK) return st;
+    return launch_score(y, yref, count, out2, part, stream);
 }
 
 }  // namespace wg

@@ -395,4 +395,10 @@ int wg_score_error(const float* y, const double* y_ref, size_t count, double* ou
     return launch_score(y, y_ref, count, out2, ws, stream);
 }
 
+int wg_score_error_noalloc(const float* y, const double* y_ref, size_t count, double* out2, wg_stream_t stream) {
+    if (!y || !y_ref || !out2) return fail(WG_EINVAL, "wg_score_error_noalloc: null pointer");
+    if (count == 0) return fail(WG_EINVAL, "wg_score_error_noalloc: count must be positive");
+    return launch_score_noalloc(y, y_ref, count, out2, stream);
+}
+
 }  // extern "C"

@@ -69,6 +69,8 @@ int launch_direct_f64(const float* x, const float* w, double* y, int N, int C, i
 int launch_score(const float* y, const double* yref, size_t count, double* out2, void* ws,
                  void* stream);
 size_t score_partials(size_t count);
+// the same with the partial sums in the library's static device scratch
+int launch_score_noalloc(const float* y, const double* yref, size_t count, double* out2, void* stream);
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

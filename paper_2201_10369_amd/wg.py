@@ -100,6 +100,7 @@ _SIGS = {
     "wg_mlp_predict": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_topk_min": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "wg_score_error": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "wg_score_error_noalloc": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
 }
 
 _lib = None
@@ -398,6 +399,18 @@ def score_error(y, yref, out=None, ws=None, stream=None):
     _check(lib().wg_score_error(_tptr(y, torch.float32, "y"), _tptr(yref, torch.float64, "yref"), count,
                                 _tptr(out, torch.float64, "out"), _tptr(ws, None, "ws"),
                                 ws.numel() * ws.element_size(), _stream(stream)))
+    return out
+
+
+def score_error_noalloc(y, yref, out, stream=None):
+    """score_error with the library's static scratch: out (device float64
+    [2]) receives [sum|y - yref|, sum|yref|]; nothing is allocated."""
+    torch = _torch()
+    count = y.numel()
+    if yref.numel() != count:
+        raise ValueError("y and yref differ in size")
+    _check(lib().wg_score_error_noalloc(_tptr(y, torch.float32, "y"), _tptr(yref, torch.float64, "yref"), count,
+                                        _tptr(out, torch.float64, "out"), _stream(stream)))
     return out
 
 
