@@ -271,8 +271,11 @@ def bench_surrogate(torch):
     """Leave-one-size-out surrogate searches: for each held-out size the
     network is trained on the sweep-scored (c1, c2) pairs of the other 11
     tile sizes (83,334 each, 1M in all) plus 64 of the held-out size; its 32
-    proposals + 3 x 32 refinements are scored exactly and compared with the
-    plain 4096-point sweep and with random search at the same budget."""
+    proposals and the four best of those 64 samples are scored exactly, then
+    refined (3 x 32 points from the best proposal and 3 x 32 from the best
+    sample; for the two-parameter families 3 x 32 in c and 3 x 32 in d from
+    the best point): 292 evaluations, compared with the plain 4096-point
+    search and with random search at the same budget."""
     from paper_2201_10369_amd import surrogate as sg
     sizes = synth.SURROGATE_SIZES
     t0 = time.perf_counter()
@@ -296,7 +299,10 @@ def bench_surrogate(torch):
         S = sweeps[(m, r)]
         pc1, pc2, qc1, qc2, two = sg.search_grids(m + r - 1)
         plain = sg.score(S, pc1, pc2, np.full(4096, sg.POOL))
-        err, c1, c2, used = sg.guided_search(model, S, m, r, qc1, qc2, refine_c2=two)
+        # the four best of the 64 exact samples of this size are re-scored
+        # beside the 32 proposals
+        err, c1, c2, used = sg.guided_search(model, S, m, r, qc1, qc2, refine_c2=two,
+                                             extra=sg.best_samples(sg.select(shots, here(shots)), 4))
         used += 64
         rng = np.random.default_rng(12)
         pick = rng.choice(4096, used, replace=False)

@@ -61,9 +61,11 @@ __global__ __launch_bounds__(256) void filter_absmax_kernel(const float* __restr
 // s[e][c] = floor((dB[e1] + dB[e2] + t[c]) / 2) of the scale table (blocks
 // of padding channels write t = 0 and its column).  vec: every plane of x is
 // a whole number of 16-byte vectors at a 16-byte aligned address; then the
-// block walks (image, vector) pairs as one flat index with eight vector
-// loads in flight per thread (a maximum does not depend on the order).
+// block walks (image, vector) pairs as one flat index with sixteen vector
+// loads in flight per thread (one round for a channel of up to 16K vectors,
+// 64 images of 28 x 28 among them; a maximum does not depend on the order).
 constexpr int kScaleThreads = 1024;
+constexpr int kScaleLoads = 16;
 
 __device__ __forceinline__ float block_max(float v, float* red) {
 #pragma unroll
@@ -86,14 +88,20 @@ __global__ __launch_bounds__(kScaleThreads) void layer_scale_kernel(const float*
     const int c = (int)blockIdx.x, tid = (int)threadIdx.x;
     int tc = 0;
     if (c < C) {
+        // the filter taps first (their loads overlap the walk over x)
+        float mw = 0.0f;
+        for (int q = tid; q < K * RR; q += kScaleThreads) {
+            const int k = q / RR, t = q - k * RR;
+            mw = fmaxf(mw, fabsf(w[((size_t)k * C + c) * RR + t]));
+        }
         float mx = 0.0f;
         if (vec) {
             const int hw4 = HW / 4;
             const long long total = (long long)N * hw4;
-            for (long long i0 = tid; i0 < total; i0 += kScaleThreads * 8) {
-                float4 v[8];
+            for (long long i0 = tid; i0 < total; i0 += kScaleThreads * kScaleLoads) {
+                float4 v[kScaleLoads];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kScaleLoads; ++u) {
                     const long long i = i0 + kScaleThreads * u;
                     v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                     if (i < total) {
@@ -102,7 +110,7 @@ __global__ __launch_bounds__(kScaleThreads) void layer_scale_kernel(const float*
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kScaleLoads; ++u)
                     mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
             }
         } else {
@@ -110,11 +118,6 @@ __global__ __launch_bounds__(kScaleThreads) void layer_scale_kernel(const float*
                 const float* src = x + ((size_t)n * C + c) * HW;
                 for (int i = tid; i < HW; i += kScaleThreads) mx = fmaxf(mx, fabsf(src[i]));
             }
-        }
-        float mw = 0.0f;
-        for (int q = tid; q < K * RR; q += kScaleThreads) {
-            const int k = q / RR, t = q - k * RR;
-            mw = fmaxf(mw, fabsf(w[((size_t)k * C + c) * RR + t]));
         }
         mx = block_max(mx, red[0]);
         mw = block_max(mw, red[1]);

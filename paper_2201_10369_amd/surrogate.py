@@ -66,6 +66,12 @@ def make_dataset(sweeps, pairs, counts):
     return dict(c1=c1, c2=c2, m=mm.astype(np.int32), r=rr.astype(np.int32), target=lab.astype(np.float32))
 
 
+def best_samples(data, k):
+    """(c1, c2) of the k samples of `data` with the lowest labels."""
+    j = np.argsort(data["target"], kind="stable")[:k]
+    return data["c1"][j], data["c2"][j]
+
+
 def select(data, keep):
     """The samples of `data` where the boolean mask `keep` is set."""
     return {k: v[keep] for k, v in data.items()}
@@ -143,27 +149,45 @@ def search_grids(alpha, lo=0.05, hi=20.0):
 
 
 def guided_search(model, S, m, r, grid_c1, grid_c2, k=32, refine=32, spans=(0.25, 0.05, 0.01),
-                  n_eval=POOL, refine_c2=False):
-    """Re-score the k best proposals exactly, then refine: for each span,
-    `refine` log-spaced values of c1 within a factor (1 +- span) of the best
-    so far (the error curve is smooth, Section 6.1), and with refine_c2 the
-    same for c2 (the two-parameter families).
+                  n_eval=POOL, refine_c2=False, extra=None):
+    """Re-score the k best proposals exactly, and the points of `extra` (a
+    pair of arrays (c1, c2), e.g. the best exact samples the network was
+    given for this size), then refine: for each span, `refine` log-spaced
+    values of c1 within a factor (1 +- span) of the best so far (the error
+    curve is smooth, Section 6.1), and with refine_c2 the same for c2 (the
+    two-parameter families).  A one-parameter search refines from the best
+    proposal and, separately, from the best extra point; a two-parameter
+    search from the best of both.
     Returns (best error, best c1, best c2, exact evaluations used)."""
     idx = propose(model, m, r, grid_c1, grid_c2, k)
     idx = idx[idx >= 0]
     c1, c2 = np.asarray(grid_c1)[idx], np.asarray(grid_c2)[idx]
-    errs = score(S, c1, c2, np.full(len(idx), n_eval))
+    errs = score(S, c1, c2, np.full(len(c1), n_eval))
+    used = len(c1)
     b = int(np.argmin(errs))
-    best = (errs[b], c1[b], c2[b])
-    used = len(idx)
-    for span in (spans if refine else ()):
-        for axis in ((0, 1) if refine_c2 else (0,)):
-            f = np.exp(np.linspace(np.log(1 - span), np.log(1 + span), refine))
-            rc1 = best[1] * f if axis == 0 else np.full(refine, best[1])
-            rc2 = best[2] * f if axis == 1 else np.full(refine, best[2])
-            rerr = score(S, rc1, rc2, np.full(refine, n_eval))
-            j = int(np.argmin(rerr))
-            if rerr[j] < best[0]:
-                best = (rerr[j], rc1[j], rc2[j])
-            used += refine
+    seeds = [(errs[b], c1[b], c2[b])]
+    if extra is not None and len(extra[0]):
+        x1, x2 = np.asarray(extra[0], np.float64), np.asarray(extra[1], np.float64)
+        xe = score(S, x1, x2, np.full(len(x1), n_eval))
+        used += len(x1)
+        j = int(np.argmin(xe))
+        if refine_c2:
+            if xe[j] < seeds[0][0]:
+                seeds = [(xe[j], x1[j], x2[j])]
+        else:
+            seeds.append((xe[j], x1[j], x2[j]))
+    results = []
+    for best in seeds:
+        for span in (spans if refine else ()):
+            for axis in ((0, 1) if refine_c2 else (0,)):
+                f = np.exp(np.linspace(np.log(1 - span), np.log(1 + span), refine))
+                rc1 = best[1] * f if axis == 0 else np.full(refine, best[1])
+                rc2 = best[2] * f if axis == 1 else np.full(refine, best[2])
+                rerr = score(S, rc1, rc2, np.full(refine, n_eval))
+                j = int(np.argmin(rerr))
+                if rerr[j] < best[0]:
+                    best = (rerr[j], rc1[j], rc2[j])
+                used += refine
+        results.append(best)
+    best = min(results, key=lambda t: t[0])
     return best[0], best[1], best[2], used

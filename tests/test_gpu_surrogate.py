@@ -118,15 +118,17 @@ def test_topk_infinities_nan_and_short_input():
     assert list(idx[:2]) == [2, 8] and list(idx[5:8]) == [4, 1, 5]
 
 
-@pytest.mark.parametrize("m,r", [(4, 3), (6, 5)])
+@pytest.mark.parametrize("m,r", [(4, 3), (2, 3), (6, 5)])
 def test_surrogate_gain_over_plain_and_random_search(m, r):
     """Hold out one tile size: the surrogate is trained on sweep errors of the
     other 11 tile sizes (F(2..8,3), F(2..6,5); 2D), plus 64 exact samples of
     the held-out size, all of which count as evaluations.  Its 32 best
-    proposals on a 4096-point grid over c in [0.05, 20] and three 32-point
-    local refinements are scored exactly (for the two-parameter family of
-    F(6x6,5x5) proposals come from a 128 x 128 (c, d) grid, refinements run
-    in c and in d, and the plain search is a 64 x 64 grid).  With 192 (288)
+    proposals on a 4096-point grid over c in [0.05, 20] and the four best of
+    those 64 samples are scored exactly, then three 32-point local
+    refinements from the best proposal and three from the best sample (for
+    the two-parameter family of F(6x6,5x5) proposals come from a 128 x 128
+    (c, d) grid, three refinements each in c and in d run from the best
+    point, and the plain search is a 64 x 64 grid).  With 292
     evaluations, more than 10x fewer than the 4096 of the plain search, the
     best error is within 1% of the plain search's best, and no worse than
     random search with the same budget."""
@@ -148,8 +150,9 @@ def test_surrogate_gain_over_plain_and_random_search(m, r):
     plain = sg.score(S, pc1, pc2, np.full(4096, sg.POOL))
     best_plain = float(np.min(plain))
     assert np.isfinite(best_plain)
-    err, c1, c2, used = sg.guided_search(model, S, m, r, qc1, qc2, k=32, refine=32, refine_c2=two)
-    assert used == 32 + 3 * 32 * (2 if two else 1)
+    err, c1, c2, used = sg.guided_search(model, S, m, r, qc1, qc2, k=32, refine=32, refine_c2=two,
+                                         extra=sg.best_samples(shots, 4))
+    assert used == 32 + 4 + 3 * 32 * 2
     used += 64
     assert used * 10 <= 4096
     rng = np.random.default_rng(12)
