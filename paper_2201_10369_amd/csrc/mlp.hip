@@ -8,7 +8,9 @@
 // Kernels (float32, deterministic reduction orders):
 //   fwd_bwd : a block takes 16 samples, runs the forward pass with all
 //             activations in LDS and, for training, the backward pass, and
-//             writes its partial gradient (one full parameter vector)
+//             writes its partial gradient (one full parameter vector); the
+//             128 x 128 products of the hidden layers and their gradients
+//             run on the float32 matrix cores
 //   reduce  : per parameter, four thread groups add interleaved block
 //             partials, the group sums are added in order, then Adam (or
 //             the gradient is written)
@@ -25,12 +27,23 @@
 namespace wg {
 
 constexpr int kIn = 4, kH = 128;
-constexpr int kS = 16;            // samples per block
-constexpr int kThreads = 256;
+constexpr int kS = 16;            // samples per block, in kHalves row tiles of kHalf
+constexpr int kHalf = 16;         // samples per matrix-core row tile
+constexpr int kHalves = kS / kHalf;
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+// each row tile of the block (8 waves) runs one 16-column tile of a
+// 128-wide layer per wave for its kHalf samples (a block of 32 samples in
+// two row tiles of 1024 threads measured slower: 43.5 against 35.8 us per
+// gradient step, half the compute units idle)
+static_assert(kH / 16 * kHalves == kWaves, "tile per wave");
+constexpr size_t kMlpLds = sizeof(float) * (kS * kIn + 6 * kS * kH);
 // parameter layout (row-major W[out][in]):
 constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
               ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kH, kParams = ob4 + 1;
 static_assert(kParams == 33793, "parameter count");
+// partial gradients of the blocks are kPartStride floats apart (16-byte aligned)
+constexpr int kPartStride = (kParams + 3) / 4 * 4;
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
@@ -60,177 +73,236 @@ struct MlpData {
     float inv_batch2;      // 2 / batch
 };
 
-// 128-wide dense layer for the block's kS samples held in LDS:
-// out[s][j] = b[j] + sum_i W[j][i] in[s][i]   (thread: j = tid % 128, two sample halves)
-__device__ __forceinline__ void dense128(const float* __restrict__ W, const float* __restrict__ b,
-                                         const float (*in)[kH], float (*out)[kH], int ns) {
-    const int j = threadIdx.x & (kH - 1), half = threadIdx.x >> 7;
-    float acc[kS / 2];
+// The 128-wide products of a block's samples run on the float32
+// matrix cores (v_mfma_f32_16x16x4_f32: a 16 x 16 tile of D += A (16 x 4)
+// B (4 x 16) per instruction).  Operand layout of one instruction: lane l
+// gives A[row l % 16][k-slot l / 16] and B[k-slot l / 16][col l % 16]; the
+// result tile has lane l holding rows 4 (l / 16) + r, r = 0..3, of column
+// l % 16.  Instruction t of a 128-long contraction gives k-slot q the index
+// k = 32 q + t, so that every lane reads 32 consecutive values of its row.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+
+// The weight operands a lane needs for its tile, loaded at the start of the
+// kernel so that their latency overlaps the layers before them:
+//   rows: W[j0 + l % 16][32 q .. 32 q + 31] (Z = A W^T), q = l / 16
+//   cols: W[32 q .. 32 q + 31][i0 + l % 16] (dH = D W)
+struct WRows {
+    float4 v[8];
+};
+struct WCols {
+    float v[32];
+};
+__device__ __forceinline__ WRows load_rows(const float* __restrict__ W, int j0) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const float4* wr = reinterpret_cast<const float4*>(W + (size_t)(j0 + c) * kH + 32 * q);
+    WRows r;
 #pragma unroll
-    for (int q = 0; q < kS / 2; ++q) acc[q] = 0.0f;
-    // weights are loaded eight float4 at a time ahead of their products;
-    // each sum still runs over i in ascending order
-    const float4* wr = reinterpret_cast<const float4*>(W + (size_t)j * kH);
-    for (int i4 = 0; i4 < kH / 4; i4 += 8) {
-        float4 w[8];
+    for (int u = 0; u < 8; ++u) r.v[u] = wr[u];
+    return r;
+}
+__device__ __forceinline__ WCols load_cols(const float* __restrict__ W, int i0) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const float* wc = W + (size_t)(32 * q) * kH + i0 + c;
+    WCols r;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) w[u] = wr[i4 + u];
+    for (int t = 0; t < 32; ++t) r.v[t] = wc[(size_t)t * kH];
+    return r;
+}
+
+// Z[s][j] = sum_k A[s][k] W[j][k] for the lane's 16-column tile (A in LDS,
+// the W operand preloaded).  Returns the lane's four entries (rows
+// 4 (l / 16) + r of column j0 + l % 16).
+__device__ __forceinline__ f32x4 mm_rows_w(const float (*A)[kH], const WRows& w) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const float4* ar = reinterpret_cast<const float4*>(&A[c][32 * q]);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int q = 0; q < kS / 2; ++q) {
-                const float4 h = *reinterpret_cast<const float4*>(&in[half + 2 * q][4 * (i4 + u)]);
-                acc[q] = fmaf(w[u].x, h.x, acc[q]);
-                acc[q] = fmaf(w[u].y, h.y, acc[q]);
-                acc[q] = fmaf(w[u].z, h.z, acc[q]);
-                acc[q] = fmaf(w[u].w, h.w, acc[q]);
-            }
+    for (int u = 0; u < 8; ++u) {
+        const float4 av = ar[u];
+        acc = mfma16(av.x, w.v[u].x, acc);
+        acc = mfma16(av.y, w.v[u].y, acc);
+        acc = mfma16(av.z, w.v[u].z, acc);
+        acc = mfma16(av.w, w.v[u].w, acc);
     }
-    const float bj = b[j];
+    return acc;
+}
+
+// dH[s][i] = sum_j D[s][j] W[j][i] for the lane's 16-column tile (the
+// columns of W preloaded).
+__device__ __forceinline__ f32x4 mm_rows_wt(const float (*D)[kH], const WCols& w) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const float4* dr = reinterpret_cast<const float4*>(&D[c][32 * q]);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int q = 0; q < kS / 2; ++q) {
-        const int s = half + 2 * q;
-        if (s < ns) out[s][j] = acc[q] + bj;
+    for (int u = 0; u < 8; ++u) {
+        const float4 dv = dr[u];
+        acc = mfma16(dv.x, w.v[4 * u + 0], acc);
+        acc = mfma16(dv.y, w.v[4 * u + 1], acc);
+        acc = mfma16(dv.z, w.v[4 * u + 2], acc);
+        acc = mfma16(dv.w, w.v[4 * u + 3], acc);
+    }
+    return acc;
+}
+
+// dW[j][i] = sum_s D[s][j] H[s][i] over the block's kS samples for the
+// tile j0 .. j0+15 x i0 .. i0+15 (kS / 4 instructions, k-slot q of
+// instruction t holds sample 4 t + q), written to the partial gradient gW
+// (row-major [j][i], pitch kH).
+__device__ __forceinline__ void mm_dw(const float (*D)[kH], const float (*H)[kH], int j0, int i0,
+                                      float* __restrict__ gW) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < kS / 4; ++t) acc = mfma16(D[4 * t + q][j0 + c], H[4 * t + q][i0 + c], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gW[(size_t)(j0 + 4 * q + r) * kH + i0 + c] = acc[r];
+}
+
+// One hidden layer forward: Z = A W^T + b on the matrix cores (in each half
+// of the block, for its kHalf samples, wave w of the half takes the column
+// tile w; bj: the bias of the lane's column), then H = gelu(Z) and
+// G = gelu'(Z) to LDS.
+__device__ __forceinline__ void dense_layer(const float (*A)[kH], const WRows& W, float bj, float (*H)[kH],
+                                            float (*G)[kH]) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    const int half = wave / (kH / 16), r0 = half * kHalf;     // this half's sample rows
+    A += r0;
+    H += r0;
+    G += r0;
+    {
+        const int j0 = (wave % (kH / 16)) * 16;
+        const f32x4 z = mm_rows_w(A, W);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float zz = z[r] + bj;
+            H[4 * q + r][j0 + c] = gelu_f(zz);
+            G[4 * q + r][j0 + c] = gelu_grad_f(zz);
+        }
     }
 }
 
-// One hidden layer of the backward pass for the block's samples: from
-// DZ = dL/dZ of the layer's output, writes dW[j][i] = sum_s DZ[s][j] Hin[s][i]
-// and db[j] = sum_s DZ[s][j] to the partial gradient, and replaces DZ by
-// dL/dZ of the layer's input, (DZ W) * gelu'(Zin).
-__device__ __forceinline__ void backprop_hidden(float (*DZ)[kH], float (*DH)[kH], const float (*Hin)[kH],
-                                                const float (*Zin)[kH], const float* __restrict__ W,
-                                                float* __restrict__ gW, float* __restrict__ gb) {
-    const int tid = threadIdx.x;
-    {
-        // thread: column i of dW for 64 rows j (consecutive lanes hold
-        // consecutive i, so each row of dW is written with whole-wave stores)
-        const int i = tid & (kH - 1), j0 = (tid >> 7) * 64;
-        float acc[64];
+// One hidden layer backward: from D = dL/dZ of the layer's output (LDS),
+// writes dW = D^T Hin and db = sum_s D to the partial gradient, and replaces
+// Gin (gelu'(Zin)) by dL/dZin = (D W) * gelu'(Zin).
+__device__ __forceinline__ void backprop_hidden(const float (*D)[kH], const float (*Hin)[kH], float (*Gin)[kH],
+                                                const WCols& W, float* __restrict__ gW, float* __restrict__ gb) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
+    const int half = wave / (kH / 16), w8 = wave % (kH / 16);
+    // dW over all kS samples: wave w of row tile h takes the row tile w of
+    // dW and its share of the column tiles
+    constexpr int kColTiles = kH / 16 / kHalves;
 #pragma unroll
-        for (int u = 0; u < 64; ++u) acc[u] = 0.0f;
-        for (int s = 0; s < kS; ++s) {
-            const float h = Hin[s][i];
-            const float4* dz4 = reinterpret_cast<const float4*>(&DZ[s][j0]);
-#pragma unroll
-            for (int u4 = 0; u4 < 16; ++u4) {
-                const float4 dz = dz4[u4];
-                acc[4 * u4 + 0] = fmaf(dz.x, h, acc[4 * u4 + 0]);
-                acc[4 * u4 + 1] = fmaf(dz.y, h, acc[4 * u4 + 1]);
-                acc[4 * u4 + 2] = fmaf(dz.z, h, acc[4 * u4 + 2]);
-                acc[4 * u4 + 3] = fmaf(dz.w, h, acc[4 * u4 + 3]);
-            }
-        }
-        float* gw = gW + (size_t)j0 * kH + i;
-#pragma unroll
-        for (int u = 0; u < 64; ++u) gw[(size_t)u * kH] = acc[u];
-    }
+    for (int it = 0; it < kColTiles; ++it) mm_dw(D, Hin, w8 * 16, (half * kColTiles + it) * 16, gW);
     if (tid < kH) {
         float a = 0.0f;
-        for (int s = 0; s < kS; ++s) a += DZ[s][tid];
+        for (int s = 0; s < kS; ++s) a += D[s][tid];
         gb[tid] = a;
     }
+    // dL/dZin = (D W) * gelu'(Zin) for this half's samples, in place over
+    // Gin (read only by this lane)
     {
-        const int i = tid & (kH - 1), half = tid >> 7;
-        float acc[kS / 2];
+        const int i0 = w8 * 16, r0 = half * kHalf;
+        const f32x4 dh = mm_rows_wt(D + r0, W);
 #pragma unroll
-        for (int q = 0; q < kS / 2; ++q) acc[q] = 0.0f;
-        for (int jj = 0; jj < kH; jj += 8) {
-            float w[8];                          // eight loads ahead, jj ascending
-#pragma unroll
-            for (int u = 0; u < 8; ++u) w[u] = W[(size_t)(jj + u) * kH + i];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int q = 0; q < kS / 2; ++q) acc[q] = fmaf(DZ[half + 2 * q][jj + u], w[u], acc[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < kS / 2; ++q) DH[half + 2 * q][i] = acc[q];
-    }
-    __syncthreads();
-    for (int q = tid; q < kS * kH; q += kThreads) {
-        const int s = q / kH, i = q % kH;
-        DZ[s][i] = DH[s][i] * gelu_grad_f(Zin[s][i]);
+        for (int r = 0; r < 4; ++r) Gin[r0 + 4 * q + r][i0 + c] *= dh[r];
     }
     __syncthreads();
 }
 
+// A block takes kS samples: forward pass with all activations in LDS (H_l
+// and gelu'(Z_l) per layer) and, for training, the backward pass, writing
+// its partial gradient (one full parameter vector) and its loss sum.
 __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __restrict__ P, MlpData d, int train,
                                                                float* __restrict__ part,
                                                                float* __restrict__ part_loss,
                                                                float* __restrict__ pred) {
-    __shared__ __attribute__((aligned(16))) float X[kS][kIn];
-    __shared__ __attribute__((aligned(16))) float Z1[kS][kH], H1[kS][kH], Z2[kS][kH], H2[kS][kH], Z3[kS][kH],
-        H3[kS][kH];
-    __shared__ __attribute__((aligned(16))) float DZ[kS][kH], DH[kS][kH];
-    __shared__ float OUT[kS], DOUT[kS];
+    extern __shared__ __attribute__((aligned(16))) float mlp_lds[];
+    float (*X)[kIn] = reinterpret_cast<float (*)[kIn]>(mlp_lds);
+    float (*H1)[kH] = reinterpret_cast<float (*)[kH]>(mlp_lds + kS * kIn);
+    float (*H2)[kH] = H1 + kS;
+    float (*H3)[kH] = H2 + kS;
+    float (*G1)[kH] = H3 + kS;
+    float (*G2)[kH] = G1 + kS;
+    float (*G3)[kH] = G2 + kS;
+    __shared__ float OUT[kS], DOUT[kS], TGT[kS], W4s[kH];
     const int tid = threadIdx.x;
     const int s0 = blockIdx.x * kS;
     const int ns = min(kS, d.n - s0);
+    // every weight operand of this wave's tiles and every small parameter,
+    // loaded up front so that their latency overlaps the layers before them
+    const int tile0 = ((tid >> 6) % (kH / 16)) * 16, lc = tid & 15;
+    const WRows w2r = load_rows(P + oW2, tile0), w3r = load_rows(P + oW3, tile0);
+    WCols w3c, w2c;
+    if (train) {
+        w3c = load_cols(P + oW3, tile0);
+        w2c = load_cols(P + oW2, tile0);
+    }
+    const int j1 = tid & (kH - 1);
+    const float4 w1v = *reinterpret_cast<const float4*>(P + oW1 + j1 * kIn);
+    const float b1v = P[ob1 + j1], b2v = P[ob2 + tile0 + lc], b3v = P[ob3 + tile0 + lc], b4v = P[ob4];
+    if (tid < kH) W4s[tid] = P[oW4 + tid];
     if (tid < kS) {
         float f[kIn] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float tg = 0.0f;
         if (tid < ns) {
             const int q = d.idx ? d.idx[s0 + tid] : s0 + tid;
+            if (train) tg = d.target[q];
             encode(d.c1, d.c2, d.m, d.r, q, f);
         }
+        TGT[tid] = tg;
 #pragma unroll
         for (int k = 0; k < kIn; ++k) X[tid][k] = f[k];
     }
     __syncthreads();
-    // layer 1 (4 -> 128)
+    // layer 1 (4 -> 128) on the vector units
     {
-        const int j = tid & (kH - 1), half = tid >> 7;
-        const float w0 = P[oW1 + j * kIn + 0], w1 = P[oW1 + j * kIn + 1], w2 = P[oW1 + j * kIn + 2],
-                    w3 = P[oW1 + j * kIn + 3], bj = P[ob1 + j];
-        for (int s = half; s < kS; s += 2) {
+        const int j = j1, part0 = tid / kH;
+        const float w0 = w1v.x, w1 = w1v.y, w2 = w1v.z, w3 = w1v.w, bj = b1v;
+        for (int s = part0; s < kS; s += kThreads / kH) {
             float a = fmaf(w0, X[s][0], 0.0f);
             a = fmaf(w1, X[s][1], a);
             a = fmaf(w2, X[s][2], a);
             a = fmaf(w3, X[s][3], a);
             a += bj;
-            Z1[s][j] = a;
             H1[s][j] = gelu_f(a);
+            G1[s][j] = gelu_grad_f(a);
         }
     }
     __syncthreads();
-    dense128(P + oW2, P + ob2, H1, Z2, kS);
+    dense_layer(H1, w2r, b2v, H2, G2);
     __syncthreads();
-    for (int q = tid; q < kS * kH; q += kThreads) H2[q / kH][q % kH] = gelu_f(Z2[q / kH][q % kH]);
-    __syncthreads();
-    dense128(P + oW3, P + ob3, H2, Z3, kS);
-    __syncthreads();
-    for (int q = tid; q < kS * kH; q += kThreads) H3[q / kH][q % kH] = gelu_f(Z3[q / kH][q % kH]);
+    dense_layer(H2, w3r, b3v, H3, G3);
     __syncthreads();
     if (tid < kS) {
         float a = 0.0f;
-        for (int i = 0; i < kH; ++i) a = fmaf(P[oW4 + i], H3[tid][i], a);
-        a += P[ob4];
+        for (int i = 0; i < kH; ++i) a = fmaf(W4s[i], H3[tid][i], a);
+        a += b4v;
         OUT[tid] = a;
         if (tid < ns) {
             if (pred) pred[s0 + tid] = a;
-            if (train) {
-                const int q = d.idx ? d.idx[s0 + tid] : s0 + tid;
-                DOUT[tid] = d.inv_batch2 * (a - d.target[q]);
-            }
+            if (train) DOUT[tid] = d.inv_batch2 * (a - TGT[tid]);
         } else {
             DOUT[tid] = 0.0f;
         }
     }
     __syncthreads();
     if (!train) return;
-    float* g = part + (size_t)blockIdx.x * kParams;
+    float* g = part + (size_t)blockIdx.x * kPartStride;
     if (tid == 0) {
         float l = 0.0f, db = 0.0f;
         for (int s = 0; s < ns; ++s) {
-            const int q = d.idx ? d.idx[s0 + s] : s0 + s;
-            const float e = OUT[s] - d.target[q];
+            const float e = OUT[s] - TGT[s];
             l = fmaf(e, e, l);
             db += DOUT[s];
         }
         part_loss[blockIdx.x] = l;
         g[ob4] = db;
     }
-    // output layer: dW4, dZ3
+    // output layer: dW4; then dL/dZ3 = DOUT W4 gelu'(Z3) in place over G3
     if (tid < kH) {
         float a = 0.0f;
         for (int s = 0; s < kS; ++s) a = fmaf(DOUT[s], H3[s][tid], a);
@@ -238,17 +310,17 @@ __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __re
     }
     for (int q = tid; q < kS * kH; q += kThreads) {
         const int s = q / kH, i = q % kH;
-        DZ[s][i] = DOUT[s] * P[oW4 + i] * gelu_grad_f(Z3[s][i]);
+        G3[s][i] = DOUT[s] * W4s[i] * G3[s][i];
     }
     __syncthreads();
-    // hidden layers 3 and 2: dW = dZ^T H_in, db = sum dZ, dH_in = dZ W
-    backprop_hidden(DZ, DH, H2, Z2, P + oW3, g + oW3, g + ob3);
-    backprop_hidden(DZ, DH, H1, Z1, P + oW2, g + oW2, g + ob2);
+    // hidden layers 3 and 2: dW = dZ^T H_in, db = sum dZ, dZ_in = (dZ W) gelu'(Z_in)
+    backprop_hidden(G3, H2, G2, w3c, g + oW3, g + ob3);
+    backprop_hidden(G2, H1, G1, w2c, g + oW2, g + ob2);
     // first layer: dW1[j][k] = sum_s dZ1[s][j] X[s][k], db1
     if (tid < kH) {
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, b = 0.0f;
         for (int s = 0; s < kS; ++s) {
-            const float dz = DZ[s][tid];
+            const float dz = G1[s][tid];
             a0 = fmaf(dz, X[s][0], a0);
             a1 = fmaf(dz, X[s][1], a1);
             a2 = fmaf(dz, X[s][2], a2);
@@ -264,12 +336,12 @@ __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __re
 }
 
 // Sum of the block partials -> Adam update or plain gradient.  A block takes
-// kRedParams parameters; its kRedGroups thread groups each add every
-// kRedGroups-th partial (group g: partials g, g + kRedGroups, ...), and the
-// group sums are added in group order, so the result is fixed for a given
-// number of partials.
+// kRedParams parameters; its thread (group g, quad u) adds parameters
+// 4u .. 4u+3 of every kRedGroups-th partial (g, g + kRedGroups, ...) with
+// 16-byte loads, eight in flight, and the group sums are added in group
+// order, so the result is fixed for a given number of partials.
 constexpr int kRedParams = 64;
-constexpr int kRedGroups = 256 / kRedParams;
+constexpr int kRedGroups = 256 / (kRedParams / 4);
 
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ part, int nblk,
                                                          float* __restrict__ P, float* __restrict__ adam,
@@ -278,10 +350,8 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict
                                                          const float* __restrict__ part_loss, float inv_batch,
                                                          float* __restrict__ loss_out) {
     __shared__ float gs[kRedGroups][kRedParams];
-    const int pl = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
-    const int p = blockIdx.x * kRedParams + pl;
-    // both sums issue their loads eight at a time and add them in the same
-    // order as a plain loop
+    const int quad = threadIdx.x % (kRedParams / 4), grp = threadIdx.x / (kRedParams / 4);
+    const int p4 = blockIdx.x * kRedParams + 4 * quad;        // first of the thread's four parameters
     if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
         float l = 0.0f;
         int b = 0;
@@ -295,21 +365,37 @@ __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict
         for (; b < nblk; ++b) l += part_loss[b];
         *loss_out = l * inv_batch;
     }
-    float acc = 0.0f;
-    if (p < kParams) {
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (p4 < kParams) {
         int b = grp;
         for (; b + 7 * kRedGroups < nblk; b += 8 * kRedGroups) {
-            float v[8];
+            float4 v[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = part[(size_t)(b + i * kRedGroups) * kParams + p];
+            for (int i = 0; i < 8; ++i)
+                v[i] = *reinterpret_cast<const float4*>(part + (size_t)(b + i * kRedGroups) * kPartStride + p4);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc += v[i];
+            for (int i = 0; i < 8; ++i) {
+                acc.x += v[i].x;
+                acc.y += v[i].y;
+                acc.z += v[i].z;
+                acc.w += v[i].w;
+            }
         }
-        for (; b < nblk; b += kRedGroups) acc += part[(size_t)b * kParams + p];
+        for (; b < nblk; b += kRedGroups) {
+            const float4 v = *reinterpret_cast<const float4*>(part + (size_t)b * kPartStride + p4);
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
     }
-    gs[grp][pl] = acc;
+    gs[grp][4 * quad + 0] = acc.x;
+    gs[grp][4 * quad + 1] = acc.y;
+    gs[grp][4 * quad + 2] = acc.z;
+    gs[grp][4 * quad + 3] = acc.w;
     __syncthreads();
-    if (grp != 0 || p >= kParams) return;
+    const int pl = threadIdx.x, p = blockIdx.x * kRedParams + pl;
+    if (pl >= kRedParams || p >= kParams) return;
     float gsum = gs[0][pl];
 #pragma unroll
     for (int g = 1; g < kRedGroups; ++g) gsum += gs[g][pl];
@@ -375,11 +461,28 @@ struct Mlp {
     float* part_loss = nullptr;
 };
 
-static int launch_step(Mlp& M, const float* P, const MlpData& d, int train, float* pred, hipStream_t s) {
+// The forward/backward kernel takes more than 64 KB of LDS: raise its limit
+// once (gfx950 has 160 KB per compute unit).
+static int fwd_bwd_lds_once() {
+    static const int st = hip_check((int)hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_fwd_bwd_kernel),
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                             (int)kMlpLds),
+                                    "hipFuncSetAttribute");
+    return st;
+}
+
+static int launch_fwd_bwd(const float* P, const MlpData& d, int train, float* part, float* part_loss, float* pred,
+                          hipStream_t s) {
+    const int st = fwd_bwd_lds_once();
+    if (st != WG_OK) return st;
     const int nblk = (d.n + kS - 1) / kS;
-    hipLaunchKernelGGL(mlp_fwd_bwd_kernel, dim3(nblk), dim3(kThreads), 0, s, P, d, train, M.part, M.part_loss,
+    hipLaunchKernelGGL(mlp_fwd_bwd_kernel, dim3(nblk), dim3(kThreads), kMlpLds, s, P, d, train, part, part_loss,
                        pred);
     return hip_check((int)hipGetLastError(), "mlp_fwd_bwd_kernel");
+}
+
+static int launch_step(Mlp& M, const float* P, const MlpData& d, int train, float* pred, hipStream_t s) {
+    return launch_fwd_bwd(P, d, train, M.part, M.part_loss, pred, s);
 }
 
 }  // namespace wg
@@ -396,7 +499,7 @@ int wg_mlp_create(wg_mlp** out, int max_batch) {
     if (!M) return fail(WG_ENOMEM, "wg_mlp_create: out of host memory");
     M->max_batch = max_batch;
     const size_t nblk = (size_t)(max_batch + kS - 1) / kS;
-    if (hipMalloc((void**)&M->part, sizeof(float) * nblk * kParams) != hipSuccess ||
+    if (hipMalloc((void**)&M->part, sizeof(float) * nblk * kPartStride) != hipSuccess ||
         hipMalloc((void**)&M->part_loss, sizeof(float) * nblk) != hipSuccess) {
         if (M->part) (void)hipFree(M->part);
         delete M;
@@ -477,9 +580,7 @@ int wg_mlp_predict(const float* params, const double* c1, const double* c2, cons
     int st = check_data(c1, m, r, n);
     if (st != WG_OK) return st;
     const MlpData d{c1, c2, m, r, nullptr, nullptr, n, 0.0f};
-    hipLaunchKernelGGL(mlp_fwd_bwd_kernel, dim3((n + kS - 1) / kS), dim3(kThreads), 0,
-                       static_cast<hipStream_t>(stream), params, d, 0, nullptr, nullptr, out);
-    return hip_check((int)hipGetLastError(), "mlp_fwd_bwd_kernel");
+    return launch_fwd_bwd(params, d, 0, nullptr, nullptr, out, static_cast<hipStream_t>(stream));
 }
 
 int wg_topk_min(const float* v, int n, int k, int* idx_out, wg_stream_t stream) {
