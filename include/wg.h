@@ -329,10 +329,10 @@ int wg_score_error_noalloc(const float* y, const double* y_ref, size_t count, do
  * Batched error sweep (device).  Section 6.1 traces the error of a point
  * family as a function of c; Section 6.3 scores many combinations.  For each
  * candidate (c1[i], c2[i]) the family of wg_family_points for
- * alpha = m + r - 1 is built, its matrices are constructed in float64 on the
- * device (float64 values whose magnitude is below the rounding noise of their
- * own computation are set to zero, so exact cancellations give zeros) and
- * rounded to float32, and float32 Winograd tiles (1D eq. conv_1d or 2D
+ * alpha = m + r - 1 is built, its matrices are constructed on the device as
+ * the float64 roundings of their exact values (Sections 4.1, 4.2; the same
+ * matrices as wg_transforms) and rounded to float32, and float32 Winograd
+ * tiles (1D eq. conv_1d or 2D
  * eq. conv_2d, evaluated as the layer's transforms are) are scored on the
  * first counts[i] samples of a shared pool against the float64 direct
  * correlation of each sample.
@@ -360,9 +360,18 @@ int wg_sweep_destroy(wg_sweep* sweep);      /* NULL is accepted */
  * [0, n_pool]).  out: device float64 [n_cand][4] =
  *   { sum |y - y_ref| (+inf when flagged), sum |y_ref|,
  *     number of outputs scored, flag (1: c not finite or zero, points
- *     coincide, |N_i| < 1e-300 or an entry overflows float32) }.
+ *     coincide, |N_i| < 1e-300, an entry overflows float32, or the exact
+ *     construction below needs integers over 1024 bits) }.
  * mean absolute error = out[0]/out[2]; relative L1 = out[0]/out[1].
- * The three launches of a run (construct, persistent evaluation, finalize)
+ * Every matrix entry is the float64 number nearest (ties to even) to its
+ * exact value for the candidate's float64 points, as wg_transforms builds
+ * it, and its float32 rounding: the construction evaluates each entry in
+ * double-word arithmetic with a rigorous error bound and keeps it when the
+ * bound decides the rounding (structural zeros of symmetric point sets come
+ * out exact); candidates with an undecided entry are rebuilt in exact
+ * multi-limb integer arithmetic by a second launch.
+ * The four launches of a run (construct, exact rebuild, persistent
+ * evaluation, finalize)
  * are captured in a hipGraph on the first call with a given argument set
  * and replayed on later calls with the same arguments; the result is
  * bitwise reproducible for a given tuning.  Runs on one sweep object must
@@ -396,7 +405,9 @@ int wg_sweep_autotune(wg_sweep* sweep, const double* c1, const double* c2, const
 int wg_sweep_tuning(const wg_sweep* sweep, int* block, int* chunk, int* blocks_per_cu);
 
 /* The float32 matrices the last run built for candidate `cand` (host
- * outputs, sizes as wg_transforms) and its flag; synchronous. */
+ * outputs, sizes as wg_transforms) and its flag: 1 flagged, 2 built by the
+ * exact integer construction, 0 built by the certified double-word
+ * construction; synchronous. */
 int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, float* BT, int* flag);
 
 /* Precision of the evaluated tiles (Section 6: besides the plain float32
@@ -416,6 +427,15 @@ int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, floa
  * Errors: WG_EINVAL (null sweep, unknown mode), WG_ENOMEM. */
 enum { WG_SWEEP_F32 = 0, WG_SWEEP_MIXED = 1 };
 int wg_sweep_set_precision(wg_sweep* sweep, int mode);
+
+/* always = 1: every valid candidate of later runs is built by the exact
+ * integer construction (the second launch of a run), bypassing the
+ * certified double-word one; always = 0 (default): only candidates the
+ * certified construction cannot decide.  Both give the same matrices; the
+ * switch serves to check that and to time the exact path.  Later runs
+ * rebuild the captured graph.  Errors: WG_EINVAL (null sweep, always not
+ * 0 or 1). */
+int wg_sweep_set_exact(wg_sweep* sweep, int always);
 
 /* The float64 matrices the last mixed-precision run built for candidate
  * `cand` (host outputs, sizes as wg_transforms); synchronous.  WG_EINVAL if

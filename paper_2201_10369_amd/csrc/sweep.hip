@@ -2,15 +2,19 @@
 //
 // For thousands of candidate point sets (the families of Section 5 of
 // arXiv:2201.10369, parameterised by c1 and c2) the sweep builds each set's
-// transform matrices in float64 on the device (Sections 4.1, 4.2), rounds
-// them to float32, evaluates float32 Winograd tiles (1D eq. conv_1d or 2D
+// transform matrices on the device (Sections 4.1, 4.2) as the float64
+// roundings of their exact values, rounds those to float32, evaluates
+// float32 Winograd tiles (1D eq. conv_1d or 2D
 // eq. conv_2d) on the first n_i samples of a shared pool, and sums the L1
 // error against the float64 direct correlation of each sample (Section 6;
 // Section 6.1 sweeps c over a range, Section 6.3 scores many combinations).
 //
 // Launch structure (one hipGraph, replayed):
-//   construct : one thread per (candidate, matrix row), float64
-//               construction -> float32
+//   construct : one thread per (candidate, matrix row), float64 with a
+//               running error bound -> the float32 matrices
+//   rebuild   : the same threads for the candidates the first launch left
+//               pending (others return at once): double words with an error
+//               bound, exact integers for rows they cannot decide
 //   evaluate  : persistent blocks stride over work items (candidate, or
 //               in 1D a group of four candidates that share each loaded
 //               sample; chunk of `chunk` samples); per item a fixed-order
@@ -27,6 +31,7 @@
 #include <string>
 #include <type_traits>
 
+#include "wg_construct.h"
 #include "wg_device.h"
 #include "wg_internal.h"
 #include "wg_sweep_internal.h"
@@ -60,146 +65,164 @@ __device__ int family_points_dev(int alpha, double c1, double c2, double* p) {
     return n;
 }
 
-// Coefficients of prod (x - a_j) over the roots, with the coefficients of
-// prod (x + |a_j|) as magnitude bounds; a coefficient no larger than the
-// float64 rounding noise of its own computation is set to zero (the point
-// families are built so that such coefficients cancel exactly).
-template <int A>
-__device__ void product_poly_snapped(const double* roots, int n, double* coef) {
-    double bnd[A + 1];
-    coef[0] = 1.0;
-    bnd[0] = 1.0;
-    for (int i = 1; i <= n; ++i) coef[i] = bnd[i] = 0.0;
-    for (int t = 0; t < n; ++t) {
-        const double a = roots[t], aa = fabs(roots[t]);
-        for (int i = t + 1; i >= 1; --i) {
-            coef[i] = coef[i - 1] - a * coef[i];
-            bnd[i] = bnd[i - 1] + aa * bnd[i];
-        }
-        coef[0] = -a * coef[0];
-        bnd[0] = aa * bnd[0];
-    }
-    const double tol = 4.0 * (n + 1) * 1.1102230246251565e-16;   // 4 (n+1) 2^-53
-    for (int i = 0; i <= n; ++i)
-        if (fabs(coef[i]) <= tol * bnd[i]) coef[i] = 0.0;
-}
+// Candidate flags between the launches of a run: kFlagBad (not finite,
+// zero parameter, coinciding points, |N_i| < 1e-300, an entry overflows
+// float32, or integers beyond the exact construction's limbs), kFlagPending
+// (left to sweep_rebuild_kernel) and kFlagExact (some row built from exact
+// integers).
+constexpr int kFlagBad = 1;
+constexpr int kFlagPending = 2;
+constexpr int kFlagExact = 4;
 
-// One thread per (candidate, row): thread i < alpha-1 builds what point i
-// owns (column i of A^T, row i of G, row i of B^T), thread alpha-1 the
-// infinity row and column; a block holds kConsCands candidates in slots of
-// kConsRows lanes.  Every entry gets the same float64 operations in the same
-// order as a single-thread construction would apply.  A candidate is flagged
-// (and its matrices left zero) when a parameter is zero or not finite or two
-// points coincide (|N_i| < 1e-300); it is also flagged when an entry comes
-// out non-finite.  With explicit point lists (pts_in, n_cand x (alpha-1),
-// infinity implied last) a non-finite point flags the candidate instead.
-// mats64 (optional) receives the float64 values before the float32 rounding
-// (the matrices of the mixed-precision evaluation).
-constexpr int kConsRows = 16;
-constexpr int kConsCands = 256 / kConsRows;
+// Both construction kernels: one thread per (candidate, row), thread i <
+// alpha-1 builds what point i owns (column i of A^T, row i of G, row i of
+// B^T), thread alpha-1 the infinity row and column.  A wave holds row i of
+// kConsCands consecutive candidates, so its lanes follow the same path
+// through the root grouping (the rows of one candidate differ in it).  With
+// explicit point lists (pts_in, n_cand x (alpha-1), infinity implied last)
+// a non-finite point flags the candidate.  Row statuses pass from the first
+// kernel to the second in row_status[cand][row] (kRowStride bytes per
+// candidate): 0 built, 1 flags the candidate, 2 left to the second kernel.
+constexpr int kConsCands = 64;
+constexpr int kRowStride = 16;
 
 template <int M, int R>
-__global__ __launch_bounds__(256) void sweep_construct_kernel(const double* __restrict__ c1,
-                                                              const double* __restrict__ c2,
-                                                              const double* __restrict__ pts_in, int n_cand,
-                                                              float* __restrict__ mats,
-                                                              double* __restrict__ mats64,
-                                                              int* __restrict__ flags) {
+__device__ __forceinline__ void candidate_points(const double* __restrict__ c1, const double* __restrict__ c2,
+                                                 const double* __restrict__ pts_in, int cand, double* pts,
+                                                 int& flag) {
     constexpr int A = M + R - 1;
     constexpr int NF = A - 1;
-    static_assert(A <= kConsRows, "rows per candidate slot");
-    __shared__ int bad[2][kConsCands];
-    const int slot = threadIdx.x / kConsRows, i = threadIdx.x % kConsRows;
-    const int cand = blockIdx.x * kConsCands + slot;
-    const bool live = cand < n_cand && i < A;
-    if (i == 0) bad[0][slot] = bad[1][slot] = 0;
-    __syncthreads();
-    double pts[NF];
-    int flag = 0;
-    if (live && pts_in != nullptr) {
+    if (pts_in != nullptr) {
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
             pts[j] = pts_in[(size_t)cand * NF + j];
             if (!isfinite(pts[j])) flag = 1;
         }
-    } else if (live) {
+    } else {
         const double x1 = c1[cand], x2 = c2 != nullptr ? c2[cand] : 1.0;
         if (!isfinite(x1) || x1 == 0.0 || (A > 6 && (!isfinite(x2) || x2 == 0.0))) flag = 1;
         if (!flag) family_points_dev(A, x1, x2, pts);
     }
-    // point i and the others in order, picked with constant indices (no
-    // dynamically indexed private arrays)
-    double a = 0.0, others[NF];
-    if (live && !flag) {
+}
+
+// Writes one row (RowOut layout) into the candidate's float32 matrices and,
+// when given, its float64 ones; returns whether a float32 entry overflows.
+template <int M, int R>
+__device__ __forceinline__ int store_row(const cons::RowOut<M, R>& o, int i, float* out, double* out64) {
+    constexpr int A = M + R - 1;
+    int nonfinite = 0;
 #pragma unroll
-        for (int j = 0; j < NF; ++j)
-            if (j == i) a = pts[j];
-#pragma unroll
-        for (int j = 0; j + 1 < NF; ++j) others[j] = j < i ? pts[j] : pts[j + 1];
+    for (int j = 0; j < M; ++j) {
+        out[j * A + i] = o.v32[j];
+        nonfinite |= !isfinite(o.v32[j]);
+        if (out64) out64[j * A + i] = o.v64[j];
     }
-    double norm = 1.0;
-    if (live && !flag && i < NF) {
 #pragma unroll
-        for (int j = 0; j + 1 < NF; ++j) norm *= (a - others[j]);
-        if (!(fabs(norm) >= 1e-300) || !isfinite(norm)) flag = 1;
+    for (int k = 0; k < R; ++k) {
+        out[M * A + i * R + k] = o.v32[M + k];
+        nonfinite |= !isfinite(o.v32[M + k]);
+        if (out64) out64[M * A + i * R + k] = o.v64[M + k];
     }
-    if (flag) bad[0][slot] = 1;
+#pragma unroll
+    for (int l = 0; l < A; ++l) {
+        out[M * A + A * R + i * A + l] = o.v32[M + R + l];
+        nonfinite |= !isfinite(o.v32[M + R + l]);
+        if (out64) out64[M * A + A * R + i * A + l] = o.v64[M + R + l];
+    }
+    return nonfinite;
+}
+
+// First construction: float64 with a running error bound decides the
+// float32 matrices (RN32 of RN64 of the exact entries) of nearly every
+// candidate.  Grid (candidate groups, alpha), one wave per block: the whole
+// chip takes part.  Rows it cannot decide, every valid row of a
+// mixed-precision run (which needs the float64 matrices) and, with
+// force_exact, every valid row are left to the second kernel.
+template <int M, int R>
+__global__ __launch_bounds__(kConsCands) void sweep_construct_kernel(const double* __restrict__ c1,
+                                                                     const double* __restrict__ c2,
+                                                                     const double* __restrict__ pts_in,
+                                                                     int n_cand, int defer_all,
+                                                                     float* __restrict__ mats,
+                                                                     uint8_t* __restrict__ row_status) {
+    constexpr int A = M + R - 1;
+    constexpr int NF = A - 1;
+    static_assert(A <= kRowStride, "rows per candidate");
+    const int cand = blockIdx.x * kConsCands + threadIdx.x, i = blockIdx.y;
+    if (cand >= n_cand) return;
+    double pts[NF];
+    int flag = 0;
+    candidate_points<M, R>(c1, c2, pts_in, cand, pts, flag);
+    int st = 1;
+    if (!flag) {
+        cons::RowOut<M, R> o;
+        st = cons::row_cert<cons::ArithF64, M, R>(pts, i, o);
+        if (st == 0 && defer_all) st = 2;
+        if (st == 0 && store_row<M, R>(o, i, mats + (size_t)cand * kMatStride, nullptr)) st = 1;
+    }
+    row_status[(size_t)cand * kRowStride + i] = (uint8_t)st;
+}
+
+// Second construction: combines the row statuses of each candidate into
+// its flag and rebuilds the candidates with an undecided row: double words
+// with an error bound decide the float64 entries, rows they cannot decide
+// (or every row, with force_exact) are built from exact integers.  Writes
+// the float32 matrices and, when mats64 is given, the float64 ones; flagged
+// candidates get zero matrices.  A block holds kConsCands candidates and
+// alpha waves (wave i: row i).
+template <int M, int R>
+__global__ __launch_bounds__(kConsCands * 10) void sweep_rebuild_kernel(const double* __restrict__ c1,
+                                                                        const double* __restrict__ c2,
+                                                                        const double* __restrict__ pts_in,
+                                                                        int n_cand, int force_exact,
+                                                                        const uint8_t* __restrict__ row_status,
+                                                                        float* __restrict__ mats,
+                                                                        double* __restrict__ mats64,
+                                                                        int* __restrict__ flags) {
+    constexpr int NF = M + R - 2;
+    static_assert(M + R - 1 <= 10, "rows per block");
+    // per candidate: a row flags it, exact integers used, a row pending, the
+    // rebuild failed or overflowed float32
+    __shared__ int s_flag[kConsCands], s_exact[kConsCands], s_pend[kConsCands], s_fail[kConsCands];
+    const int slot = threadIdx.x % kConsCands, i = threadIdx.x / kConsCands;
+    const int cand = blockIdx.x * kConsCands + slot;
+    const bool live = cand < n_cand;
+    if (i == 0) s_flag[slot] = s_exact[slot] = s_pend[slot] = s_fail[slot] = 0;
     __syncthreads();
-    flag = bad[0][slot];
-    float* out = mats + (size_t)(live ? cand : 0) * kMatStride;
-    float* AT = out;
-    float* G = out + M * A;
-    float* BT = out + M * A + A * R;
-    double at[M], gr[R], bt[A];
-    for (int j = 0; j < M; ++j) at[j] = 0.0;
-    for (int k = 0; k < R; ++k) gr[k] = 0.0;
-    for (int l = 0; l < A; ++l) bt[l] = 0.0;
-    if (live && !flag) {
-        double coef[A + 1];
-        if (i < NF) {
-            double pw = 1.0;
-            for (int j = 0; j < M; ++j) {
-                at[j] = pw;
-                pw *= a;
-            }
-            pw = 1.0;
-            for (int k = 0; k < R; ++k) {
-                gr[k] = pw / norm;
-                pw *= a;
-            }
-            product_poly_snapped<A>(others, NF - 1, coef);
-#pragma unroll
-            for (int l = 0; l < NF; ++l) bt[l] = coef[l];
-        } else {
-            at[M - 1] = 1.0;
-            gr[R - 1] = 1.0;
-            product_poly_snapped<A>(pts, NF, coef);
-#pragma unroll
-            for (int l = 0; l <= NF; ++l) bt[l] = coef[l];
+    const int st0 = live ? row_status[(size_t)cand * kRowStride + i] : 0;
+    if (st0 == 1) s_flag[slot] = 1;
+    if (st0 == 2) s_pend[slot] = 1;
+    __syncthreads();
+    const bool pending = live && !s_flag[slot] && s_pend[slot];
+    cons::RowOut<M, R> o;
+    if (pending) {
+        double pts[NF];
+        int flag = 0;
+        candidate_points<M, R>(c1, c2, pts_in, cand, pts, flag);
+        int st = force_exact ? 2 : cons::row_cert<cons::ArithDW, M, R>(pts, i, o);
+        if (st == 2) {
+            st = cons::exact_row<M, R>(pts, i, o);
+            s_exact[slot] = 1;
         }
+        if (flag || st != 0) s_fail[slot] = 1;
     }
-    if (live) {
+    __syncthreads();
+    const bool bad = live && (s_flag[slot] || s_fail[slot]);
+    if (live && (bad || pending)) {
+        if (bad) {
+#pragma unroll
+            for (int q = 0; q < cons::RowOut<M, R>::kN; ++q) {
+                o.v32[q] = 0.0f;
+                o.v64[q] = 0.0;
+            }
+        }
+        float* out = mats + (size_t)cand * kMatStride;
         double* out64 = mats64 != nullptr ? mats64 + (size_t)cand * kMatStride : nullptr;
-        int nonfinite = 0;
-        for (int j = 0; j < M; ++j) {
-            AT[j * A + i] = (float)at[j];
-            nonfinite |= !isfinite((float)at[j]);
-            if (out64) out64[j * A + i] = at[j];
-        }
-        for (int k = 0; k < R; ++k) {
-            G[i * R + k] = (float)gr[k];
-            nonfinite |= !isfinite((float)gr[k]);
-            if (out64) out64[M * A + i * R + k] = gr[k];
-        }
-        for (int l = 0; l < A; ++l) {
-            BT[i * A + l] = (float)bt[l];
-            nonfinite |= !isfinite((float)bt[l]);
-            if (out64) out64[M * A + A * R + i * A + l] = bt[l];
-        }
-        if (nonfinite) bad[1][slot] = 1;
+        if (store_row<M, R>(o, i, out, out64)) s_fail[slot] = 1;      // float32 overflow
     }
     __syncthreads();
-    if (live && i == 0) flags[cand] = flag | bad[1][slot];
+    if (live && i == 0)
+        flags[cand] = (s_flag[slot] || s_fail[slot]) ? kFlagBad : (s_exact[slot] ? kFlagExact : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -589,7 +612,7 @@ __global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict
             int n = cand < n_cand ? counts[cand] : 0;
             n = n < 0 ? 0 : (n > n_pool ? n_pool : n);
             nj[j] = n;
-            lj[j] = cand < n_cand && flags[cand] == 0 && start < n;    // uniform over the block
+            lj[j] = cand < n_cand && !(flags[cand] & kFlagBad) && start < n;    // uniform over the block
             any |= lj[j];
             if (lj[j]) nmax = max(nmax, n);
         }
@@ -672,7 +695,7 @@ __global__ __launch_bounds__(256) void sweep_finalize_kernel(const double* __res
     n = n < 0 ? 0 : (n > n_pool ? n_pool : n);
     double e = 0.0;
     for (int q = 0; q < ipc; ++q) e += partial[(size_t)cand * ipc + q];
-    const int fl = flags[cand];
+    const int fl = flags[cand] & kFlagBad;
     out[(size_t)cand * 4 + 0] = fl ? INFINITY : e;
     out[(size_t)cand * 4 + 1] = prefix[n];
     out[(size_t)cand * 4 + 2] = (double)n * outs_per_sample;
@@ -701,8 +724,11 @@ struct SweepOps {
     static void run(const Sweep& S, const SweepArgs& a, const SweepTune& t, hipStream_t st) {
         const int ipc = (S.n_pool + t.chunk - 1) / t.chunk;
         double* m64 = S.mixed ? S.mats64 : nullptr;
-        hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3((a.n_cand + kConsCands - 1) / kConsCands),
-                           dim3(256), 0, st, a.c1, a.c2, a.pts, a.n_cand, S.mats, m64, S.flags);
+        const unsigned cons_grid = (unsigned)((a.n_cand + kConsCands - 1) / kConsCands);
+        hipLaunchKernelGGL((sweep_construct_kernel<M, R>), dim3(cons_grid, M + R - 1), dim3(kConsCands), 0, st,
+                           a.c1, a.c2, a.pts, a.n_cand, (S.exact_all || S.mixed) ? 1 : 0, S.mats, S.row_status);
+        hipLaunchKernelGGL((sweep_rebuild_kernel<M, R>), dim3(cons_grid), dim3(kConsCands * (M + R - 1)), 0, st,
+                           a.c1, a.c2, a.pts, a.n_cand, S.exact_all, S.row_status, S.mats, m64, S.flags);
         const long items = (long)((a.n_cand + (DIMS == 1 ? kGroup1d : 1) - 1) / (DIMS == 1 ? kGroup1d : 1)) * ipc;
         long grid = (long)S.n_cu * t.blocks_per_cu;
         if (grid > items) grid = items;
@@ -768,7 +794,8 @@ static void release(Sweep* S) {
     if (S->exec) (void)hipGraphExecDestroy(S->exec);
     if (S->graph) (void)hipGraphDestroy(S->graph);
     if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
-    void* bufs[] = {S->d_soa, S->g_soa, S->yref, S->ref_abs, S->prefix, S->mats, S->mats64, S->flags, S->partial};
+    void* bufs[] = {S->d_soa, S->g_soa, S->yref, S->ref_abs, S->prefix, S->mats, S->mats64, S->flags, S->row_status,
+                    S->partial};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete S;
@@ -810,6 +837,7 @@ int wg_sweep_create(wg_sweep** out, int m, int r, int dims, const float* d_pool,
         {(void**)&S->prefix, sizeof(double) * (size_t)(n_pool + 1)},
         {(void**)&S->mats, sizeof(float) * (size_t)max_cand * kMatStride},
         {(void**)&S->flags, sizeof(int) * (size_t)max_cand},
+        {(void**)&S->row_status, (size_t)kRowStride * max_cand},
         {(void**)&S->partial, sizeof(double) * (size_t)max_cand * max_ipc},
     };
     for (auto& a : allocs) {
@@ -947,6 +975,18 @@ int wg_sweep_set_precision(wg_sweep* sweep, int mode) {
     return WG_OK;
 }
 
+int wg_sweep_set_exact(wg_sweep* sweep, int always) {
+    if (!sweep) return fail(WG_EINVAL, "wg_sweep_set_exact: null sweep");
+    if (always != 0 && always != 1) return fail(WG_EINVAL, "wg_sweep_set_exact: always must be 0 or 1");
+    Sweep& S = *reinterpret_cast<Sweep*>(sweep);
+    if (S.exact_all != always) {
+        S.exact_all = always;
+        if (S.exec) { (void)hipGraphExecDestroy(S.exec); S.exec = nullptr; }
+        if (S.graph) { (void)hipGraphDestroy(S.graph); S.graph = nullptr; }
+    }
+    return WG_OK;
+}
+
 int wg_sweep_matrices_f64(const wg_sweep* sweep, int cand, double* AT, double* G, double* BT) {
     if (!sweep || !AT || !G || !BT) return fail(WG_EINVAL, "wg_sweep_matrices_f64: null pointer");
     const Sweep& S = *reinterpret_cast<const Sweep*>(sweep);
@@ -971,8 +1011,10 @@ int wg_sweep_matrices(const wg_sweep* sweep, int cand, float* AT, float* G, floa
     float buf[kMatStride];
     int st = hipc(hipMemcpy(buf, S.mats + (size_t)cand * kMatStride, sizeof(buf), hipMemcpyDeviceToHost),
                   "hipMemcpy");
-    if (st == WG_OK) st = hipc(hipMemcpy(flag, S.flags + cand, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+    int raw = 0;
+    if (st == WG_OK) st = hipc(hipMemcpy(&raw, S.flags + cand, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
     if (st != WG_OK) return st;
+    *flag = (raw & kFlagBad) ? 1 : ((raw & kFlagExact) ? 2 : 0);
     std::memcpy(AT, buf, sizeof(float) * m * A);
     std::memcpy(G, buf + m * A, sizeof(float) * A * r);
     std::memcpy(BT, buf + m * A + A * r, sizeof(float) * A * A);

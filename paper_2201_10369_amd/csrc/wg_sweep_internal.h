@@ -40,7 +40,9 @@ struct Sweep {
     float* mats = nullptr;       // per candidate float32 A^T | G | B^T
     double* mats64 = nullptr;    // the same in float64 (mixed precision only)
     int mixed = 0;               // 1: float64 transforms, float32 Hadamard product
-    int* flags = nullptr;        // per candidate: 1 = invalid or singular
+    int* flags = nullptr;        // per candidate: 1 = invalid or singular, 4 = built exactly
+    int exact_all = 0;           // 1: every candidate built by the exact integer kernel
+    uint8_t* row_status = nullptr;   // per candidate and row: 0 built, 1 flags, 2 pending
     double* partial = nullptr;   // per work item error sums
     SweepTune tune{128, 2048, 4};
     bool tuned = false;

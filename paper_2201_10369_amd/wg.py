@@ -86,6 +86,7 @@ _SIGS = {
     "wg_sweep_run": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_run_points": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_set_precision": (c_int, [c_void_p, c_int]),
+    "wg_sweep_set_exact": (c_int, [c_void_p, c_int]),
     "wg_sweep_matrices_f64": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "wg_sweep_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "wg_sweep_tuning": (c_int, [c_void_p, P_int, P_int, P_int]),
@@ -500,6 +501,10 @@ class Sweep:
         code = {"f32": 0, "mixed": 1}[mode]
         _check(lib().wg_sweep_set_precision(self._h, code))
         self.precision = mode
+
+    def set_exact(self, always):
+        """True: build every candidate with the exact integer construction."""
+        _check(lib().wg_sweep_set_exact(self._h, 1 if always else 0))
 
     def matrices_f64(self, cand):
         a, m, r = self.alpha, self.m, self.r

@@ -57,33 +57,81 @@ def _ordinal(v):
 SIZES = [(m, 3) for m in range(2, 9)] + [(m, 5) for m in range(2, 7)]
 
 
+def _construction_lists(alpha, rng, n_random):
+    """Point lists that take every route of the device construction: the
+    comparison set (exactly computed entries), Chebyshev nodes (near
+    negatives whose coefficients nearly cancel), integer lists summing to
+    zero, lists with exact +-a pairs and random lists."""
+    from paper_2201_10369_amd import pointsets as ps
+    nf = alpha - 1
+    lists = [list(ps.comparison_set(alpha, 1)), list(ps.chebyshev(alpha)), list(1.7 * np.asarray(ps.chebyshev(alpha)))]
+    ints = list(range(1, nf))
+    lists.append(ints + [-float(sum(ints))])                      # sum of the roots is zero
+    half = [float(v) for v in rng.uniform(0.2, 3.0, nf // 2)]
+    sym = [v for x in half for v in (x, -x)] + ([0.0] if nf % 2 else [])
+    lists.append(sym)
+    while len(lists) < 6 + n_random:
+        lists.append(list(rng.uniform(-3, 3, nf)))
+    return np.array(lists, np.float64)
+
+
+def _mismatches(mine, ref):
+    """Entries whose bits differ (+0 and -0 count as equal)."""
+    mine, ref = np.asarray(mine), np.asarray(ref)
+    return int((~((mine == ref) & ((mine != 0) | (ref == 0)))).sum())
+
+
 @pytest.mark.parametrize("m,r", SIZES)
 def test_device_construction_matches_exact(m, r):
-    """The float64 device construction rounds to the same float32 matrices as
-    the exact rational construction of the same float64 points, entry for
-    entry (entries that cancel exactly are zero)."""
+    """The device construction gives the float64 matrices of the exact
+    rational construction of the same float64 points, rounded once, and their
+    float32 roundings, entry for entry: families over the whole parameter
+    range and point lists that take every route (float64 with an error
+    bound, double words for Chebyshev nodes and the mixed-precision run,
+    exact integers in the forced mode, which builds every candidate that way
+    and must give the same matrices)."""
     alpha = m + r - 1
     S, d, g = _make(m, r, 2, 64, 64)
+    S.set_precision("mixed")                       # keeps the float64 matrices too
     rng = np.random.default_rng(m * 10 + r)
     c1 = np.concatenate([[2.0, 1.622, 0.5, 1.5], np.exp(rng.uniform(np.log(0.05), np.log(20), 28))])
     c2 = np.concatenate([[1.0, 2.5, 3.0, 0.7], np.exp(rng.uniform(np.log(0.05), np.log(20), 28))])
     counts = np.full(len(c1), 64, np.int32)
-    S.run(_dev(c1), _dev(c2), _dev(counts))
-    torch.cuda.synchronize()
-    mismatched = 0
-    for i in range(len(c1)):
-        AT, G, BT, flag = S.matrices(i)
-        try:
-            o = _oracle_mats(alpha, m, r, c1[i], c2[i])
-        except tc.SingularPoints:
-            assert flag == 1
-            continue
-        assert flag == 0
-        for mine, ref in zip((AT, G, BT), o):
-            assert np.array_equal(mine == 0, ref == 0), (i, c1[i], c2[i])
-            ulps = np.abs(_ordinal(mine) - _ordinal(ref))
-            mismatched += int((ulps > 0).sum())
-    assert mismatched == 0
+    pts = _construction_lists(alpha, rng, 10)
+    runs = {}
+    for exact in (False, True):
+        S.set_exact(exact)
+        for mode in ("family", "points"):
+            if mode == "family":
+                S.run(_dev(c1), _dev(c2), _dev(counts))
+                lists = [_family64(alpha, c1[i], c2[i]) for i in range(len(c1))]
+            else:
+                S.run_points(_dev(pts), _dev(counts[:len(pts)]))
+                lists = [[Fr(float(v)) for v in p] for p in pts]
+            torch.cuda.synchronize()
+            got = []
+            for i, p in enumerate(lists):
+                AT, G, BT, flag = S.matrices(i)
+                try:
+                    o32 = fp.mats_f32(p, m, r)
+                    o64 = fp.mats_f64(p, m, r)
+                except tc.SingularPoints:
+                    assert flag == 1
+                    got.append(None)
+                    continue
+                assert flag in (0, 2), (mode, i)
+                if exact:
+                    assert flag == 2, (mode, i)
+                assert sum(_mismatches(a_, b_) for a_, b_ in zip((AT, G, BT), o32)) == 0, (mode, exact, i)
+                assert sum(_mismatches(a_, b_) for a_, b_ in zip(S.matrices_f64(i), o64)) == 0, (mode, exact, i)
+                got.append((flag, AT, G, BT))
+            runs[(exact, mode)] = got
+    for mode in ("family", "points"):
+        for a_, b_ in zip(runs[(False, mode)], runs[(True, mode)]):
+            assert (a_ is None) == (b_ is None)
+            if a_ is not None:
+                assert all(np.array_equal(x, y) for x, y in zip(a_[1:], b_[1:]))
+    S.set_exact(False)
 
 
 @pytest.mark.parametrize("dims", [1, 2])
@@ -208,8 +256,8 @@ def test_point_lists_match_oracle(m, r, dims):
     """Comparison sets, Chebyshev nodes, base-point subsets and random lists
     (no zero, zero not first) on uneven pool prefixes equal the oracle's
     scores of the same float64 points: the same float32 matrices and error
-    sums to 1e-12, except where the device's zeroing of coefficients within
-    their own rounding noise applies (nearly symmetric lists)."""
+    sums to 1e-12 (Chebyshev nodes and the float64 1/c of subset lists make
+    coefficients that nearly cancel; they are exact here too)."""
     from paper_2201_10369_amd import pointsets as ps
     alpha = m + r - 1
     n_pool = 500
@@ -230,7 +278,6 @@ def test_point_lists_match_oracle(m, r, dims):
     out = S.run_points(_dev(pts), _dev(counts)).cpu().numpy()
     yref = sweep.pool_reference(d, g)
     outs = m if dims == 1 else m * m
-    snapped = 0
     for i, p in enumerate(pts):
         n = min(int(counts[i]), n_pool)
         e = sweep.candidate_error_points(p, m, r, dims, d, g, yref, n)
@@ -240,38 +287,9 @@ def test_point_lists_match_oracle(m, r, dims):
             assert math.isinf(out[i, 0])
             continue
         AT, G, BT, _ = S.matrices(i)
-        oAT, oG, oBT = fp.mats_f32([Fr(float(v)) for v in p], m, r)
-        assert np.array_equal(AT, oAT) and np.array_equal(G, oG), i
-        if np.array_equal(BT, oBT):
-            assert out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-12, abs=1e-300), i
-        else:
-            # lists whose float64 points only nearly cancel (the float64
-            # Chebyshev nodes are not exactly symmetric; c times the float64
-            # 1/c is not exactly 1) have B^T coefficients of order 1e-17 in
-            # the exact construction of those float64 points, where the real
-            # points cancel exactly; the device construction sets a
-            # coefficient whose float64 magnitude lies within the rounding
-            # noise of its own computation to zero: 4 (n+1) 2^-53 times the
-            # same coefficient of prod (x + |a_j|)
-            _assert_snapped(BT, oBT, list(p))
-            assert out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-3, abs=1e-300), i
-            snapped += 1
-    assert snapped < len(pts) // 2
-
-
-def _assert_snapped(BT, oBT, pts):
-    """Every entry where the device's B^T differs from the exact one is a
-    device zero in the snapping range of the float64 construction."""
-    a = len(pts) + 1
-    for i in range(a):
-        others = [abs(x) for j, x in enumerate(pts) if j != i] if i < a - 1 else [abs(x) for x in pts]
-        bnd = np.array([1.0])
-        for x in others:                                   # coefficients of prod (x + |a_j|)
-            bnd = np.concatenate([[0.0], bnd]) + x * np.concatenate([bnd, [0.0]])
-        tol = 4.0 * (len(others) + 1) * 2.0 ** -53
-        for l in range(len(bnd)):
-            if BT[i, l] != oBT[i, l]:
-                assert BT[i, l] == 0.0 and abs(float(oBT[i, l])) <= tol * bnd[l] * 1.0000001, (i, l)
+        o = fp.mats_f32([Fr(float(v)) for v in p], m, r)
+        assert all(np.array_equal(a_, b_) for a_, b_ in zip((AT, G, BT), o)), i
+        assert out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-12, abs=1e-300), i
 
 
 def test_point_lists_flag_invalid_points():
@@ -304,7 +322,7 @@ def test_two_param_search_result_is_scored_like_the_oracle(m, dims):
     assert res["evaluations"] == 24 * 24 + 4 + 2 * 64
     assert all(b <= a for a, b in zip(res["history"], res["history"][1:]))
     e = sweep.candidate_error(alpha, m, r, dims, res["c"], res["d"], d, g, sweep.pool_reference(d, g), n_pool)
-    assert res["mean_abs"] == pytest.approx(e["mean_abs"], rel=1e-3)
+    assert res["mean_abs"] == pytest.approx(e["mean_abs"], rel=1e-12)
     # the comparison set's score is another run of the same kernels
     from paper_2201_10369_amd import pointsets as ps
     pn = search.score_points(S, [ps.comparison_set(alpha, dims)], n_pool)[0]
@@ -327,7 +345,7 @@ def test_subset_search_orders_the_subsets():
     for row in rows[:2]:
         p = ps.subset_lists([0.5], tuple(row["subset"]), [row["c"]])[0]
         e = sweep.candidate_error_points(p, m, r, dims, d, g, yref, 400)
-        assert row["mean_abs"] == pytest.approx(e["mean_abs"], rel=1e-3)
+        assert row["mean_abs"] == pytest.approx(e["mean_abs"], rel=1e-12)
         assert row["mean_abs"] == float(np.min(row["curve"]))
 
 
@@ -363,18 +381,11 @@ def test_f43_proposed_points_beat_every_base_subset(dims):
 @pytest.mark.parametrize("dims", [1, 2])
 @pytest.mark.parametrize("m,r", [(2, 3), (4, 3), (6, 3), (8, 3), (4, 5)])
 def test_mixed_precision_sweep_matches_oracle(m, r, dims):
-    """Families and explicit lists in mixed precision: every error sum agrees
-    with the oracle's mixed evaluation on the oracle's own matrices (the exact
-    construction of the same float64 points, rounded to float64).  The
-    device builds its float64 matrices in float64 arithmetic, so entries may
-    differ from the exactly rounded ones by a few float64 units in the last
-    place (checked: zeros exact, relative difference at most 1e-14); U, V and
-    Y are rounded from those float64 values to float32, and a difference of
-    2^-50 relative moves a float32 rounding only when the value lies that
-    close to a rounding boundary (a chance of about 2^-26 per rounding, some
-    60,000 roundings per candidate).  Each such move changes one output by
-    one float32 ulp, about 1e-4 of a candidate's error sum here, so the sums
-    must agree to 1e-3 (room for several moves) and most agree to 1e-12."""
+    """Families and explicit lists in mixed precision: the device's float64
+    matrices are the oracle's (the exact construction of the same float64
+    points, rounded to float64) entry for entry, and every error sum equals
+    the oracle's mixed evaluation with those matrices to 1e-12 (the float64
+    sums differ only in order)."""
     from paper_2201_10369_amd import pointsets as ps
     alpha = m + r - 1
     n_pool = 400
@@ -388,7 +399,7 @@ def test_mixed_precision_sweep_matches_oracle(m, r, dims):
     f32 = S.run(_dev(c1), _dev(c2), _dev(counts)).clone()
     S.set_precision("mixed")
     yref = sweep.pool_reference(d, g)
-    exact_hits = scored = 0
+    scored = 0
     for mode in ("family", "points"):
         if mode == "family":
             out = S.run(_dev(c1), _dev(c2), _dev(counts)).cpu().numpy()
@@ -399,14 +410,12 @@ def test_mixed_precision_sweep_matches_oracle(m, r, dims):
             if out[i, 3]:
                 continue
             ex = fp.mats_f64(_family64(alpha, c1[i], c2[i]), m, r)
-            e = sweep.candidate_error_mixed(ex, m, r, dims, d, g, yref, n)
-            assert out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-3, abs=1e-300), (mode, i)
-            exact_hits += out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-12, abs=1e-300)
-            scored += 1
             for mine, ref in zip(S.matrices_f64(i), ex):
-                assert np.array_equal(mine == 0, ref == 0)
-                assert np.allclose(mine, ref, rtol=1e-14, atol=0)
-    assert exact_hits >= 0.75 * scored
+                assert _mismatches(mine, ref) == 0, (mode, i)
+            e = sweep.candidate_error_mixed(ex, m, r, dims, d, g, yref, n)
+            assert out[i, 0] == pytest.approx(e["abs_sum"], rel=1e-12, abs=1e-300), (mode, i)
+            scored += 1
+    assert scored >= 12
     # the mixed form scores lower than float32 on the same candidates
     fin = np.isfinite(out[:, 0]) & (out[:, 2] > 0)
     assert out[fin, 0].sum() < f32.cpu().numpy()[fin, 0].sum()
