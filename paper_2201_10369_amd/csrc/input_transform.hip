@@ -93,6 +93,23 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
     using T = typename Elem<DT>::T;
     using P2 = typename PairOf<CT>::type;
     using Terms = BtTerms<A, S>;
+    // B^T per lane (vector registers) for alpha <= 7, and for alpha = 8 with
+    // the zero structure: the combined launch otherwise runs out of scalar
+    // registers and reloads spilled coefficients in its first pass (36.0 ->
+    // 33.5 us for the fp16 F(6x6,3x3) launch; the opaque zero keeps the
+    // compiler from folding the copy back into scalar registers; larger
+    // alpha would cost occupancy)
+    constexpr bool kBtVgpr = sizeof(CT) == 4 && (A <= 7 || (A == 8 && S));
+    unsigned vz = 0;
+    if constexpr (kBtVgpr) asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+    CT btv[A][A];
+#pragma unroll
+    for (int k = 0; k < A; ++k)
+#pragma unroll
+        for (int l = 0; l < A; ++l) {
+            if constexpr (kBtVgpr) btv[k][l] = __uint_as_float(__float_as_uint((float)mt.BT[k][l]) | vz);
+            else btv[k][l] = mt.BT[k][l];
+        }
     const float* __restrict__ x = ia.x;
     const int twb = ia.twb, n_twb = ia.n_twb, pair_stride = ia.pair_stride;
     extern __shared__ __align__(16) float lds_raw[];
@@ -170,8 +187,8 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
                 CT t0 = CT(0), t1 = CT(0);
 #pragma unroll
                 for (int l = Terms::lo(k); l <= Terms::hi(k); ++l) {
-                    t0 = madd(mt.BT[k][l], d0[l], t0);
-                    t1 = madd(mt.BT[k][l], d1[l], t1);
+                    t0 = madd(btv[k][l], d0[l], t0);
+                    t1 = madd(btv[k][l], d1[l], t1);
                 }
                 *reinterpret_cast<P2*>(dst + 2 * k) = P2{t0, t1};
             }
@@ -234,8 +251,8 @@ __device__ __forceinline__ void input_block(const InputArgs& ia, const Mats<M, R
             CT q0 = CT(0), q1 = CT(0);
 #pragma unroll
             for (int l = Terms::lo(kk); l <= Terms::hi(kk); ++l) {
-                q0 = madd(mt.BT[kk][l], r0[l], q0);
-                q1 = madd(mt.BT[kk][l], r1[l], q1);
+                q0 = madd(btv[kk][l], r0[l], q0);
+                q1 = madd(btv[kk][l], r1[l], q1);
             }
             float a0 = (float)q0, a1 = (float)q1;
             if (DT != kF32) {
@@ -314,6 +331,9 @@ static int input_impl(const Plan& p, const float* x, const void* U, void* ws, hi
     const wg_layout& L = p.L;
     const Geo g = make_geo(L);
     const bool structured = zero_shape(p).bt;
+    // the offsets of the alpha planes of a V' row block are 32-bit element counts
+    if ((size_t)(A - 1) * L.P_pad * L.C_pad >= (1ull << 32))
+        return fail(WG_EUNSUPPORTED, "input transform: V' planes too large for 32-bit offsets");
     const RowPerm rp = bt_row_perm(p, structured, (size_t)L.P_pad * L.C_pad);
     // B^T rows in RowPerm order
     Mats<M, R, CT> mt = pack_mats<M, R, CT>(p);

@@ -112,7 +112,7 @@ inline ZeroShape zero_shape(const Plan& p) {
 struct RowPerm {
     int row[kMaxAlpha];
     int dB[kMaxAlpha];
-    unsigned long long plane_off[kMaxAlpha];
+    unsigned plane_off[kMaxAlpha];           // elements; the launcher checks the range
 };
 
 inline RowPerm bt_row_perm(const Plan& p, bool structured, size_t plane_elems) {
@@ -130,7 +130,7 @@ inline RowPerm bt_row_perm(const Plan& p, bool structured, size_t plane_elems) {
     }
     for (int k = 0; k < A; ++k) {
         rp.dB[k] = p.dB[rp.row[k]];
-        rp.plane_off[k] = (unsigned long long)rp.row[k] * plane_elems;
+        rp.plane_off[k] = (unsigned)(rp.row[k] * plane_elems);
     }
     return rp;
 }
