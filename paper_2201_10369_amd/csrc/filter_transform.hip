@@ -85,7 +85,12 @@ __global__ __launch_bounds__(kScaleThreads) void layer_scale_kernel(const float*
                                                                     RowExps ex, int32_t* __restrict__ s_tab,
                                                                     int32_t* __restrict__ t_tab) {
     __shared__ float red[2][kScaleThreads / 64];
-    const int c = (int)blockIdx.x, tid = (int)threadIdx.x;
+    // consecutive channels on one XCD: their filter taps share cache lines
+    // (a channel's taps are 4 * RR bytes at a stride of C * 4 * RR), which
+    // one L2 then fetches once
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int c = nb % kXcdCount == 0 ? (b % kXcdCount) * (nb / kXcdCount) + b / kXcdCount : b;
+    const int tid = (int)threadIdx.x;
     int tc = 0;
     if (c < C) {
         // the filter taps first (their loads overlap the walk over x)
