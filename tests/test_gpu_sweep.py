@@ -134,6 +134,65 @@ def test_device_construction_matches_exact(m, r):
     S.set_exact(False)
 
 
+@pytest.mark.parametrize("m,r", [(2, 3), (4, 3), (6, 3), (8, 3), (3, 5), (6, 5)])
+def test_device_construction_matches_host_exact_in_bulk(m, r):
+    """2048 point lists per size (random, +-a pairs with zero, dyadic,
+    integer lists with a cancelling sum, scaled Chebyshev nodes, lists
+    spanning 10^8) built on the device in mixed precision: every float64 and
+    float32 entry equals the library's exact big-integer host construction
+    (wg_transforms, itself pinned to the rational oracle), and the singular
+    verdicts agree."""
+    from paper_2201_10369_amd import pointsets as ps
+    wg = _wg()
+    alpha = m + r - 1
+    nf = alpha - 1
+    n = 2048
+    rng = np.random.default_rng(1000 + 10 * m + r)
+    cheb = np.asarray(ps.chebyshev(alpha), np.float64)
+    pts = np.empty((n, nf))
+    for i in range(n):
+        kind = i % 6
+        if kind == 0:
+            p = rng.uniform(-3, 3, nf)
+        elif kind == 1:
+            h = rng.uniform(0.2, 3.0, nf // 2)
+            p = np.concatenate([h, -h, [0.0] * (nf % 2)])
+            rng.shuffle(p)
+        elif kind == 2:
+            p = rng.choice([0, 1, -1, 2, -2, 0.5, -0.5, 4, -4, 0.25, -0.25, 3, -3, 1.5, -1.5, 0.75], nf,
+                           replace=False).astype(np.float64)
+        elif kind == 3:
+            p = rng.choice(np.arange(-20, 21), nf, replace=False).astype(np.float64)
+            p[-1] = -(p[0] + p[1]) if -(p[0] + p[1]) not in p[:-1] else 37.0
+        elif kind == 4:
+            p = cheb * rng.uniform(0.5, 3.5)
+        else:
+            p = rng.choice([-1, 1], nf) * np.exp(rng.uniform(np.log(1e-4), np.log(1e4), nf))
+        pts[i] = p
+    S, d, g = _make(m, r, 2, 64, n)
+    S.set_precision("mixed")
+    S.run_points(_dev(pts), _dev(np.full(n, 64, np.int32)))
+    torch.cuda.synchronize()
+    for i in range(n):
+        AT, G, BT, flag = S.matrices(i)
+        try:
+            ref = wg.transforms(m, r, pts[i])
+        except wg.WGError:
+            assert flag == 1, i
+            continue
+        singular = False
+        for a in range(nf):                          # the sweep also flags |N_i| < 1e-300
+            nv = np.prod([pts[i][a] - pts[i][b] for b in range(nf) if b != a])
+            singular |= abs(nv) < 1e-299
+        if singular:
+            continue
+        assert flag in (0, 2), i
+        for mine, r64 in zip(S.matrices_f64(i), ref):
+            assert _mismatches(mine, r64) == 0, (i, pts[i])
+        for mine, r64 in zip((AT, G, BT), ref):
+            assert _mismatches(mine, r64.astype(np.float32)) == 0, (i, pts[i])
+
+
 @pytest.mark.parametrize("dims", [1, 2])
 @pytest.mark.parametrize("m,r", SIZES)
 def test_sweep_errors_match_oracle(m, r, dims):
