@@ -459,7 +459,10 @@ typedef struct wg_mlp wg_mlp;
 int wg_mlp_param_count(void);
 
 /* Training context for batches of at most max_batch samples; owns a device
- * scratch of about max_batch / 16 * 135 KB.  Errors: WG_EINVAL, WG_ENOMEM. */
+ * scratch of about 2.3 KB per sample of max_batch (the hidden activations
+ * and dL/dZ of a step and per-16-sample partial sums of the small
+ * gradients).  Calls on one context share that scratch and must not
+ * overlap.  Errors: WG_EINVAL, WG_ENOMEM. */
 int wg_mlp_create(wg_mlp** out, int max_batch);
 int wg_mlp_destroy(wg_mlp* mlp);            /* NULL is accepted */
 
@@ -478,7 +481,12 @@ int wg_mlp_gradient(wg_mlp* mlp, const float* params, const double* c1, const do
  * last n % batch entries of each pass are skipped), step counter starting at
  * step0 >= 1.  adam_state: device float32[2 * 33793] (first then second
  * moments; zero before the first step).  losses: device float32
- * [epochs * (n / batch)], the loss of every step before its update. */
+ * [epochs * (n / batch)], the loss of every step before its update.  The
+ * context also keeps 20 bytes per sample of the n (the input features and
+ * targets of a pass, in minibatch order), allocated on the first call that
+ * needs more and held until wg_mlp_destroy (WG_ENOMEM if that allocation
+ * fails).  A perm entry outside [0, n) gives NaN features for its sample
+ * (so NaN losses), not an out-of-range read. */
 int wg_mlp_train(wg_mlp* mlp, float* params, float* adam_state, int step0, float lr,
                  const double* c1, const double* c2, const int* m, const int* r,
                  const float* target, int n, const int* perm, int epochs, int batch,

@@ -5,16 +5,23 @@
 // the network interpolates that curve across parameters and tile sizes so
 // that only its best proposals need an exact sweep evaluation.
 //
-// Kernels (float32, deterministic reduction orders):
-//   fwd_bwd : a block takes 16 samples, runs the forward pass with all
-//             activations in LDS and, for training, the backward pass, and
-//             writes its partial gradient (one full parameter vector); the
-//             128 x 128 products of the hidden layers and their gradients
-//             run on the float32 matrix cores
-//   reduce  : per parameter, four thread groups add interleaved block
-//             partials, the group sums are added in order, then Adam (or
-//             the gradient is written)
-//   predict : forward pass only
+// Kernels (float32, fixed reduction orders):
+//   encode  : once per pass over the data, the input features and targets
+//             of the samples in minibatch order, so that a training step
+//             reads its samples with one contiguous load
+//   fwd_bwd : a block takes 16 samples: forward pass with all activations
+//             in LDS, the output layer and, for training, the backward pass
+//             down to dL/dZ1 (the 128 x 128 products on the float32 matrix
+//             cores).  It writes H1, H2, dL/dZ2 and dL/dZ3 of its samples
+//             (the operands of the two 128 x 128 weight gradients) and its
+//             partial sums of the small gradients (W1, b1, b2, b3, W4, b4)
+//             and of the loss
+//   update  : the weight gradients dW = dZ^T H of the two 128 x 128 layers
+//             on the matrix cores, one 16 x 16 parameter tile per block over
+//             the whole batch; the small gradients summed over the fwd_bwd
+//             blocks in a fixed order; then Adam (or the plain gradient) on
+//             every parameter
+//   predict : the forward part of fwd_bwd
 //   topk    : the k smallest values of a vector (ties -> smaller index)
 #include <hip/hip_runtime.h>
 
@@ -22,44 +29,64 @@
 #include <new>
 #include <string>
 
+#include "wg_device.h"
 #include "wg_internal.h"
 
 namespace wg {
 
 constexpr int kIn = 4, kH = 128;
-constexpr int kS = 16;            // samples per block, in kHalves row tiles of kHalf
-constexpr int kHalf = 16;         // samples per matrix-core row tile
-constexpr int kHalves = kS / kHalf;
+constexpr int kS = 16;            // samples per fwd_bwd block: one matrix-core row tile
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
-// each row tile of the block (8 waves) runs one 16-column tile of a
-// 128-wide layer per wave for its kHalf samples (a block of 32 samples in
-// two row tiles of 1024 threads measured slower: 43.5 against 35.8 us per
-// gradient step, half the compute units idle)
-static_assert(kH / 16 * kHalves == kWaves, "tile per wave");
-constexpr size_t kMlpLds = sizeof(float) * (kS * kIn + 6 * kS * kH);
+// wave w takes the 16-column tile w of each 128-wide layer (a block of 32
+// samples in two row tiles of 1024 threads measured slower: with 4096
+// samples only half the compute units get a block)
+static_assert(kH / 16 == kWaves, "one column tile per wave");
+// LDS row pitch of the activations: rows 4 floats apart in the bank map, so
+// that the 16 rows a matrix-core operand load reads do not collide
+constexpr int kP = kH + 4;
+constexpr size_t kMlpLds = sizeof(float) * (kS * kIn + 6 * kS * kP);
 // parameter layout (row-major W[out][in]):
 constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
               ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kH, kParams = ob4 + 1;
 static_assert(kParams == 33793, "parameter count");
-// partial gradients of the blocks are kPartStride floats apart (16-byte aligned)
-constexpr int kPartStride = (kParams + 3) / 4 * 4;
+// Per fwd_bwd block, the partial sums of the small gradients and of the
+// loss, kSmallStride floats apart (16-byte aligned):
+constexpr int sW1 = 0, sb1 = sW1 + kH * kIn, sb2 = sb1 + kH, sb3 = sb2 + kH, sW4 = sb3 + kH, sb4 = sW4 + kH,
+              sLoss = sb4 + 1, kSmall = sLoss + 1;
+constexpr int kSmallStride = (kSmall + 3) / 4 * 4;
+__device__ __forceinline__ int small_param(int k) {
+    return k < sb1 ? oW1 + k
+         : k < sb2 ? ob1 + (k - sb1)
+         : k < sb3 ? ob2 + (k - sb2)
+         : k < sW4 ? ob3 + (k - sb3)
+         : k < sb4 ? oW4 + (k - sW4)
+                   : ob4;
+}
+// Weight-gradient tiles of W2 and W3: 16 x 16 parameters each, a block
+// per tile over the whole batch.
+constexpr int kTile = 16, kTilesPerMat = (kH / kTile) * (kH / kTile), kTiles = 2 * kTilesPerMat;
+constexpr int kUpdThreads = 1024;
+constexpr int kUpdWaves = kUpdThreads / 64;
+constexpr int kUpdDepth = 8;       // fwd_bwd blocks whose operands a wave keeps in flight
+constexpr int kSmallPerBlock = 64;
+constexpr int kSmallBlocks = (kSmall + kSmallPerBlock - 1) / kSmallPerBlock;
+constexpr int kRedGroups = kUpdThreads / (kSmallPerBlock / 4);
+static_assert(kTilesPerMat % kXcdCount == 0 && kTilesPerMat / kXcdCount == 8, "tile regions of 2 x 4 tiles");
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad_f(float z) {
+// GELU and its derivative from one evaluation of the normal CDF
+__device__ __forceinline__ void gelu_and_grad(float z, float& h, float& g) {
     const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
-    const float pdf = expf(-0.5f * z * z) * 0.39894228040143268f;
-    return cdf + z * pdf;
+    h = z * cdf;
+    g = cdf + z * (expf(-0.5f * z * z) * 0.39894228040143268f);
 }
 
 // Input encoding: (ln c1 / ln 20, ln c2 / ln 20, (m - 5) / 3, r - 4).
-__device__ __forceinline__ void encode(const double* c1, const double* c2, const int* m, const int* r, int q,
-                                       float* f) {
+__device__ __forceinline__ float4 encode(const double* c1, const double* c2, const int* m, const int* r, int q) {
     const double ln20 = 2.995732273553991;
-    f[0] = (float)(log(c1[q]) / ln20);
-    f[1] = c2 != nullptr ? (float)(log(c2[q]) / ln20) : 0.0f;
-    f[2] = (float)((m[q] - 5) / 3.0);
-    f[3] = (float)(r[q] - 4);
+    return make_float4((float)(log(c1[q]) / ln20), c2 != nullptr ? (float)(log(c2[q]) / ln20) : 0.0f,
+                       (float)((m[q] - 5) / 3.0), (float)(r[q] - 4));
 }
 
 struct MlpData {
@@ -67,10 +94,21 @@ struct MlpData {
     const double* c2;
     const int* m;
     const int* r;
-    const float* target;   // training only
-    const int* idx;        // sample indices of this batch (NULL: 0..n-1)
+    const float* target;   // training with inline features only
+    const float4* xe;      // encoded features of this launch's samples (NULL: encode from c1 .. r)
+    const float* te;       // and their targets
     int n;                 // samples in this launch
     float inv_batch2;      // 2 / batch
+};
+
+// The per-sample operands of the two 128 x 128 weight gradients, written by
+// fwd_bwd: per array, per fwd_bwd block b, a [kH][kS] slab (unit-major, the
+// block's 16 samples contiguous) at offset b * kH * kS.
+struct Acts {
+    float* h1;   // H1 (input of layer 2)
+    float* h2;   // H2 (input of layer 3)
+    float* d2;   // dL/dZ2
+    float* d3;   // dL/dZ3
 };
 
 // The 128-wide products of a block's samples run on the float32
@@ -86,8 +124,22 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 acc) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
 }
 
-// The weight operands a lane needs for its tile, loaded at the start of the
-// kernel so that their latency overlaps the layers before them:
+// A float4 to a slab read by the next launch: a streaming store, so that the
+// end of the launch has little left to write back from L2 (measured: the
+// fwd_bwd launch about 4 us shorter than with ordinary stores).
+__device__ __forceinline__ void slab_store(float* p, float4 v) {
+    const f32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
+}
+
+// Block barrier for LDS traffic: waits for this wave's LDS operations only,
+// not for its global loads and stores, so that the weight operands stay in
+// flight across the forward layers (the waves of a fwd_bwd block exchange
+// data through LDS only; __syncthreads would wait for every outstanding
+// global access).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// The weight operands a lane needs for its tile, loaded once per block:
 //   rows: W[j0 + l % 16][32 q .. 32 q + 31] (Z = A W^T), q = l / 16
 //   cols: W[32 q .. 32 q + 31][i0 + l % 16] (dH = D W)
 struct WRows {
@@ -114,184 +166,195 @@ __device__ __forceinline__ WCols load_cols(const float* __restrict__ W, int i0) 
 }
 
 // Z[s][j] = sum_k A[s][k] W[j][k] for the lane's 16-column tile (A in LDS,
-// the W operand preloaded).  Returns the lane's four entries (rows
-// 4 (l / 16) + r of column j0 + l % 16).
-__device__ __forceinline__ f32x4 mm_rows_w(const float (*A)[kH], const WRows& w) {
+// the W operand preloaded), in two accumulators (the instructions alternate
+// between them in groups of four) added at the end.  Returns the lane's four
+// entries (rows 4 (l / 16) + r of column j0 + l % 16).
+__device__ __forceinline__ f32x4 mm_rows_w(const float (*A)[kP], const WRows& w) {
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
     const float4* ar = reinterpret_cast<const float4*>(&A[c][32 * q]);
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const float4 av = ar[u];
-        acc = mfma16(av.x, w.v[u].x, acc);
-        acc = mfma16(av.y, w.v[u].y, acc);
-        acc = mfma16(av.z, w.v[u].z, acc);
-        acc = mfma16(av.w, w.v[u].w, acc);
+        acc[u & 1] = mfma16(av.x, w.v[u].x, acc[u & 1]);
+        acc[u & 1] = mfma16(av.y, w.v[u].y, acc[u & 1]);
+        acc[u & 1] = mfma16(av.z, w.v[u].z, acc[u & 1]);
+        acc[u & 1] = mfma16(av.w, w.v[u].w, acc[u & 1]);
     }
-    return acc;
+    return acc[0] + acc[1];
 }
 
 // dH[s][i] = sum_j D[s][j] W[j][i] for the lane's 16-column tile (the
-// columns of W preloaded).
-__device__ __forceinline__ f32x4 mm_rows_wt(const float (*D)[kH], const WCols& w) {
+// columns of W preloaded), in two accumulators as above.
+__device__ __forceinline__ f32x4 mm_rows_wt(const float (*D)[kP], const WCols& w) {
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
     const float4* dr = reinterpret_cast<const float4*>(&D[c][32 * q]);
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const float4 dv = dr[u];
-        acc = mfma16(dv.x, w.v[4 * u + 0], acc);
-        acc = mfma16(dv.y, w.v[4 * u + 1], acc);
-        acc = mfma16(dv.z, w.v[4 * u + 2], acc);
-        acc = mfma16(dv.w, w.v[4 * u + 3], acc);
+        acc[u & 1] = mfma16(dv.x, w.v[4 * u + 0], acc[u & 1]);
+        acc[u & 1] = mfma16(dv.y, w.v[4 * u + 1], acc[u & 1]);
+        acc[u & 1] = mfma16(dv.z, w.v[4 * u + 2], acc[u & 1]);
+        acc[u & 1] = mfma16(dv.w, w.v[4 * u + 3], acc[u & 1]);
     }
-    return acc;
+    return acc[0] + acc[1];
 }
 
-// dW[j][i] = sum_s D[s][j] H[s][i] over the block's kS samples for the
-// tile j0 .. j0+15 x i0 .. i0+15 (kS / 4 instructions, k-slot q of
-// instruction t holds sample 4 t + q), written to the partial gradient gW
-// (row-major [j][i], pitch kH).
-__device__ __forceinline__ void mm_dw(const float (*D)[kH], const float (*H)[kH], int j0, int i0,
-                                      float* __restrict__ gW) {
-    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int t = 0; t < kS / 4; ++t) acc = mfma16(D[4 * t + q][j0 + c], H[4 * t + q][i0 + c], acc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) gW[(size_t)(j0 + 4 * q + r) * kH + i0 + c] = acc[r];
-}
-
-// One hidden layer forward: Z = A W^T + b on the matrix cores (in each half
-// of the block, for its kHalf samples, wave w of the half takes the column
-// tile w; bj: the bias of the lane's column), then H = gelu(Z) and
-// G = gelu'(Z) to LDS.
-__device__ __forceinline__ void dense_layer(const float (*A)[kH], const WRows& W, float bj, float (*H)[kH],
-                                            float (*G)[kH]) {
+// One hidden layer forward: Z = A W^T + b on the matrix cores (wave w takes
+// the column tile w for all kS samples; bj: the bias of the lane's column),
+// then H = gelu(Z) and, for training, G = gelu'(Z) to LDS and H to the
+// block's slab hg (when not NULL).
+__device__ __forceinline__ void dense_layer(const float (*A)[kP], const WRows& W, float bj, float (*H)[kP],
+                                            float (*G)[kP], int train, float* __restrict__ hg) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
-    const int half = wave / (kH / 16), r0 = half * kHalf;     // this half's sample rows
-    A += r0;
-    H += r0;
-    G += r0;
-    {
-        const int j0 = (wave % (kH / 16)) * 16;
-        const f32x4 z = mm_rows_w(A, W);
+    const int j0 = wave * 16;
+    const f32x4 z = mm_rows_w(A, W);
+    float h[4];
+    if (train) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float zz = z[r] + bj;
-            H[4 * q + r][j0 + c] = gelu_f(zz);
-            G[4 * q + r][j0 + c] = gelu_grad_f(zz);
+            float g;
+            gelu_and_grad(z[r] + bj, h[r], g);
+            H[4 * q + r][j0 + c] = h[r];
+            G[4 * q + r][j0 + c] = g;
         }
+        if (hg) slab_store(hg + (size_t)(j0 + c) * kS + 4 * q, make_float4(h[0], h[1], h[2], h[3]));
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) H[4 * q + r][j0 + c] = gelu_f(z[r] + bj);
     }
 }
 
 // One hidden layer backward: from D = dL/dZ of the layer's output (LDS),
-// writes dW = D^T Hin and db = sum_s D to the partial gradient, and replaces
-// Gin (gelu'(Zin)) by dL/dZin = (D W) * gelu'(Zin).
-__device__ __forceinline__ void backprop_hidden(const float (*D)[kH], const float (*Hin)[kH], float (*Gin)[kH],
-                                                const WCols& W, float* __restrict__ gW, float* __restrict__ gb) {
+// writes db = sum_s D to the block's small partials and replaces Gin
+// (gelu'(Zin)) by dL/dZin = (D W) * gelu'(Zin), also to the block's slab dg
+// (when not NULL).
+__device__ __forceinline__ void backprop_hidden(const float (*D)[kP], float (*Gin)[kP], const WCols& W,
+                                                float* __restrict__ gb, float* __restrict__ dg) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
-    const int half = wave / (kH / 16), w8 = wave % (kH / 16);
-    // dW over all kS samples: wave w of row tile h takes the row tile w of
-    // dW and its share of the column tiles
-    constexpr int kColTiles = kH / 16 / kHalves;
-#pragma unroll
-    for (int it = 0; it < kColTiles; ++it) mm_dw(D, Hin, w8 * 16, (half * kColTiles + it) * 16, gW);
     if (tid < kH) {
         float a = 0.0f;
         for (int s = 0; s < kS; ++s) a += D[s][tid];
         gb[tid] = a;
     }
-    // dL/dZin = (D W) * gelu'(Zin) for this half's samples, in place over
-    // Gin (read only by this lane)
-    {
-        const int i0 = w8 * 16, r0 = half * kHalf;
-        const f32x4 dh = mm_rows_wt(D + r0, W);
+    const int i0 = wave * 16;
+    const f32x4 dh = mm_rows_wt(D, W);
+    float v[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Gin[r0 + 4 * q + r][i0 + c] *= dh[r];
+    for (int r = 0; r < 4; ++r) {
+        v[r] = Gin[4 * q + r][i0 + c] * dh[r];
+        Gin[4 * q + r][i0 + c] = v[r];
     }
-    __syncthreads();
+    if (dg) slab_store(dg + (size_t)(i0 + c) * kS + 4 * q, make_float4(v[0], v[1], v[2], v[3]));
+    lds_barrier();
 }
 
 // A block takes kS samples: forward pass with all activations in LDS (H_l
-// and gelu'(Z_l) per layer) and, for training, the backward pass, writing
-// its partial gradient (one full parameter vector) and its loss sum.
+// and, for training, gelu'(Z_l) per layer) and, for training, the backward
+// pass (see the file comment for what it writes).
 __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __restrict__ P, MlpData d, int train,
-                                                               float* __restrict__ part,
-                                                               float* __restrict__ part_loss,
+                                                               Acts act, float* __restrict__ small,
                                                                float* __restrict__ pred) {
     extern __shared__ __attribute__((aligned(16))) float mlp_lds[];
     float (*X)[kIn] = reinterpret_cast<float (*)[kIn]>(mlp_lds);
-    float (*H1)[kH] = reinterpret_cast<float (*)[kH]>(mlp_lds + kS * kIn);
-    float (*H2)[kH] = H1 + kS;
-    float (*H3)[kH] = H2 + kS;
-    float (*G1)[kH] = H3 + kS;
-    float (*G2)[kH] = G1 + kS;
-    float (*G3)[kH] = G2 + kS;
+    float (*H1)[kP] = reinterpret_cast<float (*)[kP]>(mlp_lds + kS * kIn);
+    float (*H2)[kP] = H1 + kS;
+    float (*H3)[kP] = H2 + kS;
+    float (*G1)[kP] = H3 + kS;
+    float (*G2)[kP] = G1 + kS;
+    float (*G3)[kP] = G2 + kS;
     __shared__ float OUT[kS], DOUT[kS], TGT[kS], W4s[kH];
-    const int tid = threadIdx.x;
-    const int s0 = blockIdx.x * kS;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int blk = blockIdx.x, s0 = blk * kS;
     const int ns = min(kS, d.n - s0);
-    // every weight operand of this wave's tiles and every small parameter,
-    // loaded up front so that their latency overlaps the layers before them
-    const int tile0 = ((tid >> 6) % (kH / 16)) * 16, lc = tid & 15;
-    const WRows w2r = load_rows(P + oW2, tile0), w3r = load_rows(P + oW3, tile0);
-    WCols w3c, w2c;
-    if (train) {
-        w3c = load_cols(P + oW3, tile0);
-        w2c = load_cols(P + oW2, tile0);
-    }
-    const int j1 = tid & (kH - 1);
+    // layer 1: thread (unit j1, samples 4 p1 .. 4 p1 + 3)
+    const int j1 = tid & (kH - 1), p1 = tid / kH;
     const float4 w1v = *reinterpret_cast<const float4*>(P + oW1 + j1 * kIn);
-    const float b1v = P[ob1 + j1], b2v = P[ob2 + tile0 + lc], b3v = P[ob3 + tile0 + lc], b4v = P[ob4];
+    const float b1v = P[ob1 + j1];
+    // the small parameters with the samples, before the first barrier
+    const int t0 = wave * 16, lc = tid & 15;
+    const float b2v = P[ob2 + t0 + lc], b3v = P[ob3 + t0 + lc], b4v = P[ob4];
     if (tid < kH) W4s[tid] = P[oW4 + tid];
+    // the samples first: their loads must not queue behind the weights'
     if (tid < kS) {
-        float f[kIn] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float4 f = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float tg = 0.0f;
         if (tid < ns) {
-            const int q = d.idx ? d.idx[s0 + tid] : s0 + tid;
-            if (train) tg = d.target[q];
-            encode(d.c1, d.c2, d.m, d.r, q, f);
+            if (d.xe) {
+                f = d.xe[s0 + tid];
+                if (train) tg = d.te[s0 + tid];
+            } else {
+                f = encode(d.c1, d.c2, d.m, d.r, s0 + tid);
+                if (train) tg = d.target[s0 + tid];
+            }
         }
         TGT[tid] = tg;
-#pragma unroll
-        for (int k = 0; k < kIn; ++k) X[tid][k] = f[k];
+        X[tid][0] = f.x;
+        X[tid][1] = f.y;
+        X[tid][2] = f.z;
+        X[tid][3] = f.w;
     }
-    __syncthreads();
+    lds_barrier();
+    // the weight operands of this wave's tiles, each issued one layer
+    // before its use (loads complete in issue order, and a wave keeps at most
+    // 63 in flight)
+    const WRows w2r = load_rows(P + oW2, t0);
+    const size_t slab = (size_t)blk * kH * kS;
     // layer 1 (4 -> 128) on the vector units
     {
-        const int j = j1, part0 = tid / kH;
-        const float w0 = w1v.x, w1 = w1v.y, w2 = w1v.z, w3 = w1v.w, bj = b1v;
-        for (int s = part0; s < kS; s += kThreads / kH) {
-            float a = fmaf(w0, X[s][0], 0.0f);
-            a = fmaf(w1, X[s][1], a);
-            a = fmaf(w2, X[s][2], a);
-            a = fmaf(w3, X[s][3], a);
-            a += bj;
-            H1[s][j] = gelu_f(a);
-            G1[s][j] = gelu_grad_f(a);
+        float h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int s = 4 * p1 + k;
+            float a = fmaf(w1v.x, X[s][0], 0.0f);
+            a = fmaf(w1v.y, X[s][1], a);
+            a = fmaf(w1v.z, X[s][2], a);
+            a = fmaf(w1v.w, X[s][3], a);
+            a += b1v;
+            if (train) {
+                float g;
+                gelu_and_grad(a, h[k], g);
+                G1[s][j1] = g;
+            } else {
+                h[k] = gelu_f(a);
+            }
+            H1[s][j1] = h[k];
         }
+        if (train)
+            slab_store(act.h1 + slab + (size_t)j1 * kS + 4 * p1, make_float4(h[0], h[1], h[2], h[3]));
     }
-    __syncthreads();
-    dense_layer(H1, w2r, b2v, H2, G2);
-    __syncthreads();
-    dense_layer(H2, w3r, b3v, H3, G3);
-    __syncthreads();
-    if (tid < kS) {
+    lds_barrier();
+    const WRows w3r = load_rows(P + oW3, t0);
+    dense_layer(H1, w2r, b2v, H2, G2, train, train ? act.h2 + slab : nullptr);
+    lds_barrier();
+    WCols w3c, w2c;
+    if (train) w3c = load_cols(P + oW3, t0);
+    dense_layer(H2, w3r, b3v, H3, G3, train, nullptr);
+    lds_barrier();
+    if (train) w2c = load_cols(P + oW2, t0);
+    // output layer: 32 threads per sample, a butterfly sum over them
+    {
+        const int s = tid >> 5, l = tid & 31;
         float a = 0.0f;
-        for (int i = 0; i < kH; ++i) a = fmaf(W4s[i], H3[tid][i], a);
-        a += b4v;
-        OUT[tid] = a;
-        if (tid < ns) {
-            if (pred) pred[s0 + tid] = a;
-            if (train) DOUT[tid] = d.inv_batch2 * (a - TGT[tid]);
-        } else {
-            DOUT[tid] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kH / 32; ++k) a = fmaf(W4s[l + 32 * k], H3[s][l + 32 * k], a);
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) a += __shfl_xor(a, off, 32);
+        if (l == 0) {
+            a += b4v;
+            OUT[s] = a;
+            if (s < ns) {
+                if (pred) pred[s0 + s] = a;
+                DOUT[s] = train ? d.inv_batch2 * (a - TGT[s]) : 0.0f;
+            } else {
+                DOUT[s] = 0.0f;
+            }
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (!train) return;
-    float* g = part + (size_t)blockIdx.x * kPartStride;
+    float* sp = small + (size_t)blk * kSmallStride;
     if (tid == 0) {
         float l = 0.0f, db = 0.0f;
         for (int s = 0; s < ns; ++s) {
@@ -299,23 +362,31 @@ __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __re
             l = fmaf(e, e, l);
             db += DOUT[s];
         }
-        part_loss[blockIdx.x] = l;
-        g[ob4] = db;
+        sp[sLoss] = l;
+        sp[sb4] = db;
+        for (int k = kSmall; k < kSmallStride; ++k) sp[k] = 0.0f;
     }
-    // output layer: dW4; then dL/dZ3 = DOUT W4 gelu'(Z3) in place over G3
+    // output layer: dW4; dL/dZ3 = DOUT W4 gelu'(Z3) in place over G3 and to
+    // the block's slab
     if (tid < kH) {
         float a = 0.0f;
         for (int s = 0; s < kS; ++s) a = fmaf(DOUT[s], H3[s][tid], a);
-        g[oW4 + tid] = a;
+        sp[sW4 + tid] = a;
     }
-    for (int q = tid; q < kS * kH; q += kThreads) {
-        const int s = q / kH, i = q % kH;
-        G3[s][i] = DOUT[s] * W4s[i] * G3[s][i];
+    {
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int s = 4 * p1 + k;
+            v[k] = DOUT[s] * W4s[j1] * G3[s][j1];
+            G3[s][j1] = v[k];
+        }
+        slab_store(act.d3 + slab + (size_t)j1 * kS + 4 * p1, make_float4(v[0], v[1], v[2], v[3]));
     }
-    __syncthreads();
-    // hidden layers 3 and 2: dW = dZ^T H_in, db = sum dZ, dZ_in = (dZ W) gelu'(Z_in)
-    backprop_hidden(G3, H2, G2, w3c, g + oW3, g + ob3);
-    backprop_hidden(G2, H1, G1, w2c, g + oW2, g + ob2);
+    lds_barrier();
+    // hidden layers 3 and 2: db = sum dZ, dZ_in = (dZ W) gelu'(Z_in)
+    backprop_hidden(G3, G2, w3c, sp + sb3, act.d2 + slab);
+    backprop_hidden(G2, G1, w2c, sp + sb2, nullptr);
     // first layer: dW1[j][k] = sum_s dZ1[s][j] X[s][k], db1
     if (tid < kH) {
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, b = 0.0f;
@@ -327,89 +398,170 @@ __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __re
             a3 = fmaf(dz, X[s][3], a3);
             b += dz;
         }
-        g[oW1 + tid * kIn + 0] = a0;
-        g[oW1 + tid * kIn + 1] = a1;
-        g[oW1 + tid * kIn + 2] = a2;
-        g[oW1 + tid * kIn + 3] = a3;
-        g[ob1 + tid] = b;
+        sp[sW1 + tid * kIn + 0] = a0;
+        sp[sW1 + tid * kIn + 1] = a1;
+        sp[sW1 + tid * kIn + 2] = a2;
+        sp[sW1 + tid * kIn + 3] = a3;
+        sp[sb1 + tid] = b;
     }
 }
 
-// Sum of the block partials -> Adam update or plain gradient.  A block takes
-// kRedParams parameters; its thread (group g, quad u) adds parameters
-// 4u .. 4u+3 of every kRedGroups-th partial (g, g + kRedGroups, ...) with
-// 16-byte loads, eight in flight, and the group sums are added in group
-// order, so the result is fixed for a given number of partials.
-constexpr int kRedParams = 64;
-constexpr int kRedGroups = 256 / (kRedParams / 4);
+// Features and targets of `count` samples in the order `order` (entries
+// outside [0, n) give NaN features and targets rather than a load).
+__global__ __launch_bounds__(256) void mlp_encode_kernel(const double* __restrict__ c1, const double* __restrict__ c2,
+                                                         const int* __restrict__ m, const int* __restrict__ r,
+                                                         const float* __restrict__ target,
+                                                         const int* __restrict__ order, int n, int count,
+                                                         float4* __restrict__ xe, float* __restrict__ te) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const int q = order[k];
+    if (q < 0 || q >= n) {
+        xe[k] = make_float4(NAN, NAN, NAN, NAN);
+        te[k] = NAN;
+        return;
+    }
+    xe[k] = encode(c1, c2, m, r, q);
+    te[k] = target[q];
+}
 
-__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ part, int nblk,
-                                                         float* __restrict__ P, float* __restrict__ adam,
-                                                         float* __restrict__ grad_out, float lr, float b1, float b2,
-                                                         float eps, float bc1, float bc2,
-                                                         const float* __restrict__ part_loss, float inv_batch,
-                                                         float* __restrict__ loss_out) {
-    __shared__ float gs[kRedGroups][kRedParams];
-    const int quad = threadIdx.x % (kRedParams / 4), grp = threadIdx.x / (kRedParams / 4);
-    const int p4 = blockIdx.x * kRedParams + 4 * quad;        // first of the thread's four parameters
-    if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
-        float l = 0.0f;
-        int b = 0;
-        for (; b + 8 <= nblk; b += 8) {
-            float v[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = part_loss[b + i];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) l += v[i];
-        }
-        for (; b < nblk; ++b) l += part_loss[b];
-        *loss_out = l * inv_batch;
-    }
-    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (p4 < kParams) {
-        int b = grp;
-        for (; b + 7 * kRedGroups < nblk; b += 8 * kRedGroups) {
-            float4 v[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                v[i] = *reinterpret_cast<const float4*>(part + (size_t)(b + i * kRedGroups) * kPartStride + p4);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                acc.x += v[i].x;
-                acc.y += v[i].y;
-                acc.z += v[i].z;
-                acc.w += v[i].w;
-            }
-        }
-        for (; b < nblk; b += kRedGroups) {
-            const float4 v = *reinterpret_cast<const float4*>(part + (size_t)b * kPartStride + p4);
-            acc.x += v.x;
-            acc.y += v.y;
-            acc.z += v.z;
-            acc.w += v.w;
-        }
-    }
-    gs[grp][4 * quad + 0] = acc.x;
-    gs[grp][4 * quad + 1] = acc.y;
-    gs[grp][4 * quad + 2] = acc.z;
-    gs[grp][4 * quad + 3] = acc.w;
-    __syncthreads();
-    const int pl = threadIdx.x, p = blockIdx.x * kRedParams + pl;
-    if (pl >= kRedParams || p >= kParams) return;
-    float gsum = gs[0][pl];
-#pragma unroll
-    for (int g = 1; g < kRedGroups; ++g) gsum += gs[g][pl];
+struct AdamArgs {
+    float lr, b1, b2, eps, bc1, bc2;
+};
+
+// Adam on parameter p with gradient g (or, with grad_out, the gradient).
+__device__ __forceinline__ void apply_grad(int p, float g, float* __restrict__ P, float* __restrict__ adam,
+                                           float* __restrict__ grad_out, const AdamArgs& h) {
     if (grad_out) {
-        grad_out[p] = gsum;
+        grad_out[p] = g;
         return;
     }
     float m = adam[p], v = adam[kParams + p];
-    m = b1 * m + (1.0f - b1) * gsum;
-    v = b2 * v + (1.0f - b2) * gsum * gsum;
+    m = h.b1 * m + (1.0f - h.b1) * g;
+    v = h.b2 * v + (1.0f - h.b2) * g * g;
     adam[p] = m;
     adam[kParams + p] = v;
-    const float mh = m / bc1, vh = v / bc2;
-    P[p] -= lr * mh / (sqrtf(vh) + eps);
+    const float mh = m / h.bc1, vh = v / h.bc2;
+    P[p] -= h.lr * mh / (sqrtf(vh) + h.eps);
+}
+
+// Gradient sums and the parameter update.  Blocks [0, kTiles) take a
+// 16 x 16 tile of dW2 = dZ2^T H1 or dW3 = dZ3^T H2 over the whole batch on
+// the matrix cores: wave w of 16 adds the fwd_bwd blocks w, w + 16, ... in
+// four accumulators (the i-th into accumulator i % 4), the four and then
+// the 16 wave sums are added in order.  Consecutive blocks go to different XCDs (each with its
+// own L2), so the tiles are laid out for that: XCD x takes, in each matrix,
+// the 2 x 4 tiles of rows 2 (x / 2) + 0..1 and columns 4 (x % 2) + 0..3,
+// and its L2 holds two dZ and four H column slices instead of all of them.
+// Blocks [kTiles, kTiles + kSmallBlocks) take kSmallPerBlock entries of the
+// small partials each: thread (group g, quad u) adds entries 4u .. 4u+3 of
+// every kRedGroups-th block partial (g, g + kRedGroups, ...) with 16-byte
+// loads, eight in flight, and the group sums are added in group order.
+// Every sum thus has a fixed order for a given batch size, and no block
+// reads what another block of the launch writes.
+__global__ __launch_bounds__(kUpdThreads) void mlp_update_kernel(Acts act, const float* __restrict__ small, int nblk,
+                                                                 float* __restrict__ P, float* __restrict__ adam,
+                                                                 float* __restrict__ grad_out, AdamArgs h,
+                                                                 float inv_batch, float* __restrict__ loss_out) {
+    const int tid = threadIdx.x;
+    if (blockIdx.x >= kTiles) {
+        __shared__ float gs[kRedGroups][kSmallPerBlock];
+        const int sb = blockIdx.x - kTiles;
+        const int quad = tid % (kSmallPerBlock / 4), grp = tid / (kSmallPerBlock / 4);
+        const int k4 = sb * kSmallPerBlock + 4 * quad;
+        float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (k4 < kSmallStride) {
+            int b = grp;
+            for (; b + 7 * kRedGroups < nblk; b += 8 * kRedGroups) {
+                float4 v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    v[i] = *reinterpret_cast<const float4*>(small + (size_t)(b + i * kRedGroups) * kSmallStride + k4);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    acc.x += v[i].x;
+                    acc.y += v[i].y;
+                    acc.z += v[i].z;
+                    acc.w += v[i].w;
+                }
+            }
+            for (; b < nblk; b += kRedGroups) {
+                const float4 v = *reinterpret_cast<const float4*>(small + (size_t)b * kSmallStride + k4);
+                acc.x += v.x;
+                acc.y += v.y;
+                acc.z += v.z;
+                acc.w += v.w;
+            }
+        }
+        gs[grp][4 * quad + 0] = acc.x;
+        gs[grp][4 * quad + 1] = acc.y;
+        gs[grp][4 * quad + 2] = acc.z;
+        gs[grp][4 * quad + 3] = acc.w;
+        __syncthreads();
+        const int k = sb * kSmallPerBlock + tid;
+        if (tid >= kSmallPerBlock || k >= kSmall) return;
+        float g = gs[0][tid];
+#pragma unroll
+        for (int i = 1; i < kRedGroups; ++i) g += gs[i][tid];
+        if (k == sLoss) {
+            if (loss_out) *loss_out = g * inv_batch;
+            return;
+        }
+        apply_grad(small_param(k), g, P, adam, grad_out, h);
+        return;
+    }
+    __shared__ float red[kUpdWaves][kTile * kTile];
+    const int x = blockIdx.x % kXcdCount, slot = blockIdx.x / kXcdCount;
+    const int mat = slot / (kTilesPerMat / kXcdCount), k8 = slot % (kTilesPerMat / kXcdCount);
+    const int j0 = (2 * (x / 2) + k8 / 4) * kTile, i0 = (4 * (x % 2) + k8 % 4) * kTile;
+    const float* __restrict__ D = mat == 0 ? act.d2 : act.d3;
+    const float* __restrict__ Hs = mat == 0 ? act.h1 : act.h2;
+    const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
+    // lane (q, c): the k-slot q of instruction t is sample 4 q + t of the
+    // fwd_bwd block, row j0 + c of dZ^T and column i0 + c of H
+    const size_t dro = (size_t)(j0 + c) * kS + 4 * q, hco = (size_t)(i0 + c) * kS + 4 * q;
+    f32x4 acc[4] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f},
+                    {0.0f, 0.0f, 0.0f, 0.0f}};
+    // wave w takes the fwd_bwd blocks w, w + kUpdWaves, ... (the i-th into
+    // accumulator i % 4), with the operands of the next kUpdDepth blocks in
+    // flight: each block's loads are issued when the block kUpdDepth before
+    // it has been consumed
+    float4 dv[kUpdDepth], hv[kUpdDepth];
+#pragma unroll
+    for (int u = 0; u < kUpdDepth; ++u) {
+        const int b = wave + u * kUpdWaves;
+        if (b < nblk) {
+            dv[u] = *reinterpret_cast<const float4*>(D + (size_t)b * kH * kS + dro);
+            hv[u] = *reinterpret_cast<const float4*>(Hs + (size_t)b * kH * kS + hco);
+        }
+    }
+    for (int i0 = 0; wave + i0 * kUpdWaves < nblk; i0 += kUpdDepth) {
+#pragma unroll
+        for (int u = 0; u < kUpdDepth; ++u) {
+            const int b = wave + (i0 + u) * kUpdWaves;
+            if (b < nblk) {
+                acc[u % 4] = mfma16(dv[u].x, hv[u].x, acc[u % 4]);
+                acc[u % 4] = mfma16(dv[u].y, hv[u].y, acc[u % 4]);
+                acc[u % 4] = mfma16(dv[u].z, hv[u].z, acc[u % 4]);
+                acc[u % 4] = mfma16(dv[u].w, hv[u].w, acc[u % 4]);
+                const int bn = b + kUpdDepth * kUpdWaves;
+                if (bn < nblk) {
+                    dv[u] = *reinterpret_cast<const float4*>(D + (size_t)bn * kH * kS + dro);
+                    hv[u] = *reinterpret_cast<const float4*>(Hs + (size_t)bn * kH * kS + hco);
+                }
+            }
+        }
+    }
+    // tile entry e = (j - j0) * kTile + (i - i0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wave][(4 * q + r) * kTile + c] = ((acc[0][r] + acc[1][r]) + acc[2][r]) + acc[3][r];
+    __syncthreads();
+    if (tid >= kTile * kTile) return;
+    const int e = tid;
+    float g = red[0][e];
+#pragma unroll
+    for (int w = 1; w < kUpdWaves; ++w) g += red[w][e];
+    apply_grad((mat == 0 ? oW2 : oW3) + (j0 + e / kTile) * kH + i0 + e % kTile, g, P, adam, grad_out, h);
 }
 
 // k smallest entries of v (k <= 64), ascending, ties to the smaller index;
@@ -457,12 +609,20 @@ __global__ __launch_bounds__(1024) void topk_min_kernel(const float* __restrict_
 
 struct Mlp {
     int max_batch = 0;
-    float* part = nullptr;
-    float* part_loss = nullptr;
+    int nblk_cap = 0;
+    float* acts = nullptr;         // 4 arrays of nblk_cap [kH][kS] slabs
+    float* small = nullptr;        // nblk_cap x kSmallStride
+    float4* xe = nullptr;          // encoded samples of a pass (training)
+    float* te = nullptr;
+    size_t enc_cap = 0;
+    Acts act() const {
+        const size_t a = (size_t)nblk_cap * kH * kS;
+        return Acts{acts, acts + a, acts + 2 * a, acts + 3 * a};
+    }
 };
 
-// The forward/backward kernel takes more than 64 KB of LDS: raise its limit
-// once (gfx950 has 160 KB per compute unit).
+// The forward/backward kernel can take more than 64 KB of LDS: raise its
+// limit once (gfx950 has 160 KB per compute unit).
 static int fwd_bwd_lds_once() {
     static const int st = hip_check((int)hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_fwd_bwd_kernel),
                                                              hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -471,18 +631,34 @@ static int fwd_bwd_lds_once() {
     return st;
 }
 
-static int launch_fwd_bwd(const float* P, const MlpData& d, int train, float* part, float* part_loss, float* pred,
+static int launch_fwd_bwd(const float* P, const MlpData& d, int train, const Acts& act, float* small, float* pred,
                           hipStream_t s) {
     const int st = fwd_bwd_lds_once();
     if (st != WG_OK) return st;
     const int nblk = (d.n + kS - 1) / kS;
-    hipLaunchKernelGGL(mlp_fwd_bwd_kernel, dim3(nblk), dim3(kThreads), kMlpLds, s, P, d, train, part, part_loss,
-                       pred);
+    hipLaunchKernelGGL(mlp_fwd_bwd_kernel, dim3(nblk), dim3(kThreads), kMlpLds, s, P, d, train, act, small, pred);
     return hip_check((int)hipGetLastError(), "mlp_fwd_bwd_kernel");
 }
 
-static int launch_step(Mlp& M, const float* P, const MlpData& d, int train, float* pred, hipStream_t s) {
-    return launch_fwd_bwd(P, d, train, M.part, M.part_loss, pred, s);
+// One gradient step over the n samples of d: fwd_bwd, then the update
+// (Adam with h, or the gradient to grad_out).
+static int launch_step(Mlp& M, float* P, const MlpData& d, float* adam, float* grad_out, const AdamArgs& h,
+                       float* loss_out, hipStream_t s) {
+    const Acts act = M.act();
+    int st = launch_fwd_bwd(P, d, 1, act, M.small, nullptr, s);
+    if (st != WG_OK) return st;
+    const int nblk = (d.n + kS - 1) / kS;
+    hipLaunchKernelGGL(mlp_update_kernel, dim3(kTiles + kSmallBlocks), dim3(kUpdThreads), 0, s, act, M.small, nblk,
+                       P, adam, grad_out, h, 1.0f / d.n, loss_out);
+    return hip_check((int)hipGetLastError(), "mlp_update_kernel");
+}
+
+static void free_mlp(Mlp* M) {
+    if (M->acts) (void)hipFree(M->acts);
+    if (M->small) (void)hipFree(M->small);
+    if (M->xe) (void)hipFree(M->xe);
+    if (M->te) (void)hipFree(M->te);
+    delete M;
 }
 
 }  // namespace wg
@@ -498,11 +674,11 @@ int wg_mlp_create(wg_mlp** out, int max_batch) {
     Mlp* M = new (std::nothrow) Mlp();
     if (!M) return fail(WG_ENOMEM, "wg_mlp_create: out of host memory");
     M->max_batch = max_batch;
-    const size_t nblk = (size_t)(max_batch + kS - 1) / kS;
-    if (hipMalloc((void**)&M->part, sizeof(float) * nblk * kPartStride) != hipSuccess ||
-        hipMalloc((void**)&M->part_loss, sizeof(float) * nblk) != hipSuccess) {
-        if (M->part) (void)hipFree(M->part);
-        delete M;
+    M->nblk_cap = (max_batch + kS - 1) / kS;
+    const size_t nb = (size_t)M->nblk_cap;
+    if (hipMalloc((void**)&M->acts, sizeof(float) * 4 * nb * kH * kS) != hipSuccess ||
+        hipMalloc((void**)&M->small, sizeof(float) * nb * kSmallStride) != hipSuccess) {
+        free_mlp(M);
         return fail(WG_ENOMEM, "wg_mlp_create: device allocation failed");
     }
     *out = reinterpret_cast<wg_mlp*>(M);
@@ -512,9 +688,7 @@ int wg_mlp_create(wg_mlp** out, int max_batch) {
 int wg_mlp_destroy(wg_mlp* mlp) {
     Mlp* M = reinterpret_cast<Mlp*>(mlp);
     if (!M) return WG_OK;
-    if (M->part) (void)hipFree(M->part);
-    if (M->part_loss) (void)hipFree(M->part_loss);
-    delete M;
+    free_mlp(M);
     return WG_OK;
 }
 
@@ -532,15 +706,11 @@ int wg_mlp_gradient(wg_mlp* mlp, const float* params, const double* c1, const do
     int st = check_data(c1, m, r, n);
     if (st != WG_OK) return st;
     if (n > M.max_batch) return fail(WG_EINVAL, "wg_mlp_gradient: n exceeds max_batch");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const MlpData d{c1, c2, m, r, target, nullptr, n, 2.0f / n};
-    st = launch_step(M, params, d, 1, nullptr, s);
-    if (st != WG_OK) return st;
-    const int nblk = (n + kS - 1) / kS;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s, M.part,
-                       nblk, nullptr,
-                       nullptr, grad_out, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f, M.part_loss, 1.0f / n, loss_out);
-    return hip_check((int)hipGetLastError(), "mlp_reduce_kernel");
+    const MlpData d{c1, c2, m, r, target, nullptr, nullptr, n, 2.0f / n};
+    const AdamArgs none{0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f};
+    // params is read only: the update writes the gradient, not the parameters
+    return launch_step(M, const_cast<float*>(params), d, nullptr, grad_out, none, loss_out,
+                       static_cast<hipStream_t>(stream));
 }
 
 int wg_mlp_train(wg_mlp* mlp, float* params, float* adam_state, int step0, float lr, const double* c1,
@@ -555,19 +725,35 @@ int wg_mlp_train(wg_mlp* mlp, float* params, float* adam_state, int step0, float
         return fail(WG_EINVAL, "wg_mlp_train: bad batch, epochs, step0 or lr");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int steps = n / batch;                      // the tail of each permutation is dropped
+    const int used = steps * batch;
+    if ((size_t)used > M.enc_cap) {
+        // grow the per-pass sample buffers (hipFree waits for work that may
+        // still read the old ones)
+        if (M.xe) (void)hipFree(M.xe);
+        if (M.te) (void)hipFree(M.te);
+        M.xe = nullptr;
+        M.te = nullptr;
+        M.enc_cap = 0;
+        if (hipMalloc((void**)&M.xe, sizeof(float4) * used) != hipSuccess ||
+            hipMalloc((void**)&M.te, sizeof(float) * used) != hipSuccess) {
+            if (M.xe) (void)hipFree(M.xe);
+            M.xe = nullptr;
+            return fail(WG_ENOMEM, "wg_mlp_train: device allocation failed");
+        }
+        M.enc_cap = (size_t)used;
+    }
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     int t = step0;
     for (int e = 0; e < epochs; ++e) {
+        hipLaunchKernelGGL(mlp_encode_kernel, dim3((used + 255) / 256), dim3(256), 0, s, c1, c2, m, r, target,
+                           perm + (size_t)e * n, n, used, M.xe, M.te);
+        st = hip_check((int)hipGetLastError(), "mlp_encode_kernel");
+        if (st != WG_OK) return st;
         for (int b = 0; b < steps; ++b, ++t) {
-            const MlpData d{c1, c2, m, r, target, perm + (size_t)e * n + (size_t)b * batch, batch, 2.0f / batch};
-            st = launch_step(M, params, d, 1, nullptr, s);
-            if (st != WG_OK) return st;
-            const float bc1 = 1.0f - powf(b1, (float)t), bc2 = 1.0f - powf(b2, (float)t);
-            hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + kRedParams - 1) / kRedParams), dim3(256), 0, s,
-                               M.part,
-                               (batch + kS - 1) / kS, params, adam_state, nullptr, lr, b1, b2, eps, bc1, bc2,
-                               M.part_loss, 1.0f / batch, losses + (size_t)e * steps + b);
-            st = hip_check((int)hipGetLastError(), "mlp_reduce_kernel");
+            const size_t o = (size_t)b * batch;
+            const MlpData d{c1, c2, m, r, target, M.xe + o, M.te + o, batch, 2.0f / batch};
+            const AdamArgs h{lr, b1, b2, eps, 1.0f - powf(b1, (float)t), 1.0f - powf(b2, (float)t)};
+            st = launch_step(M, params, d, adam_state, nullptr, h, losses + (size_t)e * steps + b, s);
             if (st != WG_OK) return st;
         }
     }
@@ -579,8 +765,9 @@ int wg_mlp_predict(const float* params, const double* c1, const double* c2, cons
     if (!params || !out) return fail(WG_EINVAL, "wg_mlp_predict: null pointer");
     int st = check_data(c1, m, r, n);
     if (st != WG_OK) return st;
-    const MlpData d{c1, c2, m, r, nullptr, nullptr, n, 0.0f};
-    return launch_fwd_bwd(params, d, 0, nullptr, nullptr, out, static_cast<hipStream_t>(stream));
+    const MlpData d{c1, c2, m, r, nullptr, nullptr, nullptr, n, 0.0f};
+    return launch_fwd_bwd(params, d, 0, Acts{nullptr, nullptr, nullptr, nullptr}, nullptr, out,
+                          static_cast<hipStream_t>(stream));
 }
 
 int wg_topk_min(const float* v, int n, int k, int* idx_out, wg_stream_t stream) {
