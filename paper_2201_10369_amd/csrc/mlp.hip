@@ -16,11 +16,12 @@
 //             (the operands of the two 128 x 128 weight gradients) and its
 //             partial sums of the small gradients (W1, b1, b2, b3, W4, b4)
 //             and of the loss
-//   update  : the weight gradients dW = dZ^T H of the two 128 x 128 layers
-//             on the matrix cores, one 16 x 16 parameter tile per block over
-//             the whole batch; the small gradients summed over the fwd_bwd
-//             blocks in a fixed order; then Adam (or the plain gradient) on
-//             every parameter
+//   wgrad   : the weight gradients dW = dZ^T H of the two 128 x 128 layers
+//             on the matrix cores, a block per 32 x 32 parameter tile and
+//             slice of the batch; the small gradients summed over the
+//             fwd_bwd blocks in a fixed order and their parameters updated
+//   wadam   : the slice sums of dW2 and dW3 added in order, then Adam (or
+//             the plain gradient) on those parameters
 //   predict : the forward part of fwd_bwd
 //   topk    : the k smallest values of a vector (ties -> smaller index)
 #include <hip/hip_runtime.h>
@@ -63,16 +64,20 @@ __device__ __forceinline__ int small_param(int k) {
          : k < sb4 ? oW4 + (k - sW4)
                    : ob4;
 }
-// Weight-gradient tiles of W2 and W3: 16 x 16 parameters each, a block
-// per tile over the whole batch.
-constexpr int kTile = 16, kTilesPerMat = (kH / kTile) * (kH / kTile), kTiles = 2 * kTilesPerMat;
-constexpr int kUpdThreads = 1024;
+// Weight gradients of W2 and W3: 32 x 32 tiles, the batch cut into at most
+// kMaxSlices slices of consecutive fwd_bwd blocks, a block per (tile,
+// slice); the slice sums go to a [slice][kBig] buffer and a last launch adds
+// them in slice order.
+constexpr int kTile = 32, kTilesPerMat = (kH / kTile) * (kH / kTile), kTiles = 2 * kTilesPerMat;
+constexpr int kMaxSlices = kXcdCount;
+constexpr int kBig = 2 * kH * kH;            // W2 then W3
+constexpr int kUpdThreads = 512;
 constexpr int kUpdWaves = kUpdThreads / 64;
-constexpr int kUpdDepth = 8;       // fwd_bwd blocks whose operands a wave keeps in flight
+constexpr int kUpdDepth = 4;       // fwd_bwd blocks whose operands a wave keeps in flight
 constexpr int kSmallPerBlock = 64;
 constexpr int kSmallBlocks = (kSmall + kSmallPerBlock - 1) / kSmallPerBlock;
 constexpr int kRedGroups = kUpdThreads / (kSmallPerBlock / 4);
-static_assert(kTilesPerMat % kXcdCount == 0 && kTilesPerMat / kXcdCount == 8, "tile regions of 2 x 4 tiles");
+constexpr int kAdamThreads = 256;
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 // GELU and its derivative from one evaluation of the normal CDF
@@ -445,28 +450,27 @@ __device__ __forceinline__ void apply_grad(int p, float g, float* __restrict__ P
     P[p] -= h.lr * mh / (sqrtf(vh) + h.eps);
 }
 
-// Gradient sums and the parameter update.  Blocks [0, kTiles) take a
-// 16 x 16 tile of dW2 = dZ2^T H1 or dW3 = dZ3^T H2 over the whole batch on
-// the matrix cores: wave w of 16 adds the fwd_bwd blocks w, w + 16, ... in
-// four accumulators (the i-th into accumulator i % 4), the four and then
-// the 16 wave sums are added in order.  Consecutive blocks go to different XCDs (each with its
-// own L2), so the tiles are laid out for that: XCD x takes, in each matrix,
-// the 2 x 4 tiles of rows 2 (x / 2) + 0..1 and columns 4 (x % 2) + 0..3,
-// and its L2 holds two dZ and four H column slices instead of all of them.
-// Blocks [kTiles, kTiles + kSmallBlocks) take kSmallPerBlock entries of the
-// small partials each: thread (group g, quad u) adds entries 4u .. 4u+3 of
-// every kRedGroups-th block partial (g, g + kRedGroups, ...) with 16-byte
-// loads, eight in flight, and the group sums are added in group order.
-// Every sum thus has a fixed order for a given batch size, and no block
-// reads what another block of the launch writes.
-__global__ __launch_bounds__(kUpdThreads) void mlp_update_kernel(Acts act, const float* __restrict__ small, int nblk,
-                                                                 float* __restrict__ P, float* __restrict__ adam,
-                                                                 float* __restrict__ grad_out, AdamArgs h,
-                                                                 float inv_batch, float* __restrict__ loss_out) {
+// Gradient sums.  Blocks [0, kTiles * nslice) take a (tile, slice) pair,
+// tile = block / nslice, slice = block % nslice (with 8 slices, slice k runs
+// on XCD k, whose L2 then holds only that slice's operands): the 32 x 32
+// tile of dW2 = dZ2^T H1 or dW3 = dZ3^T H2 over the slice's fwd_bwd blocks
+// on the matrix cores, wave w of 8 adding the slice's blocks w, w + 8, ...
+// in four 16 x 16 accumulators, the 8 wave sums added in order, to
+// slice_part[slice].  Blocks [kTiles * nslice, + kSmallBlocks) take
+// kSmallPerBlock entries of the small partials each: thread (group g, quad
+// u) adds entries 4u .. 4u+3 of every kRedGroups-th block partial (g,
+// g + kRedGroups, ...) with 16-byte loads, eight in flight, the group sums
+// are added in group order, and the parameter is updated (or the gradient
+// written).  No block reads what another block of the launch writes.
+__global__ __launch_bounds__(kUpdThreads) void mlp_wgrad_kernel(Acts act, const float* __restrict__ small, int nblk,
+                                                                int nslice, float* __restrict__ slice_part,
+                                                                float* __restrict__ P, float* __restrict__ adam,
+                                                                float* __restrict__ grad_out, AdamArgs h,
+                                                                float inv_batch, float* __restrict__ loss_out) {
     const int tid = threadIdx.x;
-    if (blockIdx.x >= kTiles) {
+    if (blockIdx.x >= kTiles * nslice) {
         __shared__ float gs[kRedGroups][kSmallPerBlock];
-        const int sb = blockIdx.x - kTiles;
+        const int sb = blockIdx.x - kTiles * nslice;
         const int quad = tid % (kSmallPerBlock / 4), grp = tid / (kSmallPerBlock / 4);
         const int k4 = sb * kSmallPerBlock + 4 * quad;
         float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -511,57 +515,98 @@ __global__ __launch_bounds__(kUpdThreads) void mlp_update_kernel(Acts act, const
         return;
     }
     __shared__ float red[kUpdWaves][kTile * kTile];
-    const int x = blockIdx.x % kXcdCount, slot = blockIdx.x / kXcdCount;
-    const int mat = slot / (kTilesPerMat / kXcdCount), k8 = slot % (kTilesPerMat / kXcdCount);
-    const int j0 = (2 * (x / 2) + k8 / 4) * kTile, i0 = (4 * (x % 2) + k8 % 4) * kTile;
+    const int tile = blockIdx.x / nslice, slice = blockIdx.x % nslice;
+    const int mat = tile / kTilesPerMat, tj = (tile % kTilesPerMat) / (kH / kTile), ti = tile % (kH / kTile);
+    const int j0 = tj * kTile, i0 = ti * kTile;
     const float* __restrict__ D = mat == 0 ? act.d2 : act.d3;
     const float* __restrict__ Hs = mat == 0 ? act.h1 : act.h2;
+    const int blo = slice * nblk / nslice, bhi = (slice + 1) * nblk / nslice;
     const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, c = lane & 15;
     // lane (q, c): the k-slot q of instruction t is sample 4 q + t of the
-    // fwd_bwd block, row j0 + c of dZ^T and column i0 + c of H
+    // fwd_bwd block; rows j0 + c, j0 + 16 + c of dZ^T, columns i0 + c,
+    // i0 + 16 + c of H
     const size_t dro = (size_t)(j0 + c) * kS + 4 * q, hco = (size_t)(i0 + c) * kS + 4 * q;
-    f32x4 acc[4] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f},
-                    {0.0f, 0.0f, 0.0f, 0.0f}};
-    // wave w takes the fwd_bwd blocks w, w + kUpdWaves, ... (the i-th into
-    // accumulator i % 4), with the operands of the next kUpdDepth blocks in
-    // flight: each block's loads are issued when the block kUpdDepth before
-    // it has been consumed
-    float4 dv[kUpdDepth], hv[kUpdDepth];
+    constexpr size_t k16 = (size_t)16 * kS;
+    f32x4 a00 = {0.0f, 0.0f, 0.0f, 0.0f}, a01 = a00, a10 = a00, a11 = a00;
+    // the operands of the wave's next kUpdDepth blocks in flight: each
+    // block's loads are issued when the block kUpdDepth before it has been
+    // consumed
+    float4 da[kUpdDepth], db[kUpdDepth], ha[kUpdDepth], hb[kUpdDepth];
 #pragma unroll
     for (int u = 0; u < kUpdDepth; ++u) {
-        const int b = wave + u * kUpdWaves;
-        if (b < nblk) {
-            dv[u] = *reinterpret_cast<const float4*>(D + (size_t)b * kH * kS + dro);
-            hv[u] = *reinterpret_cast<const float4*>(Hs + (size_t)b * kH * kS + hco);
+        const int b = blo + wave + u * kUpdWaves;
+        if (b < bhi) {
+            const float* Db = D + (size_t)b * kH * kS + dro;
+            const float* Hb = Hs + (size_t)b * kH * kS + hco;
+            da[u] = *reinterpret_cast<const float4*>(Db);
+            db[u] = *reinterpret_cast<const float4*>(Db + k16);
+            ha[u] = *reinterpret_cast<const float4*>(Hb);
+            hb[u] = *reinterpret_cast<const float4*>(Hb + k16);
         }
     }
-    for (int i0 = 0; wave + i0 * kUpdWaves < nblk; i0 += kUpdDepth) {
+    for (int i0b = 0; blo + wave + i0b * kUpdWaves < bhi; i0b += kUpdDepth) {
 #pragma unroll
         for (int u = 0; u < kUpdDepth; ++u) {
-            const int b = wave + (i0 + u) * kUpdWaves;
-            if (b < nblk) {
-                acc[u % 4] = mfma16(dv[u].x, hv[u].x, acc[u % 4]);
-                acc[u % 4] = mfma16(dv[u].y, hv[u].y, acc[u % 4]);
-                acc[u % 4] = mfma16(dv[u].z, hv[u].z, acc[u % 4]);
-                acc[u % 4] = mfma16(dv[u].w, hv[u].w, acc[u % 4]);
+            const int b = blo + wave + (i0b + u) * kUpdWaves;
+            if (b < bhi) {
+                a00 = mfma16(da[u].x, ha[u].x, a00);
+                a01 = mfma16(da[u].x, hb[u].x, a01);
+                a10 = mfma16(db[u].x, ha[u].x, a10);
+                a11 = mfma16(db[u].x, hb[u].x, a11);
+                a00 = mfma16(da[u].y, ha[u].y, a00);
+                a01 = mfma16(da[u].y, hb[u].y, a01);
+                a10 = mfma16(db[u].y, ha[u].y, a10);
+                a11 = mfma16(db[u].y, hb[u].y, a11);
+                a00 = mfma16(da[u].z, ha[u].z, a00);
+                a01 = mfma16(da[u].z, hb[u].z, a01);
+                a10 = mfma16(db[u].z, ha[u].z, a10);
+                a11 = mfma16(db[u].z, hb[u].z, a11);
+                a00 = mfma16(da[u].w, ha[u].w, a00);
+                a01 = mfma16(da[u].w, hb[u].w, a01);
+                a10 = mfma16(db[u].w, ha[u].w, a10);
+                a11 = mfma16(db[u].w, hb[u].w, a11);
                 const int bn = b + kUpdDepth * kUpdWaves;
-                if (bn < nblk) {
-                    dv[u] = *reinterpret_cast<const float4*>(D + (size_t)bn * kH * kS + dro);
-                    hv[u] = *reinterpret_cast<const float4*>(Hs + (size_t)bn * kH * kS + hco);
+                if (bn < bhi) {
+                    const float* Db = D + (size_t)bn * kH * kS + dro;
+                    const float* Hb = Hs + (size_t)bn * kH * kS + hco;
+                    da[u] = *reinterpret_cast<const float4*>(Db);
+                    db[u] = *reinterpret_cast<const float4*>(Db + k16);
+                    ha[u] = *reinterpret_cast<const float4*>(Hb);
+                    hb[u] = *reinterpret_cast<const float4*>(Hb + k16);
                 }
             }
         }
     }
     // tile entry e = (j - j0) * kTile + (i - i0)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[wave][(4 * q + r) * kTile + c] = ((acc[0][r] + acc[1][r]) + acc[2][r]) + acc[3][r];
+    for (int r = 0; r < 4; ++r) {
+        red[wave][(4 * q + r) * kTile + c] = a00[r];
+        red[wave][(4 * q + r) * kTile + 16 + c] = a01[r];
+        red[wave][(16 + 4 * q + r) * kTile + c] = a10[r];
+        red[wave][(16 + 4 * q + r) * kTile + 16 + c] = a11[r];
+    }
     __syncthreads();
-    if (tid >= kTile * kTile) return;
-    const int e = tid;
-    float g = red[0][e];
+    float* out = slice_part + (size_t)slice * kBig + (size_t)mat * kH * kH;
 #pragma unroll
-    for (int w = 1; w < kUpdWaves; ++w) g += red[w][e];
-    apply_grad((mat == 0 ? oW2 : oW3) + (j0 + e / kTile) * kH + i0 + e % kTile, g, P, adam, grad_out, h);
+    for (int u = 0; u < kTile * kTile / kUpdThreads; ++u) {
+        const int e = tid + u * kUpdThreads;
+        float g = red[0][e];
+#pragma unroll
+        for (int w = 1; w < kUpdWaves; ++w) g += red[w][e];
+        out[(j0 + e / kTile) * kH + i0 + e % kTile] = g;
+    }
+}
+
+// W2 and W3: the slice sums added in slice order, then the update (or the
+// gradient).
+__global__ __launch_bounds__(kAdamThreads) void mlp_wadam_kernel(const float* __restrict__ slice_part, int nslice,
+                                                                 float* __restrict__ P, float* __restrict__ adam,
+                                                                 float* __restrict__ grad_out, AdamArgs h) {
+    const int k = blockIdx.x * kAdamThreads + threadIdx.x;
+    if (k >= kBig) return;
+    float g = slice_part[k];
+    for (int sl = 1; sl < nslice; ++sl) g += slice_part[(size_t)sl * kBig + k];
+    apply_grad(k < kH * kH ? oW2 + k : oW3 + (k - kH * kH), g, P, adam, grad_out, h);
 }
 
 // k smallest entries of v (k <= 64), ascending, ties to the smaller index;
@@ -612,6 +657,7 @@ struct Mlp {
     int nblk_cap = 0;
     float* acts = nullptr;         // 4 arrays of nblk_cap [kH][kS] slabs
     float* small = nullptr;        // nblk_cap x kSmallStride
+    float* slice_part = nullptr;   // kMaxSlices x kBig
     float4* xe = nullptr;          // encoded samples of a pass (training)
     float* te = nullptr;
     size_t enc_cap = 0;
@@ -640,22 +686,29 @@ static int launch_fwd_bwd(const float* P, const MlpData& d, int train, const Act
     return hip_check((int)hipGetLastError(), "mlp_fwd_bwd_kernel");
 }
 
-// One gradient step over the n samples of d: fwd_bwd, then the update
-// (Adam with h, or the gradient to grad_out).
+// One gradient step over the n samples of d: fwd_bwd, the gradient sums and
+// the update of the small parameters, then that of W2 and W3 (Adam with h,
+// or the gradient to grad_out).
 static int launch_step(Mlp& M, float* P, const MlpData& d, float* adam, float* grad_out, const AdamArgs& h,
                        float* loss_out, hipStream_t s) {
     const Acts act = M.act();
     int st = launch_fwd_bwd(P, d, 1, act, M.small, nullptr, s);
     if (st != WG_OK) return st;
     const int nblk = (d.n + kS - 1) / kS;
-    hipLaunchKernelGGL(mlp_update_kernel, dim3(kTiles + kSmallBlocks), dim3(kUpdThreads), 0, s, act, M.small, nblk,
-                       P, adam, grad_out, h, 1.0f / d.n, loss_out);
-    return hip_check((int)hipGetLastError(), "mlp_update_kernel");
+    const int nslice = nblk < kMaxSlices ? nblk : kMaxSlices;
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(kTiles * nslice + kSmallBlocks), dim3(kUpdThreads), 0, s, act, M.small,
+                       nblk, nslice, M.slice_part, P, adam, grad_out, h, 1.0f / d.n, loss_out);
+    st = hip_check((int)hipGetLastError(), "mlp_wgrad_kernel");
+    if (st != WG_OK) return st;
+    hipLaunchKernelGGL(mlp_wadam_kernel, dim3((kBig + kAdamThreads - 1) / kAdamThreads), dim3(kAdamThreads), 0, s,
+                       M.slice_part, nslice, P, adam, grad_out, h);
+    return hip_check((int)hipGetLastError(), "mlp_wadam_kernel");
 }
 
 static void free_mlp(Mlp* M) {
     if (M->acts) (void)hipFree(M->acts);
     if (M->small) (void)hipFree(M->small);
+    if (M->slice_part) (void)hipFree(M->slice_part);
     if (M->xe) (void)hipFree(M->xe);
     if (M->te) (void)hipFree(M->te);
     delete M;
@@ -677,7 +730,8 @@ int wg_mlp_create(wg_mlp** out, int max_batch) {
     M->nblk_cap = (max_batch + kS - 1) / kS;
     const size_t nb = (size_t)M->nblk_cap;
     if (hipMalloc((void**)&M->acts, sizeof(float) * 4 * nb * kH * kS) != hipSuccess ||
-        hipMalloc((void**)&M->small, sizeof(float) * nb * kSmallStride) != hipSuccess) {
+        hipMalloc((void**)&M->small, sizeof(float) * nb * kSmallStride) != hipSuccess ||
+        hipMalloc((void**)&M->slice_part, sizeof(float) * kMaxSlices * kBig) != hipSuccess) {
         free_mlp(M);
         return fail(WG_ENOMEM, "wg_mlp_create: device allocation failed");
     }
