@@ -92,18 +92,26 @@ class Model:
 def train(data, init_params, perm, batch=4096, lr=1e-3):
     """Adam on the mean squared error of standardised log10 errors from the
     initial parameters init_params ([(W, b), ...] per layer, W (out, in)),
-    one epoch per row of perm (int32 permutations of the n samples);
+    one epoch per row of perm (int32 permutations of the n samples, on the
+    host or as a contiguous int32 tensor on the GPU);
     returns (Model, per-step losses)."""
     torch = _torch()
     n = len(data["c1"])
-    perm = np.ascontiguousarray(perm, np.int32)
+    if isinstance(perm, torch.Tensor):
+        if perm.dtype != torch.int32 or not perm.is_cuda or not perm.is_contiguous():
+            raise ValueError("perm as a tensor must be contiguous int32 on the GPU")
+        permd = perm
+    else:
+        permd = None
+        perm = np.ascontiguousarray(perm, np.int32)
     if perm.ndim != 2 or perm.shape[1] != n:
         raise ValueError("perm must have shape (epochs, n)")
     t = np.asarray(data["target"], np.float64)
     mean, std = float(t.mean()), float(t.std()) or 1.0
     params = torch.from_numpy(wg.mlp_pack(init_params)).cuda()
     adam = torch.zeros(2 * params.numel(), dtype=torch.float32, device="cuda")
-    permd = torch.from_numpy(perm).cuda()
+    if permd is None:
+        permd = torch.from_numpy(perm).cuda()
     dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in data.items() if k != "target"}
     tz = torch.from_numpy(((t - mean) / std).astype(np.float32)).cuda()
     ctx = wg.Mlp(batch)

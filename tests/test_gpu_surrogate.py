@@ -48,6 +48,51 @@ def test_gradient_matches_oracle():
             assert np.linalg.norm(a - b) <= 2e-4 * np.linalg.norm(b) + 1e-9
 
 
+@pytest.mark.parametrize("n", [1000, 4096])
+def test_gradient_matches_oracle_at_training_batches(n):
+    """The batch of the training runs (4096 samples: 256 forward blocks, the
+    weight gradients over 8 slices) and a ragged one (1000 = 62 blocks of 16
+    and one of 8), twice: the two results are bitwise equal."""
+    wg = _wg()
+    params = _params(6)
+    c1, c2, m, r, t = _data(n, 7)
+    ctx = wg.Mlp(4096)
+    args = (_dev(wg.mlp_pack(params)), _dev(c1), _dev(c2), _dev(m), _dev(r), _dev(t))
+    g, loss = ctx.gradient(*args)
+    g2, loss2 = ctx.gradient(*args)
+    assert torch.equal(g, g2) and torch.equal(loss, loss2)
+    X = omlp.features(c1, c2, m, r)
+    l64, g64 = omlp.loss_and_grads([(W.astype(np.float64), b.astype(np.float64)) for W, b in params], X, t)
+    assert loss.item() == pytest.approx(l64, rel=1e-5)
+    for (gW, gb), (oW, ob) in zip(wg.mlp_unpack(g.cpu().numpy()), g64):
+        for a, b in ((gW, oW), (gb, ob)):
+            assert np.linalg.norm(a - b) <= 2e-4 * np.linalg.norm(b) + 1e-9
+
+
+def test_training_from_device_permutations_and_bad_entries():
+    """Training with the minibatch orders already on the GPU gives the same
+    bits as from the host; an order entry outside [0, n) gives NaN losses for
+    its minibatch, not an out-of-range read."""
+    from paper_2201_10369_amd import surrogate as sg
+    wg = _wg()
+    n = 512
+    c1, c2, m, r, t = _data(n, 8)
+    data = {"c1": c1, "c2": c2, "m": m, "r": r, "target": t.astype(np.float64)}
+    perm = synth.minibatch_order(n, 2, seed=4)
+    init = _params(7)
+    a, la = sg.train(data, init, perm, batch=128)
+    b, lb = sg.train(data, init, _dev(perm), batch=128)
+    assert torch.equal(la, lb) and torch.equal(a.params, b.params)
+    bad = perm.copy()
+    bad[1, 5] = n + 7
+    ctx = wg.Mlp(128)
+    P = _dev(wg.mlp_pack(init))
+    adam = torch.zeros(2 * P.numel(), dtype=torch.float32, device="cuda")
+    losses = ctx.train(P, adam, 1, 1e-3, _dev(c1), _dev(c2), _dev(m), _dev(r),
+                       _dev(((t - t.mean()) / t.std()).astype(np.float32)), _dev(bad), 128).cpu().numpy()
+    assert np.all(np.isfinite(losses[:4])) and np.isnan(losses[4])
+
+
 def test_predict_matches_oracle():
     wg = _wg()
     params = _params(4)
