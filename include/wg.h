@@ -444,7 +444,9 @@ int wg_sweep_matrices_f64(const wg_sweep* sweep, int cand, double* AT, double* G
 
 /* ------------------------------------------------------------------------
  * Error surrogate (device).  A fully connected network 4 -> 128 -> 128 ->
- * 128 -> 1 with GELU (z * Phi(z), exact erf form) maps a point-family
+ * 128 -> 1 with GELU (z * Phi(z); the kernels evaluate the normal tail with
+ * the erfc approximation of Abramowitz and Stegun 7.1.26, absolute error at
+ * most 1.5e-7, sharing its exponential with the derivative) maps a point-family
  * description to a predicted log10 mean absolute error, so that the smooth
  * error curve (Sections 1 and 6.1) can be searched with few exact sweep
  * evaluations.  Input encoding of a sample (c1, c2, m, r):

@@ -79,13 +79,30 @@ constexpr int kSmallBlocks = (kSmall + kSmallPerBlock - 1) / kSmallPerBlock;
 constexpr int kRedGroups = kUpdThreads / (kSmallPerBlock / 4);
 constexpr int kAdamThreads = 256;
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-// GELU and its derivative from one evaluation of the normal CDF
-__device__ __forceinline__ void gelu_and_grad(float z, float& h, float& g) {
-    const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+// GELU h = z Phi(z) and its derivative g = Phi(z) + z phi(z), from one
+// exponential e = exp(-z^2 / 2).  The normal tail 1 - Phi(|z|) =
+// erfc(|z| / sqrt 2) / 2 uses the rational approximation of Abramowitz and
+// Stegun (Handbook of Mathematical Functions, 7.1.26: erfc(x) ~
+// (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x), x >= 0, absolute error
+// at most 1.5e-7), which shares that exponential and has no cancellation for
+// z < 0.
+__device__ __forceinline__ void gelu_parts(float z, float& h, float& g, bool grad) {
+    const float p = 0.3275911f, a1 = 0.254829592f, a2 = -0.284496736f, a3 = 1.421413741f, a4 = -1.453152027f,
+                a5 = 1.061405429f;
+    const float e = __expf(-0.5f * z * z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(p * 0.70710678118654752f, fabsf(z), 1.0f));
+    const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, a5, a4), a3), a2), a1);
+    const float tail = 0.5f * poly * e;                      // 1 - Phi(|z|)
+    const float cdf = z >= 0.0f ? 1.0f - tail : tail;
     h = z * cdf;
-    g = cdf + z * (expf(-0.5f * z * z) * 0.39894228040143268f);
+    if (grad) g = fmaf(z * e, 0.39894228040143268f, cdf);
 }
+__device__ __forceinline__ float gelu_f(float z) {
+    float h, g;
+    gelu_parts(z, h, g, false);
+    return h;
+}
+__device__ __forceinline__ void gelu_and_grad(float z, float& h, float& g) { gelu_parts(z, h, g, true); }
 
 // Input encoding: (ln c1 / ln 20, ln c2 / ln 20, (m - 5) / 3, r - 4).
 __device__ __forceinline__ float4 encode(const double* c1, const double* c2, const int* m, const int* r, int q) {
