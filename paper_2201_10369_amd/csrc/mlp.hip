@@ -684,8 +684,9 @@ struct Mlp {
     }
 };
 
-// The forward/backward kernel can take more than 64 KB of LDS: raise its
-// limit once (gfx950 has 160 KB per compute unit).
+// The forward/backward kernel's dynamic LDS (kMlpLds, 50 KB with the padded
+// rows) is declared to the runtime once, so that a larger kS or pitch (up to
+// the 160 KB of a gfx950 compute unit) needs no other change.
 static int fwd_bwd_lds_once() {
     static const int st = hip_check((int)hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_fwd_bwd_kernel),
                                                              hipFuncAttributeMaxDynamicSharedMemorySize,
