@@ -102,12 +102,15 @@ def test_predict_matches_oracle():
     assert np.allclose(out, ref, rtol=1e-5, atol=1e-5)
 
 
-def test_adam_training_matches_oracle():
-    """Five Adam steps on the same minibatches: the loss of every step agrees
-    with the float64 oracle, and the parameters stay close."""
+@pytest.mark.parametrize("batch", [128, 100])
+def test_adam_training_matches_oracle(batch):
+    """Adam steps on the same minibatches (batch 128: five steps; batch 100:
+    six steps of 7 forward blocks, the last one partial, over 7 slices): the
+    loss of every step agrees with the float64 oracle, and the parameters
+    stay close."""
     wg = _wg()
     params = _params(5)
-    n, batch, epochs = 640, 128, 1
+    n, epochs = 640, 1
     c1, c2, m, r, t = _data(n, 3)
     perm = synth.minibatch_order(n, epochs, seed=9)
     P = _dev(wg.mlp_pack(params))
