@@ -577,11 +577,23 @@ __device__ __forceinline__ double tile_error_1d(const Samples1d<M, R, NT, T>& sp
 constexpr int kTiles1d = 4;
 constexpr int kGroup1d = 4;          // candidates per 1D work item
 
+// Waves per SIMD the compiler must leave room for.  The float64 2D tiles of
+// F(6x6,3x3) need 281 registers per lane, one wave per SIMD; held to two
+// waves they spill 25 (104 bytes per lane) and the 4096-candidate mixed
+// sweep takes 1.34-1.40 ms instead of 2.02 ms, with identical sums.  Larger
+// tiles would spill 316-940 bytes and keep one wave; the 1D float64 tiles
+// (0.22 ms with the bound against 0.18 ms) and the float32 ones keep theirs.
+template <int M, int R, int DIMS, typename T>
+constexpr int eval_min_waves() {
+    return DIMS == 2 && sizeof(T) == 8 && R == 3 && M + R - 1 <= 8 ? 2 : 1;
+}
+
 // FAM: candidates are family sets (FamilyZeros applies), else explicit lists.
 // T: float (float32 evaluation) or double (mixed precision; mats holds the
 // float64 matrices).
 template <int M, int R, int DIMS, bool FAM, typename T>
-__global__ __launch_bounds__(256) void sweep_eval_kernel(const float* __restrict__ d_soa,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(eval_min_waves<M, R, DIMS, T>())))
+void sweep_eval_kernel(const float* __restrict__ d_soa,
                                                          const float* __restrict__ g_soa,
                                                          const double* __restrict__ yref,
                                                          const T* __restrict__ mats,
