@@ -294,29 +294,30 @@ __global__ __launch_bounds__(kThreads) void mlp_fwd_bwd_kernel(const float* __re
     const int j1 = tid & (kH - 1), p1 = tid / kH;
     const float4 w1v = *reinterpret_cast<const float4*>(P + oW1 + j1 * kIn);
     const float b1v = P[ob1 + j1];
-    // the small parameters with the samples, before the first barrier
+    // the small parameters and the samples, all in flight together before
+    // the first barrier (the weight operands follow it)
     const int t0 = wave * 16, lc = tid & 15;
     const float b2v = P[ob2 + t0 + lc], b3v = P[ob3 + t0 + lc], b4v = P[ob4];
-    if (tid < kH) W4s[tid] = P[oW4 + tid];
-    // the samples first: their loads must not queue behind the weights'
-    if (tid < kS) {
-        float4 f = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float tg = 0.0f;
-        if (tid < ns) {
-            if (d.xe) {
-                f = d.xe[s0 + tid];
-                if (train) tg = d.te[s0 + tid];
-            } else {
-                f = encode(d.c1, d.c2, d.m, d.r, s0 + tid);
-                if (train) tg = d.target[s0 + tid];
-            }
+    const float w4v = P[oW4 + j1];
+    float4 f = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float tg = 0.0f;
+    if (tid < ns) {
+        if (d.xe) {
+            f = d.xe[s0 + tid];
+            if (train) tg = d.te[s0 + tid];
+        } else {
+            f = encode(d.c1, d.c2, d.m, d.r, s0 + tid);
+            if (train) tg = d.target[s0 + tid];
         }
+    }
+    if (tid < kS) {
         TGT[tid] = tg;
         X[tid][0] = f.x;
         X[tid][1] = f.y;
         X[tid][2] = f.z;
         X[tid][3] = f.w;
     }
+    if (tid < kH) W4s[tid] = w4v;
     lds_barrier();
     // the weight operands of this wave's tiles, each issued one layer
     // before its use (loads complete in issue order, and a wave keeps at most
