@@ -243,3 +243,22 @@ def test_launch_size_limits_are_rejected_before_any_launch():
     p = wg.Plan(6, 3, pts, 16384, 16, 256, 28, 28, "same", "f32")
     assert L.wg_output_transform(p.handle, fake, p.workspace_bytes, fake, None) == -3
     assert "planes of M" in L.wg_last_error().decode()
+
+
+def test_surrogate_train_rejects_bad_permutations_before_any_gpu_work():
+    """surrogate.train checks the minibatch orders on the host: a tensor must
+    be contiguous int32 on the GPU, and an array must have shape (epochs, n);
+    both are rejected before anything is uploaded or launched."""
+    torch = pytest.importorskip("torch")
+    from paper_2201_10369_amd import surrogate as sg
+    n = 8
+    data = {"c1": np.ones(n), "c2": np.ones(n), "m": np.full(n, 4, np.int32), "r": np.full(n, 3, np.int32),
+            "target": np.zeros(n, np.float32)}
+    with pytest.raises(ValueError, match="int32 on the GPU"):
+        sg.train(data, None, torch.zeros((2, n), dtype=torch.int64))
+    with pytest.raises(ValueError, match="int32 on the GPU"):
+        sg.train(data, None, torch.zeros((2, n), dtype=torch.int32))          # on the host
+    with pytest.raises(ValueError, match="shape"):
+        sg.train(data, None, np.zeros((2, n + 1), np.int32))
+    with pytest.raises(ValueError, match="shape"):
+        sg.train(data, None, np.zeros(n, np.int32))
