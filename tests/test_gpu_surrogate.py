@@ -48,11 +48,13 @@ def test_gradient_matches_oracle():
             assert np.linalg.norm(a - b) <= 2e-4 * np.linalg.norm(b) + 1e-9
 
 
-@pytest.mark.parametrize("n", [1000, 4096])
+@pytest.mark.parametrize("n", [1, 17, 1000, 4096])
 def test_gradient_matches_oracle_at_training_batches(n):
     """The batch of the training runs (4096 samples: 256 forward blocks, the
-    weight gradients over 8 slices) and a ragged one (1000 = 62 blocks of 16
-    and one of 8), twice: the two results are bitwise equal."""
+    weight gradients over 8 slices), a ragged one (1000 = 62 blocks of 16
+    and one of 8) and the degenerate ones (one sample: one block, one slice;
+    17: a second block holding one sample), twice: the two results are
+    bitwise equal."""
     wg = _wg()
     params = _params(6)
     c1, c2, m, r, t = _data(n, 7)
